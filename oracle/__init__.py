@@ -1,0 +1,339 @@
+"""Plain FP64 CPU oracle of the splitting-based dual-energy CT ADMM.
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, by the smoke check and by the
+benchmark's CPU-baseline leg, never by the reconstruction library.  It shares
+no code with the GPU path; the two meet only in the seeded inputs.
+
+The operators R, R^T, the forward transform f and the per-ray decomposition are
+plain C (dect_oracle.c, double precision); everything else is numpy, written to
+be read against the paper:
+
+* Eq. (3)    forward transform f_s(a) = -ln sum_k w_s[k] exp(-f_KN[k] a_c - f_p[k] a_p)
+* Eq. (4)    MAP objective 1/2 ||f(R x) - m||^2_Sigma + lambda |x|_TV + g(x)
+* Eq. (9)    y = shrinkage(D x - u^y, lambda/rho)  (soft threshold)
+* Eq. (10)   z = max(0, x - u^z)
+* Eq. (11)   u <- u + [a; y; z] - [R; D; I] x
+* Eq. (12)   x = argmin ||[a; y; z] - [R; D; I] x + [u^a; u^y; u^z]||^2, by CG
+* Eq. (13)   a = argmin per ray 1/2 ||f(a) - m||^2_Sigma + sum_b rho_b/2 (a_b - R x_b + u^a_b)^2,
+             by Levenberg-Marquardt
+* Sec. 3.2   rho adapted from the primal and dual residuals (residual balancing)
+* Eq. (14)   xi(x) = 20 log10(||x - x*|| / ||x*||)
+* Table 1    operator counts per iteration: R 2n, R^T 2(n+1), f 4m
+
+Readings where the paper is silent (each listed with its reason in the design
+notes): Sigma = diag(counts / I0); anisotropic TV with forward differences and a
+zero last difference; LM damping mu0 = 1e-3 reset every outer iteration, x10 / /10,
+Marquardt scaling; residual balancing with mu = 10 and tau = 2; initial state
+x = 0 and a from a rho = 0 decomposition started at the linearised solution.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import build as _build
+
+_LIB = None
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        path = _build.LIB
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SRC):
+            _build.build()
+        _LIB = ctypes.CDLL(path)
+        P = ctypes.POINTER
+        d, i, l = ctypes.c_double, ctypes.c_int, ctypes.c_long
+        pd = P(d)
+        _LIB.orc_project.argtypes = [P(_Geom), pd, pd]
+        _LIB.orc_backproject.argtypes = [P(_Geom), pd, pd]
+        _LIB.orc_forward.argtypes = [i, pd, pd, pd, i, pd, pd, pd, l, pd, pd, pd, pd, pd, pd]
+        _LIB.orc_udm.argtypes = [i, pd, pd, pd, i, pd, pd, pd, l, pd, pd, pd, pd, pd, pd, d, d, i,
+                                 d, pd, pd, pd]
+        _LIB.orc_udm.restype = i
+    return _LIB
+
+
+class _Geom(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int),
+                ("pixel", ctypes.c_double), ("n_views", ctypes.c_int), ("n_det", ctypes.c_int),
+                ("det_cm", ctypes.c_double), ("det_offset", ctypes.c_double),
+                ("src_iso", ctypes.c_double), ("src_det", ctypes.c_double),
+                ("angle0", ctypes.c_double), ("span", ctypes.c_double)]
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if a is not None else None
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# -----------------------------------------------------------------------------
+# Finite differences (Eq. (5)): forward differences, last difference zero.
+# -----------------------------------------------------------------------------
+
+def D(x: np.ndarray) -> np.ndarray:
+    """[2, ny, nx]: horizontal then vertical forward differences of x [ny, nx]."""
+    out = np.zeros((2,) + x.shape)
+    out[0, :, :-1] = x[:, 1:] - x[:, :-1]
+    out[1, :-1, :] = x[1:, :] - x[:-1, :]
+    return out
+
+
+def DT(y: np.ndarray) -> np.ndarray:
+    """Transpose of D."""
+    h, v = y[0], y[1]
+    out = np.zeros(h.shape)
+    out[:, :-1] -= h[:, :-1]
+    out[:, 1:] += h[:, :-1]
+    out[:-1, :] -= v[:-1, :]
+    out[1:, :] += v[:-1, :]
+    return out
+
+
+def shrink(v: np.ndarray, t: float) -> np.ndarray:
+    """Soft threshold: the minimiser of t|y| + 1/2 (y - v)^2 (Eq. (9))."""
+    return np.sign(v) * np.maximum(np.abs(v) - t, 0.0)
+
+
+def xi_db(x: np.ndarray, x_true: np.ndarray) -> float:
+    """Eq. (14): normalised l2 distance to the ground truth, in dB."""
+    return 20.0 * np.log10(np.linalg.norm(x - x_true) / np.linalg.norm(x_true))
+
+
+def ingest(counts: np.ndarray, i0: float):
+    """Log measurement m = ln(I0 / max(c, 1)) and weight w = c / I0 (Sigma = diag(counts))."""
+    c = np.asarray(counts, dtype=np.float64)
+    return np.log(i0 / np.maximum(c, 1.0)), c / i0
+
+
+# -----------------------------------------------------------------------------
+# State and parameters
+# -----------------------------------------------------------------------------
+
+
+@dataclass
+class Params:
+    lam: tuple = (1e-5, 1e-5)        # lambda_c, lambda_p (Sec. 4)
+    rho0: tuple = (1e-3, 1e-3)       # initial rho_c, rho_p (Sec. 4)
+    lm_iters: int = 1                # m
+    cg_iters: int = 1                # n
+    rho_mode: str = "adaptive"       # "adaptive" | "fixed"
+    bal_mu: float = 10.0
+    bal_tau: float = 2.0
+    lm_mu0: float = 1e-3
+
+
+@dataclass
+class State:
+    """Full ADMM state, per basis b in (c, p): index 0 = Compton, 1 = photoelectric."""
+    x: np.ndarray      # [2, ny, nx]
+    Rx: np.ndarray     # [2, V, D], tracked R x
+    a: np.ndarray      # [2, V, D]
+    ua: np.ndarray     # [2, V, D]
+    y: np.ndarray      # [2, 2, ny, nx]
+    uy: np.ndarray     # [2, 2, ny, nx]
+    z: np.ndarray      # [2, ny, nx]
+    uz: np.ndarray     # [2, ny, nx]
+    rho: np.ndarray    # [2]
+    it: int = 0
+    log: list = field(default_factory=list)
+
+    def copy(self):
+        return State(*(np.array(getattr(self, k)) for k in
+                       ("x", "Rx", "a", "ua", "y", "uy", "z", "uz", "rho")),
+                     it=self.it, log=list(self.log))
+
+
+class Oracle:
+    """FP64 reference for one geometry and one pair of spectra."""
+
+    def __init__(self, geom: dict, spec):
+        self.geom = dict(geom)
+        g = _Geom()
+        g.kind = 0 if geom["kind"] == "parallel" else 1
+        for k in ("nx", "ny", "n_views", "n_det"):
+            setattr(g, k, int(geom[k]))
+        g.pixel = geom["pixel_cm"]
+        g.det_cm = geom["det_cm"]
+        g.det_offset = geom["det_offset"]
+        g.src_iso = geom["src_iso_cm"]
+        g.src_det = geom["src_det_cm"]
+        g.angle0 = geom["angle0"]
+        g.span = geom["span"]
+        self._g = g
+        self.img_shape = (int(geom["ny"]), int(geom["nx"]))
+        self.sino_shape = (int(geom["n_views"]), int(geom["n_det"]))
+        # Normalised spectra restricted to their nonzero bins (the constant C_s of
+        # Eq. (3) makes f independent of the scale of S).
+        self._spec = []
+        self.mean_f = []
+        for s in (spec.s_high, spec.s_low):
+            s = np.asarray(s, dtype=np.float64)
+            nz = np.nonzero(s > 0)[0]
+            w = s[nz] / s.sum()
+            fkn = _f64(np.asarray(spec.f_kn)[nz])
+            fp = _f64(np.asarray(spec.f_p)[nz])
+            self._spec.append((len(nz), _f64(np.log(w)), fkn, fp))
+            self.mean_f.append((float(np.sum(w * fkn)), float(np.sum(w * fp))))
+        self.counts = {"R": 0, "RT": 0, "RT_dual": 0, "f": 0}
+
+    # -- tomographic operators ------------------------------------------------
+    def project(self, img: np.ndarray, count: str | None = "R") -> np.ndarray:
+        img = _f64(img)
+        assert img.shape == self.img_shape
+        out = np.empty(self.sino_shape)
+        _lib().orc_project(ctypes.byref(self._g), _ptr(img), _ptr(out))
+        if count:
+            self.counts[count] += 1
+        return out
+
+    def backproject(self, sino: np.ndarray, count: str = "RT") -> np.ndarray:
+        sino = _f64(sino)
+        assert sino.shape == self.sino_shape
+        out = np.empty(self.img_shape)
+        _lib().orc_backproject(ctypes.byref(self._g), _ptr(sino), _ptr(out))
+        self.counts[count] += 1
+        return out
+
+    # -- forward transform and decomposition -----------------------------------
+    def _spec_args(self):
+        (nh, lh, kh, ph), (nl, ll, kl, pl) = self._spec
+        return [nh, _ptr(lh), _ptr(kh), _ptr(ph), nl, _ptr(ll), _ptr(kl), _ptr(pl)]
+
+    def forward(self, a_c, a_p):
+        """f_h, f_l and their gradients [.., 2] at line integrals (a_c, a_p) (Eq. (3))."""
+        ac, ap = _f64(a_c), _f64(a_p)
+        n = ac.size
+        fh, fl = np.empty(n), np.empty(n)
+        gh, gl = np.empty(2 * n), np.empty(2 * n)
+        _lib().orc_forward(*self._spec_args(), n, _ptr(ac), _ptr(ap), _ptr(fh), _ptr(fl),
+                           _ptr(gh), _ptr(gl))
+        sh = ac.shape
+        return fh.reshape(sh), fl.reshape(sh), gh.reshape(sh + (2,)), gl.reshape(sh + (2,))
+
+    def udm(self, mh, ml, wh, wl, vc, vp, rho_c, rho_p, iters, a_c, a_p, mu0=1e-3):
+        """Eq. (13) per ray by `iters` LM iterations from (a_c, a_p); returns (a_c, a_p, Phi)."""
+        sh = np.shape(a_c)
+        ac, ap = _f64(a_c).ravel().copy(), _f64(a_p).ravel().copy()
+        n = ac.size
+        args = [_f64(v).ravel() if v is not None else None for v in (mh, ml, wh, wl, vc, vp)]
+        phi = np.empty(n)
+        nf = _lib().orc_udm(*self._spec_args(), n, *(_ptr(v) for v in args), float(rho_c),
+                            float(rho_p), int(iters), float(mu0), _ptr(ac), _ptr(ap), _ptr(phi))
+        self.counts["f"] += nf
+        return ac.reshape(sh), ap.reshape(sh), phi.reshape(sh)
+
+    def linearised(self, mh, ml):
+        """a solving the 2x2 linearisation of f at a = 0 (rows = spectrum-mean f_KN, f_p)."""
+        (hc, hp), (lc, lp) = self.mean_f
+        det = hc * lp - hp * lc
+        return (lp * mh - hp * ml) / det, (hc * ml - lc * mh) / det
+
+    # -- objectives ------------------------------------------------------------
+    def data_cost(self, a_c, a_p, mh, ml, wh, wl) -> float:
+        fh, fl, _, _ = self.forward(a_c, a_p)
+        return 0.5 * float(np.sum(wh * (fh - mh) ** 2) + np.sum(wl * (fl - ml) ** 2))
+
+    def map_objective(self, x, mh, ml, wh, wl, lam) -> float:
+        """Eq. (4) at the nonnegative part of x (where g = 0)."""
+        xp = np.maximum(x, 0.0)
+        a = [self.project(xp[b], count=None) for b in range(2)]
+        tv = sum(lam[b] * np.abs(D(xp[b])).sum() for b in range(2))
+        return self.data_cost(a[0], a[1], mh, ml, wh, wl) + tv
+
+    def split_objective(self, st: State, mh, ml, wh, wl, lam) -> float:
+        return (self.data_cost(st.a[0], st.a[1], mh, ml, wh, wl)
+                + sum(lam[b] * np.abs(st.y[b]).sum() for b in range(2)))
+
+    # -- ADMM ------------------------------------------------------------------
+    def admm_init(self, mh, ml, wh, wl, params: Params, init_iters: int = 10) -> State:
+        """x = 0 and a from a rho = 0 decomposition started at the linearised solution."""
+        ny, nx = self.img_shape
+        V, Dn = self.sino_shape
+        ac, ap = self.linearised(mh, ml)
+        ac, ap, _ = self.udm(mh, ml, wh, wl, None, None, 0.0, 0.0, init_iters, ac, ap,
+                             params.lm_mu0)
+        z2 = lambda *s: np.zeros((2,) + s)
+        return State(x=z2(ny, nx), Rx=z2(V, Dn), a=np.stack([ac, ap]), ua=z2(V, Dn),
+                     y=z2(2, ny, nx), uy=z2(2, ny, nx), z=z2(ny, nx), uz=z2(ny, nx),
+                     rho=np.array(params.rho0, dtype=np.float64))
+
+    def cg(self, x, Rx, rhs_sino, rhs_img, n):
+        """n CG iterations on (R^T R + D^T D + I) x = R^T rhs_sino + rhs_img (Eq. (12)),
+        warm-started at x with R x = Rx known; returns (x, Rx) with Rx kept equal to R x."""
+        r = self.backproject(rhs_sino - Rx) + rhs_img - DT(D(x)) - x
+        p = r.copy()
+        gamma = float(np.dot(r.ravel(), r.ravel()))
+        for _ in range(n):
+            if gamma == 0.0:
+                break
+            Rp = self.project(p)
+            q = self.backproject(Rp) + DT(D(p)) + p
+            alpha = gamma / float(np.dot(p.ravel(), q.ravel()))
+            x = x + alpha * p
+            Rx = Rx + alpha * Rp
+            r = r - alpha * q
+            gamma_new = float(np.dot(r.ravel(), r.ravel()))
+            p = r + (gamma_new / gamma) * p
+            gamma = gamma_new
+        return x, Rx
+
+    def admm_iterate(self, st: State, mh, ml, wh, wl, params: Params, n_iters: int = 1) -> State:
+        """n_iters ADMM iterations: x (Eq. 12), a (Eq. 13), y and z (Eq. 9-10), u (Eq. 11), rho."""
+        st = st.copy()
+        for _ in range(n_iters):
+            rho = st.rho.copy()
+            a_prev, y_prev, z_prev = st.a.copy(), st.y.copy(), st.z.copy()
+            # x-update, independently per basis (Eq. (12)); rho cancels.
+            for b in range(2):
+                st.x[b], st.Rx[b] = self.cg(
+                    st.x[b], st.Rx[b], st.a[b] + st.ua[b],
+                    DT(st.y[b] + st.uy[b]) + st.z[b] + st.uz[b], params.cg_iters)
+            # a-update: per-ray decomposition (Eq. (13)) with v = R x - u^a.
+            v = st.Rx - st.ua
+            ac, ap, _ = self.udm(mh, ml, wh, wl, v[0], v[1], rho[0], rho[1], params.lm_iters,
+                                 st.a[0], st.a[1], params.lm_mu0)
+            st.a = np.stack([ac, ap])
+            # y and z updates (Eq. (9)-(10)) and the scaled duals (Eq. (11)).
+            for b in range(2):
+                Dx = D(st.x[b])
+                st.y[b] = shrink(Dx - st.uy[b], params.lam[b] / rho[b])
+                st.z[b] = np.maximum(0.0, st.x[b] - st.uz[b])
+                st.ua[b] += st.a[b] - st.Rx[b]
+                st.uy[b] += st.y[b] - Dx
+                st.uz[b] += st.z[b] - st.x[b]
+            # Residuals and the rho update (residual balancing).
+            r_norm = np.zeros(2)
+            s_norm = np.zeros(2)
+            for b in range(2):
+                r_norm[b] = np.sqrt(np.sum((st.a[b] - st.Rx[b]) ** 2)
+                                    + np.sum((st.y[b] - D(st.x[b])) ** 2)
+                                    + np.sum((st.z[b] - st.x[b]) ** 2))
+                if params.rho_mode == "adaptive":
+                    sv = (self.backproject(st.a[b] - a_prev[b], count="RT_dual")
+                          + DT(st.y[b] - y_prev[b]) + (st.z[b] - z_prev[b]))
+                    s_norm[b] = rho[b] * np.linalg.norm(sv)
+            new_rho = rho.copy()
+            if params.rho_mode == "adaptive":
+                for b in range(2):
+                    if r_norm[b] > params.bal_mu * s_norm[b]:
+                        new_rho[b] = rho[b] * params.bal_tau
+                    elif s_norm[b] > params.bal_mu * r_norm[b]:
+                        new_rho[b] = rho[b] / params.bal_tau
+            for b in range(2):
+                k = rho[b] / new_rho[b]
+                st.ua[b] *= k
+                st.uy[b] *= k
+                st.uz[b] *= k
+            st.rho = new_rho
+            st.log.append(dict(it=st.it, rho=rho.copy(), r=r_norm.copy(), s=s_norm.copy(),
+                               phi=self.split_objective(st, mh, ml, wh, wl, params.lam)))
+            st.it += 1
+        return st
