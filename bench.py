@@ -1,0 +1,151 @@
+"""Benchmark: ADMM outer iterations per second on a 512x512 fan-beam luggage slice.
+
+One step is one outer iteration of the splitting scheme (CG x-update with R and
+R^T, per-ray LM decomposition, shrinkage/nonnegativity/dual updates, rho
+adaptation) on a synthetic 512x512 FP32 slice, 720 views x 1024 bins, with the
+measurements already resident in device memory.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps 50] [--warmup 5] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X: 256 compute units x 64 VALU lanes x 2.4 GHz = one lane-operation per lane
+# per clock (an FMA counts as one operation; packed FP32 is not used).
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=2)
+    return ap.parse_args()
+
+
+def cpu_baseline(pr, iters: int):
+    """The FP64 oracle on the host cores: `iters` ADMM iterations of the same slice."""
+    import oracle as O
+    orc = O.Oracle(pr.geom, pr.spec)
+    mh, wh = O.ingest(pr.counts_high, pr.i0)
+    ml, wl = O.ingest(pr.counts_low, pr.i0)
+    prm = O.Params()
+    st = orc.admm_init(mh, ml, wh, wl, prm)
+    t0 = time.perf_counter()
+    orc.admm_iterate(st, mh, ml, wh, wl, prm, iters)
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": iters / dt, "unit": "iter/s", "cores": cores, "kind": "oracle",
+            "sample": f"{iters} ADMM iterations (UDM1-CG1, adaptive rho, FP64) of the same "
+                      f"512x512 slice after its initialisation; {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(slices are independent and would shard across GPUs without communication)",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1905_00934_amd import dect, synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    pr = synth.slice_problem(0, with_image=True)
+    plan = dect.Plan(pr.geom, pr.spec, torch.float32, device=dev)
+    counts = [torch.from_numpy(c).to(dev, torch.float32) for c in (pr.counts_high, pr.counts_low)]
+    meas = list(plan.ingest(counts[0], counts[1], pr.i0))
+    params = dect.AdmmParams()
+    st = plan.new_state()
+    plan.admm_init(meas, st, params)
+    plan.admm_iterate(meas, st, params, args.warmup)
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    plan.admm_iterate(meas, st, params, args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    ms_per_step = ms / args.steps
+
+    # Per-kernel times, live, with HIP events on the stream the kernels run on.
+    dect.profile_start()
+    plan.admm_iterate(meas, st, params, args.steps)
+    kt = dect.profile_stop()
+    log = plan.admm_iterate(meas, st, params, 1, log=True)
+    x = st.x.double().cpu().numpy()
+    xi = [20 * math.log10(np.linalg.norm(x[..., b] - pr.x_true[b]) / np.linalg.norm(pr.x_true[b]))
+          for b in range(2)]
+
+    info = plan.info()
+    # Algorithmic VALU operations of one two-channel R or R^T application: per Joseph
+    # sample the position (fma), floor and fraction; per channel the difference, the
+    # interpolating fma and the accumulation.
+    ops_apply = 3 * info["samples"] + 3 * 2 * info["samples"]
+    per_kernel = {k: {"avg_us": 1e3 * v[0] / v[1], "launches": v[1],
+                      "share": v[0] / sum(t for t, _ in kt.values())} for k, v in kt.items()}
+    dominant = max(kt, key=lambda k: kt[k][0])
+    bp = [k for k in kt if k.startswith("backproject")]
+    roof_name = dominant
+    avg_s = kt[roof_name][0] / kt[roof_name][1] / 1e3
+    achieved = ops_apply / avg_s / 1e12
+    alg_bytes = 4 * (2 * info["n_pixels"] + 2 * info["n_rays"])
+    roofline = {"kernel": roof_name, "bound": "alu", "achieved": round(achieved, 3),
+                "peak": round(VALU_PEAK_TOPS, 2), "unit": "TOP/s",
+                "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
+                "ops_per_launch": ops_apply, "avg_launch_us": round(avg_s * 1e6, 2),
+                "hbm_alg_bytes_per_launch": alg_bytes,
+                "hbm_alg_frac": round(alg_bytes / avg_s / 1e9 / HBM_PEAK_GBS, 5)}
+
+    out = {
+        "metric": "ADMM iters/s on 512² fan-beam slice",
+        "value": round(1e3 / ms_per_step, 3),
+        "unit": "iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "single fan-beam slice, 512x512 at 0.1 cm, 720 views x 1024 "
+                               "bins, luggage phantom (30 objects, 2 steel), I0 2e5, "
+                               "UDM1-CG1, adaptive rho, lambda 1e-5, rho0 1e-3",
+                   "slices": 1, "image": 512, "views": 720, "bins": 1024,
+                   "lm_iters": 1, "cg_iters": 1},
+        "roofline": roofline,
+        "kernels": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
+                        for kk, vv in v.items()} for k, v in per_kernel.items()},
+        "accuracy": {"xi_c_db": round(xi[0], 3), "xi_p_db": round(xi[1], 3),
+                     "iterations": args.warmup + 2 * args.steps + 1,
+                     "rho": log[-1]["rho"]},
+        "wall_s": round(wall, 4),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(pr, args.cpu_iters)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

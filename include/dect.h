@@ -1,0 +1,226 @@
+/*
+ * dect.h -- C ABI of the MI355X dual-energy CT ADMM library (gfx950, HIP).
+ *
+ * The library implements one outer iteration of the splitting-based ADMM for
+ * statistical dual-energy CT of Li, Manerikar, Prakash and Kak (Sec. 3.3):
+ * the x-update by conjugate gradients on Eq. (12) with a Joseph projector R and
+ * its exact transpose R^T, the per-ray decomposition of Eq. (13) by
+ * Levenberg-Marquardt, the shrinkage and nonnegativity steps of Eq. (9)-(10),
+ * the scaled-dual update of Eq. (11) and residual-balancing adaptation of rho.
+ *
+ * Conventions
+ *  - Every array argument is a plain pointer.  "device" pointers address GPU
+ *    memory (hipMalloc'd or a torch CUDA tensor's data_ptr()); "host" pointers
+ *    address CPU memory.  Sizes are element counts.
+ *  - Floating-point arrays have the plan's dtype (float for DECT_F32, double
+ *    for DECT_F64).  Counts, measurements and weights too.
+ *  - Images are row-major [ny][nx]; sinograms are view-major [n_views][n_det].
+ *    Multi-channel arrays keep the channels innermost: an image with ch
+ *    channels is [ny][nx][ch], a sinogram [n_views][n_det][ch].  The two ADMM
+ *    bases (Compton c, photoelectric p) are such channel pairs (c, p).
+ *  - Pixel (j, i) has its centre at ((i-(nx-1)/2) pixel_cm, (j-(ny-1)/2) pixel_cm);
+ *    view v is at angle angle0 + v*span/n_views; bin b sits at detector
+ *    coordinate u_b = (b - (n_det-1)/2 + det_offset) * det_cm.  Parallel beam:
+ *    the ray of (v, b) is the line p.(cos t, sin t) = u_b.  Fan beam with a flat
+ *    detector: source at src_iso_cm (cos t, sin t), bin at
+ *    -(src_det_cm - src_iso_cm)(cos t, sin t) + u_b (-sin t, cos t).
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Calls marked
+ *    "async" only enqueue work on it; the caller keeps every buffer alive and
+ *    unmodified until that work completes.
+ *  - Errors: every function returns a dect_status; on failure a message is
+ *    available from dect_last_error() (thread-local).  Nothing is thrown.
+ *    Argument and shape checks are done at plan creation and on every call's
+ *    pointer and channel arguments; faults inside kernels are reported by the
+ *    HIP runtime at the next synchronising call.
+ */
+#ifndef DECT_H
+#define DECT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DECT_OK = 0,
+    DECT_NOT_READY = 1,
+    DECT_E_ARG = -1,       /* null pointer, bad enum, bad channel count, bad parameter */
+    DECT_E_SHAPE = -2,     /* geometry the library cannot represent */
+    DECT_E_NOMEM = -3,     /* device or host allocation failed */
+    DECT_E_DEVICE = -4,    /* a HIP runtime call failed */
+    DECT_E_NONFINITE = -5, /* a non-finite residual or objective was produced */
+    DECT_E_CAPACITY = -6   /* a request does not fit the server's memory budget */
+} dect_status;
+
+typedef enum { DECT_F32 = 0, DECT_F64 = 1 } dect_dtype;
+typedef enum { DECT_PARALLEL = 0, DECT_FAN = 1 } dect_beam;
+
+/* Scanner geometry (the projection matrix R of Eq. (2)). */
+typedef struct {
+    int kind;            /* dect_beam */
+    int nx, ny;          /* image columns, rows */
+    double pixel_cm;     /* square pixel side */
+    int n_views, n_det;  /* views, detector bins */
+    double det_cm;       /* bin spacing on the (flat) detector */
+    double det_offset;   /* detector shift, in bins */
+    double src_iso_cm;   /* fan: source to rotation centre */
+    double src_det_cm;   /* fan: source to detector */
+    double angle0;       /* first view angle, radians */
+    double span;         /* angular range covered by the views, radians */
+} dect_geometry;
+
+/* Spectral model of Eq. (1)-(3): photon spectra S_h, S_l on an energy grid and the
+ * Compton (f_KN) and photoelectric (f_p) energy multipliers.  Host arrays of
+ * n_bins doubles, copied at plan creation.  S >= 0 with a positive sum; f_kn > 0;
+ * f_p >= 0.  Bins where a spectrum is zero are dropped for that spectrum. */
+typedef struct {
+    int n_bins;
+    const double* energy_kev;
+    const double* s_high;
+    const double* s_low;
+    const double* f_kn;
+    const double* f_p;
+} dect_spectra;
+
+typedef struct dect_plan dect_plan;
+
+/* Create a plan: validated geometry, per-ray Joseph tables and per-view
+ * footprint tables (device), and the spectral tables.  The plan belongs to the
+ * library; it is bound to the device current at creation.  DECT_E_SHAPE if a
+ * fan source lies inside the circle circumscribing the image, or if a view's
+ * rays do not split into one run of x-stepped and one run of y-stepped bins. */
+dect_status dect_plan_create(const dect_geometry* geom, const dect_spectra* spec,
+                             dect_dtype dtype, dect_plan** out);
+void dect_plan_destroy(dect_plan* plan);
+const char* dect_last_error(void);
+
+/* R: sino[v][b][c] = sum over the Joseph samples of ray (v,b) of the linearly
+ * interpolated img[.][.][c] times the step length (Eq. (2), Sec. 3.1).
+ * img: device [ny][nx][ch]; sino: device [n_views][n_det][ch] (overwritten);
+ * ch in {1, 2, 4}.  async.  Uses a plan-owned scratch image, so calls with one
+ * plan must not run concurrently on different streams. */
+dect_status dect_project(const dect_plan* plan, const void* img, void* sino, int ch,
+                         void* stream);
+
+/* R^T, the exact transpose of dect_project (same weights, gathered per pixel,
+ * no atomics): img[j][i][c] = sum over rays of weight * sino[v][b][c].
+ * sino: device [n_views][n_det][ch]; img: device [ny][nx][ch] (overwritten);
+ * ch in {1, 2, 4}.  async. */
+dect_status dect_backproject(const dect_plan* plan, const void* sino, void* img, int ch,
+                             void* stream);
+
+/* Per-ray unconstrained decomposition, Eq. (13): for every ray i minimise
+ *   1/2 sum_s w_s (f_s(a) - m_s)^2 + 1/2 sum_b rho_b (a_b - v_b)^2
+ * over a = (a_c, a_p), f_s the polychromatic transform of Eq. (3), by lm_iters
+ * Levenberg-Marquardt iterations started at the given a (damping 1e-3, x10 on
+ * rejection, /10 on acceptance, Marquardt scaling).
+ * m_h, m_l, w_h, w_l: device [n_views*n_det]; v: device [..][2] or NULL (then the
+ * rho terms are dropped); a: device [..][2], in/out; cost: device [..] or NULL
+ * (final value of the minimised function).  async. */
+dect_status dect_decompose_rays(const dect_plan* plan, const void* m_h, const void* m_l,
+                                const void* w_h, const void* w_l, const void* v,
+                                double rho_c, double rho_p, int lm_iters, void* a, void* cost,
+                                void* stream);
+
+/* Ingest photon counts: m = ln(I0 / max(c, 1)) and w = c / I0 (Sigma of Eq. (4) as
+ * counts normalised by the unattenuated count).  All device [n_views*n_det]. async. */
+dect_status dect_ingest_counts(const dect_plan* plan, const void* counts_h,
+                               const void* counts_l, double i0_h, double i0_l, void* m_h,
+                               void* m_l, void* w_h, void* w_l, void* stream);
+
+/* ---------------------------------------------------------------- ADMM --- */
+
+typedef enum {
+    DECT_RHO_FIXED = 0,    /* rho stays at rho0 */
+    DECT_RHO_ADAPTIVE = 1, /* residual balancing: r > mu s -> rho*tau; s > mu r -> rho/tau */
+    DECT_RHO_SCHEDULE = 2  /* rho of iteration k taken from rho_schedule[2k], [2k+1] */
+} dect_rho_mode;
+
+typedef struct {
+    double lambda_c, lambda_p; /* TV weights of Eq. (9) */
+    double rho_c, rho_p;       /* initial penalties (used by dect_admm_init) */
+    int lm_iters;              /* m: LM iterations per outer iteration, >= 1 */
+    int cg_iters;              /* n: CG iterations per outer iteration, >= 1 */
+    int rho_mode;              /* dect_rho_mode */
+    double bal_mu, bal_tau;    /* residual balancing constants (10, 2) */
+    double lm_mu0;             /* LM initial damping (1e-3) */
+    const double* rho_schedule;/* host, 2*rho_schedule_len doubles, for DECT_RHO_SCHEDULE */
+    int rho_schedule_len;
+} dect_params;
+
+/* Per-iteration record, filled when the caller passes a log buffer. */
+typedef struct {
+    int32_t iter;       /* outer iteration index */
+    int32_t flags;      /* bit 0: a non-finite value was met */
+    double rho[2];      /* rho in force during the iteration (c, p) */
+    double r_primal[2]; /* ||(a - Rx, y - Dx, z - x)|| per basis */
+    double s_dual[2];   /* rho ||R^T da + D^T dy + dz|| per basis (0 in fixed mode) */
+    double data_cost;   /* 1/2 sum w (f(a) - m)^2 after the a-update */
+    double tv_cost;     /* lambda_c |y_c|_1 + lambda_p |y_p|_1 */
+} dect_iter_log;
+
+/* The state of one slice lives in ONE caller-owned device buffer of
+ * dect_state_bytes() bytes (256-byte aligned).  Its layout is described by
+ * dect_state_layout: byte offsets of the named arrays; image arrays are
+ * [ny][nx][2] basis pairs, y and u^y [ny][nx][4] = (c_h, p_h, c_v, p_v),
+ * sinogram arrays [n_views][n_det][2].  The buffer holds everything an iteration
+ * reads or writes, so copying it checkpoints the reconstruction. */
+typedef struct {
+    size_t bytes;
+    size_t x, y, uy, z, uz;   /* images */
+    size_t a, ua, Rx;         /* sinograms */
+    size_t scalars;           /* device doubles: rho_c, rho_p, iteration, ... */
+} dect_layout;
+
+/* Sizes of the operator, for cost accounting: Joseph samples (steps with at least
+ * one tap inside the image) and nonzero taps (nonzeros of R) over all rays. */
+typedef struct {
+    int64_t n_pixels, n_rays;
+    int64_t samples, taps;
+} dect_plan_info;
+
+/* Counted on the host on first call (a pass over every ray's samples). */
+dect_status dect_plan_get_info(const dect_plan* plan, dect_plan_info* out);
+
+size_t dect_state_bytes(const dect_plan* plan);
+dect_status dect_state_layout(const dect_plan* plan, dect_layout* out);
+
+/* Initial state: x = 0, R x = 0, y = z = u = 0, rho = (rho_c, rho_p), and a from a
+ * rho = 0 decomposition (10 LM iterations) started at the linearised solution.
+ * m_*, w_*: device [n_views*n_det]; state: device buffer.  async. */
+dect_status dect_admm_init(const dect_plan* plan, const void* m_h, const void* m_l,
+                           const void* w_h, const void* w_l, void* state,
+                           const dect_params* params, void* stream);
+
+/* n_iters outer iterations (x by CG(n) on Eq. (12), a by LM(m) on Eq. (13), y and
+ * z by Eq. (9)-(10), u by Eq. (11), then rho).  log: host array of n_iters
+ * records or NULL; with a log the call synchronises the stream and returns
+ * DECT_E_NONFINITE if any record has the non-finite flag.  Without a log the
+ * call is async.  A DECT_RHO_SCHEDULE run must cover every iteration index it
+ * reaches (DECT_E_ARG otherwise). */
+dect_status dect_admm_iterate(const dect_plan* plan, const void* m_h, const void* m_l,
+                              const void* w_h, const void* w_l, void* state,
+                              const dect_params* params, int n_iters, dect_iter_log* log,
+                              void* stream);
+
+/* --------------------------------------------------------------- timing --- */
+
+/* Per-kernel timing for benchmarks: between dect_profile_start and
+ * dect_profile_stop every kernel the library launches is bracketed by HIP
+ * events recorded on the stream it runs on.  stop waits for those events and
+ * writes one record per kernel name (at most max; *n_out = number of names). */
+typedef struct {
+    char name[32];
+    double total_ms;
+    int32_t launches;
+} dect_kernel_time;
+
+dect_status dect_profile_start(void);
+dect_status dect_profile_stop(dect_kernel_time* out, int max, int* n_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DECT_H */

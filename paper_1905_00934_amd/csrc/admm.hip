@@ -1,0 +1,668 @@
+// One ADMM outer iteration of the splitting scheme (Sec. 3.3) on one slice:
+// image-side kernels, deterministic reductions, the host driver, and the C ABI.
+//
+// Per outer iteration (n CG steps, m LM steps), all on the caller's stream and
+// with every scalar (CG step sizes, rho, dual rescale) kept in device memory:
+//   R^T t + image terms -> r0 = p0, |r0|^2          (Eq. (12) right-hand side)
+//   n x { R p ; R^T R p + D^T D p + p ; alpha ; x += alpha p, R x += alpha R p ; beta }
+//   per-ray LM on Eq. (13), u^a and next t           (fused, one lane per ray)
+//   y, z, u^y, u^z (Eq. (9)-(11)), residual partials (fused, one lane per pixel)
+//   [adaptive rho] R^T da + D^T dy + dz              (dual residual)
+//   residual balancing, rho, dual rescale            (one block)
+#include <cmath>
+#include <cstring>
+
+#include "common.h"
+#include "kernels.h"
+#include "profile.h"
+
+namespace dect {
+
+namespace {
+
+enum RedMode : int { RED_GAMMA = 0, RED_ALPHA = 1, RED_BETA = 2, RED_FINAL = 3 };
+
+__global__ __launch_bounds__(256) void k_zero(uint32_t* p, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+__global__ void k_set_scalars(double* s, double rc, double rp, double lc, double lp) {
+    if (threadIdx.x != 0) return;
+    for (int k = 0; k < S_COUNT; ++k) s[k] = 0.0;
+    s[S_RHO] = rc;
+    s[S_RHO + 1] = rp;
+    s[S_KAPPA] = 1.0;
+    s[S_KAPPA + 1] = 1.0;
+    s[S_LAM] = lc;
+    s[S_LAM + 1] = lp;
+}
+
+// x += alpha p; with FULL also r -= alpha q and block partials of r.r.
+template <typename T, bool FULL>
+__global__ __launch_bounds__(256) void k_cg_step(long N, T* __restrict__ x, const T* __restrict__ p,
+                                                 T* __restrict__ r, const T* __restrict__ q,
+                                                 const double* __restrict__ scal,
+                                                 double* __restrict__ partials) {
+    using V2 = vec<T, 2>;
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const T al[2] = {(T)scal[S_ALPHA], (T)scal[S_ALPHA + 1]};
+    double part[2] = {0.0, 0.0};
+    if (i < N) {
+        V2 xv = reinterpret_cast<V2*>(x)[i];
+        const V2 pv = reinterpret_cast<const V2*>(p)[i];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) xv.v[c] += al[c] * pv.v[c];
+        reinterpret_cast<V2*>(x)[i] = xv;
+        if constexpr (FULL) {
+            V2 rv = reinterpret_cast<V2*>(r)[i];
+            const V2 qv = reinterpret_cast<const V2*>(q)[i];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                rv.v[c] -= al[c] * qv.v[c];
+                part[c] = (double)rv.v[c] * (double)rv.v[c];
+            }
+            reinterpret_cast<V2*>(r)[i] = rv;
+        }
+    }
+    if constexpr (FULL) block_sum_store<2>(part, partials + (size_t)blockIdx.x * kPartialSlots);
+}
+
+// R x += alpha R p (tracking, so no extra projection of x is needed).
+template <typename T>
+__global__ __launch_bounds__(256) void k_rx_step(long M, T* __restrict__ Rx,
+                                                 const T* __restrict__ Rp,
+                                                 const double* __restrict__ scal) {
+    using V2 = vec<T, 2>;
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    V2 a = reinterpret_cast<V2*>(Rx)[i];
+    const V2 b = reinterpret_cast<const V2*>(Rp)[i];
+    a.v[0] += (T)scal[S_ALPHA] * b.v[0];
+    a.v[1] += (T)scal[S_ALPHA + 1] * b.v[1];
+    reinterpret_cast<V2*>(Rx)[i] = a;
+}
+
+// p = r + beta p.
+template <typename T>
+__global__ __launch_bounds__(256) void k_p_step(long N, T* __restrict__ p, const T* __restrict__ r,
+                                                const double* __restrict__ scal) {
+    using V2 = vec<T, 2>;
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    V2 a = reinterpret_cast<V2*>(p)[i];
+    const V2 b = reinterpret_cast<const V2*>(r)[i];
+    a.v[0] = b.v[0] + (T)scal[S_BETA] * a.v[0];
+    a.v[1] = b.v[1] + (T)scal[S_BETA + 1] * a.v[1];
+    reinterpret_cast<V2*>(p)[i] = a;
+}
+
+template <typename T>
+__device__ inline T soft(T v, T t) {
+    const T m = fabs(v) - t;
+    return m > T(0) ? copysign(m, v) : T(0);
+}
+
+// y = shrink(D x - u^y, lambda/rho) (Eq. (9)), z = max(0, x - u^z) (Eq. (10)),
+// u^y += y - D x, u^z += z - x (Eq. (11)); dy, dz = changes of y, z.
+// Partials: |y - Dx|^2 + |z - x|^2 per basis, |y_c|_1, |y_p|_1.
+template <typename T>
+__global__ __launch_bounds__(256) void k_tv_dual(int nx, int ny, const T* __restrict__ x,
+                                                 T* __restrict__ y, T* __restrict__ uy,
+                                                 T* __restrict__ dy, T* __restrict__ z,
+                                                 T* __restrict__ uz, T* __restrict__ dz,
+                                                 const double* __restrict__ scal,
+                                                 double* __restrict__ partials) {
+    using V2 = vec<T, 2>;
+    using V4 = vec<T, 4>;
+    const long N = (long)nx * ny;
+    const long pix = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    double part[4] = {0.0, 0.0, 0.0, 0.0};
+    if (pix < N) {
+        const int j = (int)(pix / nx), i = (int)(pix % nx);
+        const V2* x2 = reinterpret_cast<const V2*>(x);
+        const V2 xc = x2[pix];
+        V4 Dx;
+        if (i < nx - 1) {
+            const V2 xr = x2[pix + 1];
+            Dx.v[0] = xr.v[0] - xc.v[0];
+            Dx.v[1] = xr.v[1] - xc.v[1];
+        } else {
+            Dx.v[0] = Dx.v[1] = T(0);
+        }
+        if (j < ny - 1) {
+            const V2 xd = x2[pix + nx];
+            Dx.v[2] = xd.v[0] - xc.v[0];
+            Dx.v[3] = xd.v[1] - xc.v[1];
+        } else {
+            Dx.v[2] = Dx.v[3] = T(0);
+        }
+        const T th[2] = {(T)(scal[S_LAM] / scal[S_RHO]), (T)(scal[S_LAM + 1] / scal[S_RHO + 1])};
+        V4 u = reinterpret_cast<V4*>(uy)[pix];
+        const V4 yo = reinterpret_cast<V4*>(y)[pix];
+        V4 yn, d;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            yn.v[k] = soft<T>(Dx.v[k] - u.v[k], th[k & 1]);
+            u.v[k] += yn.v[k] - Dx.v[k];
+            d.v[k] = yn.v[k] - yo.v[k];
+            const double e = (double)(yn.v[k] - Dx.v[k]);
+            part[k & 1] += e * e;
+            part[2 + (k & 1)] += fabs((double)yn.v[k]);
+        }
+        reinterpret_cast<V4*>(y)[pix] = yn;
+        reinterpret_cast<V4*>(uy)[pix] = u;
+        reinterpret_cast<V4*>(dy)[pix] = d;
+        V2 w = reinterpret_cast<V2*>(uz)[pix];
+        const V2 zo = reinterpret_cast<V2*>(z)[pix];
+        V2 zn, dzv;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            zn.v[c] = fmax(T(0), xc.v[c] - w.v[c]);
+            w.v[c] += zn.v[c] - xc.v[c];
+            dzv.v[c] = zn.v[c] - zo.v[c];
+            const double e = (double)(zn.v[c] - xc.v[c]);
+            part[c] += e * e;
+        }
+        reinterpret_cast<V2*>(z)[pix] = zn;
+        reinterpret_cast<V2*>(uz)[pix] = w;
+        reinterpret_cast<V2*>(dz)[pix] = dzv;
+    }
+    block_sum_store<4>(part, partials + (size_t)blockIdx.x * kPartialSlots);
+}
+
+// Scaled duals follow rho: u *= rho_old / rho_new, and t = a + u^a - R x again.
+template <typename T>
+__global__ __launch_bounds__(256) void k_rescale(long M, long N, T* __restrict__ ua,
+                                                 T* __restrict__ t, const T* __restrict__ a,
+                                                 const T* __restrict__ Rx, T* __restrict__ uy,
+                                                 T* __restrict__ uz,
+                                                 const double* __restrict__ scal) {
+    using V2 = vec<T, 2>;
+    using V4 = vec<T, 4>;
+    const double k0 = scal[S_KAPPA], k1 = scal[S_KAPPA + 1];
+    if (k0 == 1.0 && k1 == 1.0) return;
+    const T kc[2] = {(T)k0, (T)k1};
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < M) {
+        V2 u = reinterpret_cast<V2*>(ua)[i];
+        const V2 av = reinterpret_cast<const V2*>(a)[i];
+        const V2 rv = reinterpret_cast<const V2*>(Rx)[i];
+        V2 tv;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            u.v[c] *= kc[c];
+            tv.v[c] = av.v[c] + u.v[c] - rv.v[c];
+        }
+        reinterpret_cast<V2*>(ua)[i] = u;
+        reinterpret_cast<V2*>(t)[i] = tv;
+    }
+    if (i < N) {
+        V4 u4 = reinterpret_cast<V4*>(uy)[i];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) u4.v[k] *= kc[k & 1];
+        reinterpret_cast<V4*>(uy)[i] = u4;
+        V2 u2 = reinterpret_cast<V2*>(uz)[i];
+        u2.v[0] *= kc[0];
+        u2.v[1] *= kc[1];
+        reinterpret_cast<V2*>(uz)[i] = u2;
+    }
+}
+
+struct RedArgs {
+    const double* tiles;
+    int nb_tiles;
+    const double* img;
+    int nb_img;
+    const double* sino;
+    int nb_sino;
+    double* scal;
+    double* log;
+    int mode;
+    int rho_mode;
+    int dual;  // dual-residual partials present
+    double bal_mu, bal_tau, next_rho_c, next_rho_p;
+};
+
+// Fixed-order sum of K slots over nb block partials; the result reaches all threads.
+template <int K>
+__device__ inline void section_sum(const double* base, int nb, double (&out)[K]) {
+    __shared__ double res[K];
+    double v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x)
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] += base[(size_t)b * kPartialSlots + k];
+    block_sum_store<K>(v, res);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) out[k] = res[k];
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_reduce(RedArgs A) {
+    double* s = A.scal;
+    if (A.mode == RED_GAMMA) {
+        double g[2];
+        section_sum<2>(A.tiles, A.nb_tiles, g);
+        if (threadIdx.x == 0) {
+            s[S_GAMMA] = g[0];
+            s[S_GAMMA + 1] = g[1];
+        }
+    } else if (A.mode == RED_ALPHA) {
+        double pq[2];
+        section_sum<2>(A.tiles, A.nb_tiles, pq);
+        if (threadIdx.x == 0)
+            for (int c = 0; c < 2; ++c) {
+                s[S_PQ + c] = pq[c];
+                s[S_ALPHA + c] = (pq[c] > 0.0 && s[S_GAMMA + c] > 0.0) ? s[S_GAMMA + c] / pq[c] : 0.0;
+            }
+    } else if (A.mode == RED_BETA) {
+        double g[2];
+        section_sum<2>(A.img, A.nb_img, g);
+        if (threadIdx.x == 0)
+            for (int c = 0; c < 2; ++c) {
+                s[S_BETA + c] = s[S_GAMMA + c] > 0.0 ? g[c] / s[S_GAMMA + c] : 0.0;
+                s[S_GAMMA + c] = g[c];
+            }
+    } else {
+        double sn[4], im[4], du[2] = {0.0, 0.0};
+        section_sum<4>(A.sino, A.nb_sino, sn);
+        section_sum<4>(A.img, A.nb_img, im);
+        if (A.dual) section_sum<2>(A.tiles, A.nb_tiles, du);
+        if (threadIdx.x == 0) {
+            const double rho[2] = {s[S_RHO], s[S_RHO + 1]};
+            double r[2], sd[2], nr[2];
+            for (int c = 0; c < 2; ++c) {
+                r[c] = sqrt(sn[c] + im[c]);
+                sd[c] = rho[c] * sqrt(du[c]);
+                nr[c] = rho[c];
+                if (A.rho_mode == DECT_RHO_ADAPTIVE) {
+                    if (r[c] > A.bal_mu * sd[c]) nr[c] = rho[c] * A.bal_tau;
+                    else if (sd[c] > A.bal_mu * r[c]) nr[c] = rho[c] / A.bal_tau;
+                }
+            }
+            if (A.rho_mode == DECT_RHO_SCHEDULE) {
+                nr[0] = A.next_rho_c;
+                nr[1] = A.next_rho_p;
+            }
+            const double data = sn[2];
+            const double tv = s[S_LAM] * im[2] + s[S_LAM + 1] * im[3];
+            bool bad = sn[3] > 0.0;
+            for (int c = 0; c < 2; ++c) bad = bad || !isfinite(r[c]) || !isfinite(sd[c]);
+            bad = bad || !isfinite(data) || !isfinite(tv);
+            const long it = (long)s[S_ITER];
+            double* L = A.log + (size_t)(it % kLogCap) * kLogStride;
+            L[0] = (double)it;
+            L[1] = bad ? 1.0 : 0.0;
+            L[2] = rho[0];
+            L[3] = rho[1];
+            L[4] = r[0];
+            L[5] = r[1];
+            L[6] = sd[0];
+            L[7] = sd[1];
+            L[8] = data;
+            L[9] = tv;
+            for (int c = 0; c < 2; ++c) {
+                s[S_KAPPA + c] = rho[c] / nr[c];
+                s[S_RHO + c] = nr[c];
+            }
+            if (bad) s[S_FLAGS] = (double)((long)s[S_FLAGS] | 1L);
+            s[S_ITER] = (double)(it + 1);
+        }
+    }
+}
+
+template <typename T>
+T* at(void* base, size_t off) {
+    return reinterpret_cast<T*>(static_cast<char*>(base) + off);
+}
+
+unsigned nblk(long n) { return (unsigned)((n + 255) / 256); }
+
+template <typename T>
+dect_status iterate_T(const dect_plan* p, const void* mh, const void* ml, const void* wh,
+                      const void* wl, void* st, const dect_params* prm, int n_iters,
+                      dect_iter_log* log, hipStream_t s) {
+    const dect_layout& L = p->layout;
+    T* x = at<T>(st, L.x);
+    T* y = at<T>(st, L.y);
+    T* uy = at<T>(st, L.uy);
+    T* z = at<T>(st, L.z);
+    T* uz = at<T>(st, L.uz);
+    T* a = at<T>(st, L.a);
+    T* ua = at<T>(st, L.ua);
+    T* Rx = at<T>(st, L.Rx);
+    double* scal = at<double>(st, L.scalars);
+    T* pp = at<T>(st, p->off_p);
+    T* pT = at<T>(st, p->off_pT);
+    T* r = at<T>(st, p->off_r);
+    T* q = at<T>(st, p->off_q);
+    T* dy = at<T>(st, p->off_dy);
+    T* dz = at<T>(st, p->off_dz);
+    T* Rp = at<T>(st, p->off_Rp);
+    T* t = at<T>(st, p->off_t);
+    T* da = at<T>(st, p->off_da);
+    double* part = at<double>(st, p->off_partials);
+    Partials P{part, part + (size_t)p->nb_sino * kPartialSlots,
+               part + (size_t)(p->nb_sino + p->nb_img) * kPartialSlots};
+    double* dlog = at<double>(st, p->off_log);
+    const int n = prm->cg_iters;
+    const bool adaptive = prm->rho_mode == DECT_RHO_ADAPTIVE;
+
+    long it0 = 0;
+    if (prm->rho_mode == DECT_RHO_SCHEDULE || log) {
+        DECT_HIP(hipStreamSynchronize(s));
+        double v = 0.0;
+        DECT_HIP(hipMemcpy(&v, scal + S_ITER, sizeof v, hipMemcpyDeviceToHost));
+        it0 = (long)v;
+    }
+    if (prm->rho_mode == DECT_RHO_SCHEDULE &&
+        (!prm->rho_schedule || it0 + n_iters >= (long)prm->rho_schedule_len))
+        return fail(DECT_E_ARG, "rho schedule of length %d does not reach iteration %ld",
+                    prm->rho_schedule_len, it0 + n_iters);
+
+    RedArgs R{P.tiles, p->nb_tiles, P.img, p->nb_img, P.sino, p->nb_sino, scal, dlog, 0,
+              prm->rho_mode, adaptive ? 1 : 0, prm->bal_mu, prm->bal_tau, 0.0, 0.0};
+    auto reduce = [&](int mode, long it) -> hipError_t {
+        RedArgs A = R;
+        A.mode = mode;
+        if (mode == RED_FINAL && prm->rho_mode == DECT_RHO_SCHEDULE) {
+            A.next_rho_c = prm->rho_schedule[2 * (it + 1)];
+            A.next_rho_p = prm->rho_schedule[2 * (it + 1) + 1];
+        }
+        ProfScope ps("reduce", s);
+        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, A);
+        return hipGetLastError();
+    };
+#define DECT_OK_OR(e)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (e);                                                             \
+        if (e_ != hipSuccess)                                                            \
+            return fail(DECT_E_DEVICE, "launch failed: %s (%s:%d)", hipGetErrorString(e_), \
+                        __FILE__, __LINE__);                                             \
+    } while (0)
+
+    for (int k = 0; k < n_iters; ++k) {
+        const long it = it0 + k;
+        // Right-hand side of Eq. (12) and the initial CG residual.
+        BpArgs<T> b{};
+        b.sino = t;
+        b.out = pp;
+        b.out2 = n > 1 ? r : nullptr;
+        b.x = x;
+        b.y = y;
+        b.uy = uy;
+        b.z = z;
+        b.uz = uz;
+        b.partials = P.tiles;
+        DECT_OK_OR(launch_backproject<T>(p, 2, EPI_RHS, b, s));
+        DECT_OK_OR(reduce(RED_GAMMA, it));
+        for (int c = 0; c < n; ++c) {
+            DECT_OK_OR(launch_project_pair<T>(p, pp, pT, Rp, s));
+            BpArgs<T> bq{};
+            bq.sino = Rp;
+            bq.out = n > 1 ? q : nullptr;
+            bq.x = pp;
+            bq.partials = P.tiles;
+            DECT_OK_OR(launch_backproject<T>(p, 2, EPI_Q, bq, s));
+            DECT_OK_OR(reduce(RED_ALPHA, it));
+            if (c < n - 1) {
+                ProfScope ps("cg_vector", s);
+                hipLaunchKernelGGL((k_rx_step<T>), dim3(nblk(p->M)), dim3(256), 0, s, p->M, Rx,
+                                   Rp, scal);
+                hipLaunchKernelGGL((k_cg_step<T, true>), dim3(nblk(p->N)), dim3(256), 0, s,
+                                   p->N, x, pp, r, q, scal, P.img);
+                DECT_OK_OR(reduce(RED_BETA, it));
+                hipLaunchKernelGGL((k_p_step<T>), dim3(nblk(p->N)), dim3(256), 0, s, p->N, pp,
+                                   r, scal);
+            } else {
+                ProfScope ps("cg_vector", s);
+                hipLaunchKernelGGL((k_cg_step<T, false>), dim3(nblk(p->N)), dim3(256), 0, s,
+                                   p->N, x, pp, r, q, scal, P.img);
+            }
+            DECT_OK_OR(hipGetLastError());
+        }
+        // a-update (Eq. (13)) fused with R x += alpha R p, u^a and the next t.
+        UdmArgs<T> u{};
+        u.M = p->M;
+        u.mh = static_cast<const T*>(mh);
+        u.ml = static_cast<const T*>(ml);
+        u.wh = static_cast<const T*>(wh);
+        u.wl = static_cast<const T*>(wl);
+        u.a = a;
+        u.ua = ua;
+        u.Rx = Rx;
+        u.Rp = Rp;
+        u.t = t;
+        u.da = da;
+        u.scal = scal;
+        u.partials = P.sino;
+        u.iters = prm->lm_iters;
+        u.mu0 = prm->lm_mu0;
+        DECT_OK_OR(launch_udm<T>(p, 2, u, s));
+        {
+            ProfScope ps("tv_dual", s);
+            hipLaunchKernelGGL((k_tv_dual<T>), dim3(nblk(p->N)), dim3(256), 0, s, p->nx, p->ny, x,
+                               y, uy, dy, z, uz, dz, scal, P.img);
+        }
+        DECT_OK_OR(hipGetLastError());
+        if (adaptive) {
+            BpArgs<T> bd{};
+            bd.sino = da;
+            bd.y = dy;
+            bd.z = dz;
+            bd.partials = P.tiles;
+            DECT_OK_OR(launch_backproject<T>(p, 2, EPI_DUAL, bd, s));
+        }
+        DECT_OK_OR(reduce(RED_FINAL, it));
+        if (prm->rho_mode != DECT_RHO_FIXED) {
+            const long nmax = p->M > p->N ? p->M : p->N;
+            ProfScope ps("rescale", s);
+            hipLaunchKernelGGL((k_rescale<T>), dim3(nblk(nmax)), dim3(256), 0, s, p->M, p->N, ua,
+                               t, a, Rx, uy, uz, scal);
+            DECT_OK_OR(hipGetLastError());
+        }
+    }
+#undef DECT_OK_OR
+    if (log) {
+        DECT_HIP(hipStreamSynchronize(s));
+        std::vector<double> h((size_t)kLogCap * kLogStride);
+        DECT_HIP(hipMemcpy(h.data(), dlog, h.size() * sizeof(double), hipMemcpyDeviceToHost));
+        bool bad = false;
+        for (int k = 0; k < n_iters; ++k) {
+            const long it = it0 + k;
+            const double* e = &h[(size_t)(it % kLogCap) * kLogStride];
+            dect_iter_log& o = log[k];
+            o.iter = (int32_t)e[0];
+            o.flags = (int32_t)e[1];
+            o.rho[0] = e[2];
+            o.rho[1] = e[3];
+            o.r_primal[0] = e[4];
+            o.r_primal[1] = e[5];
+            o.s_dual[0] = e[6];
+            o.s_dual[1] = e[7];
+            o.data_cost = e[8];
+            o.tv_cost = e[9];
+            bad = bad || (o.flags & 1);
+        }
+        if (bad) return fail(DECT_E_NONFINITE, "a non-finite residual or objective was produced");
+    }
+    return DECT_OK;
+}
+
+template <typename T>
+dect_status init_T(const dect_plan* p, const void* mh, const void* ml, const void* wh,
+                   const void* wl, void* st, const dect_params* prm, hipStream_t s) {
+    const size_t words = p->layout.bytes / 4;
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, s,
+                       static_cast<uint32_t*>(st), words);
+    hipLaunchKernelGGL(k_set_scalars, dim3(1), dim3(64), 0, s, at<double>(st, p->layout.scalars),
+                       prm->rho_c, prm->rho_p, prm->lambda_c, prm->lambda_p);
+    UdmArgs<T> u{};
+    u.M = p->M;
+    u.mh = static_cast<const T*>(mh);
+    u.ml = static_cast<const T*>(ml);
+    u.wh = static_cast<const T*>(wh);
+    u.wl = static_cast<const T*>(wl);
+    u.a = at<T>(st, p->layout.a);
+    u.t = at<T>(st, p->off_t);
+    u.iters = 10;
+    u.mu0 = prm->lm_mu0;
+    // Inverse of the linearisation at a = 0: rows (mean f_KN, mean f_p) per spectrum.
+    const double hc = p->mean_f[0][0], hp = p->mean_f[0][1];
+    const double lc = p->mean_f[1][0], lp = p->mean_f[1][1];
+    const double det = hc * lp - hp * lc;
+    u.lin[0] = lp / det;
+    u.lin[1] = -hp / det;
+    u.lin[2] = -lc / det;
+    u.lin[3] = hc / det;
+    hipError_t e = launch_udm<T>(p, 1, u, s);
+    if (e != hipSuccess) return fail(DECT_E_DEVICE, "launch failed: %s", hipGetErrorString(e));
+    return DECT_OK;
+}
+
+dect_status check_params(const dect_params* prm) {
+    if (!prm) return fail(DECT_E_ARG, "null params");
+    if (prm->lm_iters < 1 || prm->cg_iters < 1)
+        return fail(DECT_E_ARG, "lm_iters and cg_iters must be >= 1");
+    if (prm->rho_mode < DECT_RHO_FIXED || prm->rho_mode > DECT_RHO_SCHEDULE)
+        return fail(DECT_E_ARG, "bad rho_mode %d", prm->rho_mode);
+    if (!(prm->rho_c > 0) || !(prm->rho_p > 0) || !(prm->lambda_c >= 0) || !(prm->lambda_p >= 0))
+        return fail(DECT_E_ARG, "rho must be > 0 and lambda >= 0");
+    if (prm->rho_mode == DECT_RHO_ADAPTIVE && (!(prm->bal_mu > 1) || !(prm->bal_tau > 1)))
+        return fail(DECT_E_ARG, "residual balancing needs mu > 1 and tau > 1");
+    if (!(prm->lm_mu0 > 0)) return fail(DECT_E_ARG, "lm_mu0 must be > 0");
+    return DECT_OK;
+}
+
+bool bad_ch(int ch) { return ch != 1 && ch != 2 && ch != 4; }
+
+}  // namespace
+}  // namespace dect
+
+using namespace dect;
+
+extern "C" {
+
+dect_status dect_project(const dect_plan* p, const void* img, void* sino, int ch, void* stream) {
+    if (!p || !img || !sino) return fail(DECT_E_ARG, "null argument");
+    if (bad_ch(ch)) return fail(DECT_E_ARG, "ch must be 1, 2 or 4 (got %d)", ch);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = p->dtype == DECT_F32 ? launch_project<float>(p, img, sino, ch, s)
+                                        : launch_project<double>(p, img, sino, ch, s);
+    if (e != hipSuccess) return fail(DECT_E_DEVICE, "launch failed: %s", hipGetErrorString(e));
+    return DECT_OK;
+}
+
+dect_status dect_backproject(const dect_plan* p, const void* sino, void* img, int ch,
+                             void* stream) {
+    if (!p || !img || !sino) return fail(DECT_E_ARG, "null argument");
+    if (bad_ch(ch)) return fail(DECT_E_ARG, "ch must be 1, 2 or 4 (got %d)", ch);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e;
+    if (p->dtype == DECT_F32) {
+        BpArgs<float> a{};
+        a.sino = static_cast<const float*>(sino);
+        a.out = static_cast<float*>(img);
+        e = launch_backproject<float>(p, ch, EPI_NONE, a, s);
+    } else {
+        BpArgs<double> a{};
+        a.sino = static_cast<const double*>(sino);
+        a.out = static_cast<double*>(img);
+        e = launch_backproject<double>(p, ch, EPI_NONE, a, s);
+    }
+    if (e != hipSuccess) return fail(DECT_E_DEVICE, "launch failed: %s", hipGetErrorString(e));
+    return DECT_OK;
+}
+
+dect_status dect_decompose_rays(const dect_plan* p, const void* m_h, const void* m_l,
+                                const void* w_h, const void* w_l, const void* v, double rho_c,
+                                double rho_p, int lm_iters, void* a, void* cost, void* stream) {
+    if (!p || !m_h || !m_l || !w_h || !w_l || !a) return fail(DECT_E_ARG, "null argument");
+    if (lm_iters < 0) return fail(DECT_E_ARG, "lm_iters must be >= 0");
+    if (v && (!(rho_c >= 0) || !(rho_p >= 0))) return fail(DECT_E_ARG, "rho must be >= 0");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e;
+    if (p->dtype == DECT_F32) {
+        UdmArgs<float> u{};
+        u.M = p->M;
+        u.mh = static_cast<const float*>(m_h);
+        u.ml = static_cast<const float*>(m_l);
+        u.wh = static_cast<const float*>(w_h);
+        u.wl = static_cast<const float*>(w_l);
+        u.a = static_cast<float*>(a);
+        u.v = static_cast<const float*>(v);
+        u.cost = static_cast<float*>(cost);
+        u.rho_c = rho_c;
+        u.rho_p = rho_p;
+        u.iters = lm_iters;
+        u.mu0 = 1e-3;
+        e = launch_udm<float>(p, 0, u, s);
+    } else {
+        UdmArgs<double> u{};
+        u.M = p->M;
+        u.mh = static_cast<const double*>(m_h);
+        u.ml = static_cast<const double*>(m_l);
+        u.wh = static_cast<const double*>(w_h);
+        u.wl = static_cast<const double*>(w_l);
+        u.a = static_cast<double*>(a);
+        u.v = static_cast<const double*>(v);
+        u.cost = static_cast<double*>(cost);
+        u.rho_c = rho_c;
+        u.rho_p = rho_p;
+        u.iters = lm_iters;
+        u.mu0 = 1e-3;
+        e = launch_udm<double>(p, 0, u, s);
+    }
+    if (e != hipSuccess) return fail(DECT_E_DEVICE, "launch failed: %s", hipGetErrorString(e));
+    return DECT_OK;
+}
+
+dect_status dect_ingest_counts(const dect_plan* p, const void* counts_h, const void* counts_l,
+                               double i0_h, double i0_l, void* m_h, void* m_l, void* w_h,
+                               void* w_l, void* stream) {
+    if (!p || !counts_h || !counts_l || !m_h || !m_l || !w_h || !w_l)
+        return fail(DECT_E_ARG, "null argument");
+    if (!(i0_h > 0) || !(i0_l > 0)) return fail(DECT_E_ARG, "I0 must be positive");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = p->dtype == DECT_F32
+                       ? launch_ingest<float>(p, counts_h, counts_l, i0_h, i0_l, m_h, m_l, w_h, w_l, s)
+                       : launch_ingest<double>(p, counts_h, counts_l, i0_h, i0_l, m_h, m_l, w_h, w_l, s);
+    if (e != hipSuccess) return fail(DECT_E_DEVICE, "launch failed: %s", hipGetErrorString(e));
+    return DECT_OK;
+}
+
+dect_status dect_admm_init(const dect_plan* p, const void* m_h, const void* m_l,
+                           const void* w_h, const void* w_l, void* state,
+                           const dect_params* prm, void* stream) {
+    if (!p || !m_h || !m_l || !w_h || !w_l || !state) return fail(DECT_E_ARG, "null argument");
+    if (reinterpret_cast<uintptr_t>(state) % 256)
+        return fail(DECT_E_ARG, "state buffer must be 256-byte aligned");
+    dect_status st = check_params(prm);
+    if (st) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return p->dtype == DECT_F32 ? init_T<float>(p, m_h, m_l, w_h, w_l, state, prm, s)
+                                : init_T<double>(p, m_h, m_l, w_h, w_l, state, prm, s);
+}
+
+dect_status dect_admm_iterate(const dect_plan* p, const void* m_h, const void* m_l,
+                              const void* w_h, const void* w_l, void* state,
+                              const dect_params* prm, int n_iters, dect_iter_log* log,
+                              void* stream) {
+    if (!p || !m_h || !m_l || !w_h || !w_l || !state) return fail(DECT_E_ARG, "null argument");
+    if (reinterpret_cast<uintptr_t>(state) % 256)
+        return fail(DECT_E_ARG, "state buffer must be 256-byte aligned");
+    dect_status st = check_params(prm);
+    if (st) return st;
+    if (n_iters < 0) return fail(DECT_E_ARG, "n_iters must be >= 0");
+    if (log && n_iters > kLogCap)
+        return fail(DECT_E_ARG, "a log holds at most %d iterations per call", kLogCap);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return p->dtype == DECT_F32
+               ? iterate_T<float>(p, m_h, m_l, w_h, w_l, state, prm, n_iters, log, s)
+               : iterate_T<double>(p, m_h, m_l, w_h, w_l, state, prm, n_iters, log, s);
+}
+
+}  // extern "C"

@@ -1,0 +1,128 @@
+// Internal declarations of the dual-energy CT ADMM library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "dect.h"
+
+namespace dect {
+
+// ---------------------------------------------------------------- errors ---
+void set_error(const char* fmt, ...);
+dect_status fail(dect_status st, const char* fmt, ...);
+
+#define DECT_HIP(expr)                                                               \
+    do {                                                                             \
+        hipError_t e_ = (expr);                                                      \
+        if (e_ != hipSuccess)                                                        \
+            return ::dect::fail(DECT_E_DEVICE, "%s failed: %s (%s:%d)", #expr,       \
+                                hipGetErrorString(e_), __FILE__, __LINE__);          \
+    } while (0)
+
+#define DECT_LAUNCH_CHECK()                                                          \
+    do {                                                                             \
+        hipError_t e_ = hipGetLastError();                                           \
+        if (e_ != hipSuccess)                                                        \
+            return ::dect::fail(DECT_E_DEVICE, "kernel launch failed: %s (%s:%d)",   \
+                                hipGetErrorString(e_), __FILE__, __LINE__);          \
+    } while (0)
+
+// ------------------------------------------------------------ vector types ---
+// N values of T stored together, aligned so that one load moves all of them.
+template <typename T, int N>
+struct alignas(sizeof(T) * N) vec {
+    T v[N];
+};
+
+// -------------------------------------------------------------- plan tables ---
+// Joseph parameters of one ray.  An x-stepped ray (|d_x| >= |d_y|) is sampled at
+// every pixel column i at the fractional row phi(i) = phi0 + slope * i; a
+// y-stepped ray at every row j at the fractional column phi0 + slope * j.  Each
+// sample is weighted by `step`, the ray length between two samples.  The forward
+// projector and the transposed gather both evaluate phi with one fma on these
+// exact values, so their interpolation weights are bit-identical.
+template <typename T>
+struct alignas(sizeof(T) * 4) RayParam {
+    T phi0, slope, step, pad;
+};
+
+// Per-view data for the pixel-driven transpose.  The detector coordinate (in
+// bins) of the ray through the point with centred pixel coordinates (i', j') is
+//   beta = (ni i' + nj j') / (d0 + di i' + dj j') + boff
+// (fan beam: central projection from the source; parallel: d0 = 1, di = dj = 0).
+// Bins [xb0, xb1) of the view are x-stepped, [yb0, yb1) y-stepped.
+template <typename T>
+struct ViewParam {
+    T ni, nj, d0, di, dj, boff;
+    int xb0, xb1, yb0, yb1;
+};
+
+// Energy-bin tables of one spectrum in base-2 units: the normalised weight as
+// lw = log2(omega), and kc = f_KN log2(e), kp = f_p log2(e), nonzero bins only.
+template <typename T>
+struct SpecTables {
+    const T* lw;
+    const T* kc;
+    const T* kp;
+    int n;
+};
+
+}  // namespace dect
+
+// The plan: everything that depends on geometry, spectra and precision only.
+struct dect_plan {
+    dect_geometry geom;
+    dect_dtype dtype;
+    int device;
+    size_t elem;            // bytes per scalar
+    int nx, ny, V, D;
+    long N, M;              // pixels, rays
+    // device tables
+    void* rays = nullptr;   // RayParam<T>[M]
+    void* views = nullptr;  // ViewParam<T>[V]
+    void* spec = nullptr;   // T[6 * Kmax]: lw_h, kc_h, kp_h, lw_l, kc_l, kp_l
+    int kh = 0, kl = 0, kmax = 0;
+    double mean_f[2][2];    // spectrum-mean (f_KN, f_p) per spectrum (h, l)
+    // plan-owned scratch: a transposed copy of the image being projected
+    void* scratch_imgT = nullptr;  // T[N * 4]
+    // state layout (bytes)
+    dect_layout layout;
+    size_t off_p, off_pT, off_r, off_q, off_dy, off_dz, off_Rp, off_t, off_da, off_partials,
+        off_log;
+    int nb_sino, nb_img, nb_tiles;  // block counts of the reducing kernels
+};
+
+namespace dect {
+
+constexpr int kLogCap = 256;      // iterations kept in the device log ring
+constexpr int kLogStride = 12;    // doubles per log entry
+constexpr int kPartialSlots = 4;  // doubles per block partial
+
+// Device scalar block (doubles), at layout.scalars.
+enum Scalar : int {
+    S_RHO = 0,      // [2] rho in force
+    S_KAPPA = 2,    // [2] pending dual rescale rho_old / rho_new
+    S_GAMMA = 4,    // [2] r.r
+    S_ALPHA = 6,    // [2] CG step
+    S_BETA = 8,     // [2] CG direction update
+    S_PQ = 10,      // [2] p.q
+    S_ITER = 12,    // outer iteration counter
+    S_FLAGS = 13,   // bit 0: non-finite value met
+    S_LAM = 14,     // [2] lambda
+    S_NEXT_RHO = 16,// [2] scheduled rho of the next iteration
+    S_COUNT = 24
+};
+
+// Partial-sum sections (block partials of kPartialSlots doubles each).
+struct Partials {
+    double* sino;   // UDM: |a-Rx|^2 c, p; data cost; non-finite count
+    double* img;    // TV: |y-Dx|^2+|z-x|^2 c, p; |y_c|_1, |y_p|_1
+    double* tiles;  // backprojection epilogues: two sums per tile
+};
+
+}  // namespace dect

@@ -1,0 +1,326 @@
+// Plan creation: geometry validation, Joseph ray tables, per-view footprint
+// tables, spectral tables and the per-slice state layout.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "common.h"
+
+namespace dect {
+
+static thread_local std::string g_last_error;
+
+void set_error(const char* fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+}
+
+dect_status fail(dect_status st, const char* fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+namespace {
+
+struct HostRay {
+    double phi0, slope, step;
+    bool xstep;
+};
+
+// Joseph parameters of ray (v, b), from the ray's line in scanner coordinates.
+HostRay host_ray(const dect_geometry& g, int v, int b) {
+    const double t = g.angle0 + (double)v * g.span / (double)g.n_views;
+    const double c = std::cos(t), s = std::sin(t);
+    const double u = ((double)b - 0.5 * (double)(g.n_det - 1) + g.det_offset) * g.det_cm;
+    double ox, oy, dx, dy;
+    if (g.kind == DECT_PARALLEL) {
+        ox = u * c;
+        oy = u * s;
+        dx = -s;
+        dy = c;
+    } else {
+        ox = g.src_iso_cm * c;
+        oy = g.src_iso_cm * s;
+        const double qx = -(g.src_det_cm - g.src_iso_cm) * c - u * s;
+        const double qy = -(g.src_det_cm - g.src_iso_cm) * s + u * c;
+        dx = qx - ox;
+        dy = qy - oy;
+    }
+    const double d = g.pixel_cm, cx = 0.5 * (g.nx - 1), cy = 0.5 * (g.ny - 1);
+    HostRay r;
+    if (std::fabs(dx) >= std::fabs(dy)) {
+        // Row coordinate where the ray crosses column i: linear in i.
+        r.xstep = true;
+        r.slope = dy / dx;
+        r.phi0 = (oy - ox * r.slope) / d - cx * r.slope + cy;
+    } else {
+        r.xstep = false;
+        r.slope = dx / dy;
+        r.phi0 = (ox - oy * r.slope) / d - cy * r.slope + cx;
+    }
+    r.step = d * std::sqrt(1.0 + r.slope * r.slope);
+    return r;
+}
+
+template <typename T>
+dect_status upload(const void* host, size_t bytes, void** dev) {
+    DECT_HIP(hipMalloc(dev, bytes));
+    DECT_HIP(hipMemcpy(*dev, host, bytes, hipMemcpyHostToDevice));
+    return DECT_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+template <typename T>
+dect_status build_tables(dect_plan* p, const dect_spectra* spec) {
+    const dect_geometry& g = p->geom;
+    const int V = p->V, D = p->D;
+    std::vector<RayParam<T>> rays((size_t)V * D);
+    std::vector<ViewParam<T>> views(V);
+    const double d = g.pixel_cm;
+    for (int v = 0; v < V; ++v) {
+        int first_kind = -1, switches = 0, split = D;
+        for (int b = 0; b < D; ++b) {
+            HostRay r = host_ray(g, v, b);
+            RayParam<T>& q = rays[(size_t)v * D + b];
+            q.phi0 = (T)r.phi0;
+            q.slope = (T)r.slope;
+            q.step = (T)r.step;
+            q.pad = (T)(r.xstep ? 0 : 1);
+            int kind = r.xstep ? 0 : 1;
+            if (b == 0) {
+                first_kind = kind;
+            } else if (kind != (int)rays[(size_t)v * D + b - 1].pad) {
+                ++switches;
+                split = b;
+            }
+        }
+        if (switches > 1)
+            return fail(DECT_E_SHAPE,
+                        "view %d: x- and y-stepped rays interleave (%d switches); the fan is "
+                        "wider than 90 degrees",
+                        v, switches);
+        ViewParam<T>& w = views[v];
+        const int lo0 = 0, hi0 = split, lo1 = split, hi1 = D;
+        if (first_kind == 0) {
+            w.xb0 = lo0; w.xb1 = hi0; w.yb0 = lo1; w.yb1 = hi1;
+        } else {
+            w.yb0 = lo0; w.yb1 = hi0; w.xb0 = lo1; w.xb1 = hi1;
+        }
+        const double t = g.angle0 + (double)v * g.span / (double)g.n_views;
+        const double c = std::cos(t), s = std::sin(t);
+        const double boff = 0.5 * (D - 1) - g.det_offset;
+        if (g.kind == DECT_PARALLEL) {
+            w.ni = (T)(d * c / g.det_cm);
+            w.nj = (T)(d * s / g.det_cm);
+            w.d0 = (T)1;
+            w.di = (T)0;
+            w.dj = (T)0;
+        } else {
+            const double K = g.src_det_cm / g.det_cm;
+            w.ni = (T)(-K * d * s);
+            w.nj = (T)(K * d * c);
+            w.d0 = (T)g.src_iso_cm;
+            w.di = (T)(-d * c);
+            w.dj = (T)(-d * s);
+        }
+        w.boff = (T)boff;
+    }
+    dect_status st = upload<T>(rays.data(), rays.size() * sizeof(rays[0]), &p->rays);
+    if (st) return st;
+    st = upload<T>(views.data(), views.size() * sizeof(views[0]), &p->views);
+    if (st) return st;
+
+    // Spectral tables: normalised spectra on their nonzero bins, base-2 units.
+    const double log2e = 1.4426950408889634;
+    std::vector<T> tab[2][3];
+    const double* S[2] = {spec->s_high, spec->s_low};
+    for (int h = 0; h < 2; ++h) {
+        double tot = 0.0;
+        for (int k = 0; k < spec->n_bins; ++k) tot += S[h][k];
+        double mkn = 0.0, mp = 0.0;
+        for (int k = 0; k < spec->n_bins; ++k) {
+            if (!(S[h][k] > 0.0)) continue;
+            const double om = S[h][k] / tot;
+            tab[h][0].push_back((T)std::log2(om));
+            tab[h][1].push_back((T)(spec->f_kn[k] * log2e));
+            tab[h][2].push_back((T)(spec->f_p[k] * log2e));
+            mkn += om * spec->f_kn[k];
+            mp += om * spec->f_p[k];
+        }
+        p->mean_f[h][0] = mkn;
+        p->mean_f[h][1] = mp;
+    }
+    p->kh = (int)tab[0][0].size();
+    p->kl = (int)tab[1][0].size();
+    p->kmax = p->kh > p->kl ? p->kh : p->kl;
+    std::vector<T> packed((size_t)6 * p->kmax, (T)0);
+    for (int h = 0; h < 2; ++h)
+        for (int q = 0; q < 3; ++q)
+            for (size_t k = 0; k < tab[h][q].size(); ++k)
+                packed[(size_t)(3 * h + q) * p->kmax + k] = tab[h][q][k];
+    st = upload<T>(packed.data(), packed.size() * sizeof(T), &p->spec);
+    if (st) return st;
+    DECT_HIP(hipMalloc(&p->scratch_imgT, (size_t)p->N * 4 * sizeof(T)));
+    return DECT_OK;
+}
+
+void make_layout(dect_plan* p) {
+    const size_t e = p->elem;
+    const size_t N = (size_t)p->N, M = (size_t)p->M;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    dect_layout& L = p->layout;
+    L.x = take(N * 2 * e);
+    L.y = take(N * 4 * e);
+    L.uy = take(N * 4 * e);
+    L.z = take(N * 2 * e);
+    L.uz = take(N * 2 * e);
+    L.a = take(M * 2 * e);
+    L.ua = take(M * 2 * e);
+    L.Rx = take(M * 2 * e);
+    L.scalars = take(S_COUNT * sizeof(double));
+    p->off_p = take(N * 2 * e);
+    p->off_pT = take(N * 2 * e);
+    p->off_r = take(N * 2 * e);
+    p->off_q = take(N * 2 * e);
+    p->off_dy = take(N * 4 * e);
+    p->off_dz = take(N * 2 * e);
+    p->off_Rp = take(M * 2 * e);
+    p->off_t = take(M * 2 * e);
+    p->off_da = take(M * 2 * e);
+    p->nb_sino = (int)((M + 255) / 256);
+    p->nb_img = (int)((N + 255) / 256);
+    p->nb_tiles = ((p->nx + 15) / 16) * ((p->ny + 15) / 16);
+    p->off_partials =
+        take((size_t)(p->nb_sino + p->nb_img + p->nb_tiles) * kPartialSlots * sizeof(double));
+    p->off_log = take((size_t)kLogCap * kLogStride * sizeof(double));
+    L.bytes = off;
+}
+
+}  // namespace
+}  // namespace dect
+
+using namespace dect;
+
+extern "C" {
+
+const char* dect_last_error(void) { return g_last_error.c_str(); }
+
+dect_status dect_plan_create(const dect_geometry* geom, const dect_spectra* spec,
+                             dect_dtype dtype, dect_plan** out) {
+    if (!geom || !spec || !out) return fail(DECT_E_ARG, "null argument");
+    *out = nullptr;
+    const dect_geometry& g = *geom;
+    if (dtype != DECT_F32 && dtype != DECT_F64) return fail(DECT_E_ARG, "bad dtype %d", dtype);
+    if (g.kind != DECT_PARALLEL && g.kind != DECT_FAN)
+        return fail(DECT_E_ARG, "bad geometry kind %d", g.kind);
+    if (g.nx < 2 || g.ny < 2 || g.n_views < 1 || g.n_det < 1)
+        return fail(DECT_E_SHAPE, "image must be at least 2x2 and have views and bins");
+    if ((long)g.nx * g.ny > (1L << 30) || (long)g.n_views * g.n_det > (1L << 30))
+        return fail(DECT_E_SHAPE, "image or sinogram larger than 2^30 elements");
+    if (!(g.pixel_cm > 0) || !(g.det_cm > 0) || !std::isfinite(g.span) ||
+        !std::isfinite(g.angle0) || !std::isfinite(g.det_offset))
+        return fail(DECT_E_SHAPE, "pixel and bin sizes must be positive, angles finite");
+    if (g.kind == DECT_FAN) {
+        const double rc = 0.5 * g.pixel_cm * std::hypot((double)g.nx, (double)g.ny);
+        if (!(g.src_det_cm > g.src_iso_cm) || !(g.src_iso_cm > rc + 2.0 * g.pixel_cm))
+            return fail(DECT_E_SHAPE,
+                        "fan source must lie outside the image's circumscribed circle "
+                        "(radius %.4g cm) by two pixels, detector beyond the centre",
+                        rc);
+    }
+    if (spec->n_bins < 1 || !spec->s_high || !spec->s_low || !spec->f_kn || !spec->f_p)
+        return fail(DECT_E_ARG, "spectra: null table or no bins");
+    for (int h = 0; h < 2; ++h) {
+        const double* S = h ? spec->s_low : spec->s_high;
+        double tot = 0.0;
+        for (int k = 0; k < spec->n_bins; ++k) {
+            if (!(S[k] >= 0.0)) return fail(DECT_E_ARG, "spectrum %d bin %d negative", h, k);
+            tot += S[k];
+        }
+        if (!(tot > 0.0)) return fail(DECT_E_ARG, "spectrum %d has no photons", h);
+    }
+    for (int k = 0; k < spec->n_bins; ++k)
+        if (!(spec->f_kn[k] > 0.0) || !(spec->f_p[k] >= 0.0))
+            return fail(DECT_E_ARG, "f_kn must be > 0 and f_p >= 0 (bin %d)", k);
+
+    dect_plan* p = new (std::nothrow) dect_plan();
+    if (!p) return fail(DECT_E_NOMEM, "host allocation failed");
+    p->geom = g;
+    p->dtype = dtype;
+    p->elem = dtype == DECT_F32 ? 4 : 8;
+    p->nx = g.nx;
+    p->ny = g.ny;
+    p->V = g.n_views;
+    p->D = g.n_det;
+    p->N = (long)g.nx * g.ny;
+    p->M = (long)g.n_views * g.n_det;
+    if (hipGetDevice(&p->device) != hipSuccess) {
+        delete p;
+        return fail(DECT_E_DEVICE, "no HIP device");
+    }
+    dect_status st = dtype == DECT_F32 ? build_tables<float>(p, spec) : build_tables<double>(p, spec);
+    if (st != DECT_OK) {
+        dect_plan_destroy(p);
+        return st;
+    }
+    make_layout(p);
+    *out = p;
+    return DECT_OK;
+}
+
+void dect_plan_destroy(dect_plan* p) {
+    if (!p) return;
+    (void)hipFree(p->rays);
+    (void)hipFree(p->views);
+    (void)hipFree(p->spec);
+    (void)hipFree(p->scratch_imgT);
+    delete p;
+}
+
+dect_status dect_plan_get_info(const dect_plan* p, dect_plan_info* out) {
+    if (!p || !out) return fail(DECT_E_ARG, "null argument");
+    dect_plan_info info{};
+    info.n_pixels = p->N;
+    info.n_rays = p->M;
+    // Same sampling rule as the projector, in double precision.
+    for (int v = 0; v < p->V; ++v)
+        for (int b = 0; b < p->D; ++b) {
+            HostRay r = host_ray(p->geom, v, b);
+            const int n_steps = r.xstep ? p->nx : p->ny, n_lines = r.xstep ? p->ny : p->nx;
+            for (int k = 0; k < n_steps; ++k) {
+                const double j0 = std::floor(r.phi0 + r.slope * k);
+                const int in0 = (j0 >= 0 && j0 < n_lines), in1 = (j0 + 1 >= 0 && j0 + 1 < n_lines);
+                info.samples += (in0 | in1);
+                info.taps += in0 + in1;
+            }
+        }
+    *out = info;
+    return DECT_OK;
+}
+
+size_t dect_state_bytes(const dect_plan* plan) { return plan ? plan->layout.bytes : 0; }
+
+dect_status dect_state_layout(const dect_plan* plan, dect_layout* out) {
+    if (!plan || !out) return fail(DECT_E_ARG, "null argument");
+    *out = plan->layout;
+    return DECT_OK;
+}
+
+}  // extern "C"

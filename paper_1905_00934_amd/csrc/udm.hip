@@ -1,0 +1,236 @@
+// Per-ray unconstrained decomposition (Eq. (13)) by Levenberg-Marquardt, and the
+// count-to-measurement ingest, for gfx950.
+//
+// One ray per lane.  The energy-bin tables are read with wave-uniform indices,
+// so they come from scalar loads and every lane runs the same bin loop; the
+// only divergence is the per-ray accept/reject of the LM step.  The polychromatic
+// transform f_s(a) = -ln sum_k omega_k exp(-f_KN[k] a_c - f_p[k] a_p) (Eq. (3))
+// is a log-sum-exp evaluated in base 2 with the largest exponent factored out,
+// which keeps metal rays (exponents below -700) finite in single precision.
+#include <cmath>
+
+#include "common.h"
+#include "kernels.h"
+#include "profile.h"
+
+namespace dect {
+
+namespace {
+
+template <typename T> struct Cst;
+template <> struct Cst<float> {
+    __device__ static float exp2(float x) { return exp2f(x); }
+    __device__ static float log2(float x) { return log2f(x); }
+};
+template <> struct Cst<double> {
+    __device__ static double exp2(double x) { return ::exp2(x); }
+    __device__ static double log2(double x) { return ::log2(x); }
+};
+
+// f and gradient of one spectrum at (ac, ap), tables in base-2 units.
+template <typename T>
+__device__ inline void spectrum_eval(const T* __restrict__ lw, const T* __restrict__ kc,
+                                     const T* __restrict__ kp, int n, T ac, T ap, T& f, T& gc,
+                                     T& gp) {
+    constexpr T ln2 = T(0.6931471805599453);
+    T m = -INFINITY;
+#pragma unroll 4
+    for (int k = 0; k < n; ++k) m = fmax(m, lw[k] - kc[k] * ac - kp[k] * ap);
+    T z = T(0), sc = T(0), sp = T(0);
+#pragma unroll 4
+    for (int k = 0; k < n; ++k) {
+        const T q = Cst<T>::exp2(lw[k] - kc[k] * ac - kp[k] * ap - m);
+        z += q;
+        sc += q * kc[k];
+        sp += q * kp[k];
+    }
+    f = -(m + Cst<T>::log2(z)) * ln2;
+    // sum_k q_k f_KN[k] / z = ln2 * sum_k q_k kc[k] / z, since kc = f_KN / ln2.
+    const T iz = ln2 / z;
+    gc = sc * iz;
+    gp = sp * iz;
+}
+
+template <typename T>
+struct Point {
+    T ac, ap, fh, fl, ghc, ghp, glc, glp, phi;
+};
+
+template <typename T>
+__device__ inline void evaluate(const T* __restrict__ spec, int kmax, int kh, int kl, T mh, T ml,
+                                T wh, T wl, T vc, T vp, T rc, T rp, Point<T>& P) {
+    spectrum_eval<T>(spec, spec + kmax, spec + 2 * kmax, kh, P.ac, P.ap, P.fh, P.ghc, P.ghp);
+    spectrum_eval<T>(spec + 3 * kmax, spec + 4 * kmax, spec + 5 * kmax, kl, P.ac, P.ap, P.fl,
+                     P.glc, P.glp);
+    const T rh = P.fh - mh, rl = P.fl - ml, dc = P.ac - vc, dp = P.ap - vp;
+    P.phi = T(0.5) * (wh * rh * rh + wl * rl * rl) + T(0.5) * (rc * dc * dc + rp * dp * dp);
+}
+
+// a*d - b*c with the rounding error of b*c compensated (Kahan).
+template <typename T>
+__device__ inline T det2(T a, T d, T b, T c) {
+    const T w = b * c;
+    const T e = fma(-b, c, w);
+    const T f = fma(a, d, -w);
+    return f + e;
+}
+
+// m Levenberg-Marquardt iterations from P (evaluated); P ends at the last accepted point.
+template <typename T>
+__device__ inline void lm_solve(const T* __restrict__ spec, int kmax, int kh, int kl, T mh, T ml,
+                                T wh, T wl, T vc, T vp, T rc, T rp, int iters, T mu,
+                                Point<T>& P) {
+    for (int it = 0; it < iters; ++it) {
+        const T rh = P.fh - mh, rl = P.fl - ml;
+        const T Gc = wh * rh * P.ghc + wl * rl * P.glc + rc * (P.ac - vc);
+        const T Gp = wh * rh * P.ghp + wl * rl * P.glp + rp * (P.ap - vp);
+        const T Acc = wh * P.ghc * P.ghc + wl * P.glc * P.glc;
+        const T App = wh * P.ghp * P.ghp + wl * P.glp * P.glp;
+        const T Hcc = Acc + rc, Hpp = App + rp;
+        const T Hcp = wh * P.ghc * P.ghp + wl * P.glc * P.glp;
+        // det(H + mu diag H) as a sum of nonnegative terms (no cancellation):
+        // w_h w_l (g_h x g_l)^2 + rc App + rp Acc + rc rp + mu (2 + mu) Hcc Hpp.
+        const T cr = det2<T>(P.ghc, P.glp, P.ghp, P.glc);
+        const T det = wh * wl * cr * cr + rc * App + rp * Acc + rc * rp +
+                      mu * (T(2) + mu) * Hcc * Hpp;
+        if (!(det > T(0)) || !(det < INFINITY)) {
+            mu *= T(10);
+            continue;
+        }
+        const T Dcc = (T(1) + mu) * Hcc, Dpp = (T(1) + mu) * Hpp;
+        const T id = T(1) / det;
+        Point<T> Q;
+        Q.ac = P.ac - (Dpp * Gc - Hcp * Gp) * id;
+        Q.ap = P.ap - (Dcc * Gp - Hcp * Gc) * id;
+        evaluate<T>(spec, kmax, kh, kl, mh, ml, wh, wl, vc, vp, rc, rp, Q);
+        if (Q.phi < P.phi) {
+            P = Q;
+            mu *= T(0.1);
+        } else {
+            mu *= T(10);
+        }
+    }
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void k_udm(UdmArgs<T> A, const T* __restrict__ spec, int kmax,
+                                             int kh, int kl) {
+    using V2 = vec<T, 2>;
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    double part[4] = {0.0, 0.0, 0.0, 0.0};
+    if (i < A.M) {
+        const T mh = A.mh[i], ml = A.ml[i], wh = A.wh[i], wl = A.wl[i];
+        V2* a2 = reinterpret_cast<V2*>(A.a);
+        Point<T> P;
+        T vc = T(0), vp = T(0), rc = T(0), rp = T(0);
+        V2 rx;
+        V2 ua;
+        const V2 a_prev = a2[i];
+        if constexpr (MODE == 1) {
+            // Initialisation: start at the solution of the linearisation at a = 0.
+            P.ac = (T)(A.lin[0] * (double)mh + A.lin[1] * (double)ml);
+            P.ap = (T)(A.lin[2] * (double)mh + A.lin[3] * (double)ml);
+        } else {
+            P.ac = a_prev.v[0];
+            P.ap = a_prev.v[1];
+        }
+        if constexpr (MODE == 0) {
+            if (A.v) {
+                const V2 v2 = reinterpret_cast<const V2*>(A.v)[i];
+                vc = v2.v[0];
+                vp = v2.v[1];
+                rc = (T)A.rho_c;
+                rp = (T)A.rho_p;
+            }
+        } else if constexpr (MODE == 2) {
+            // R x after the last CG step (tracked: R x += alpha R p), v = R x - u^a.
+            const V2 rx0 = reinterpret_cast<const V2*>(A.Rx)[i];
+            const V2 rp2 = reinterpret_cast<const V2*>(A.Rp)[i];
+            ua = reinterpret_cast<const V2*>(A.ua)[i];
+            rx.v[0] = rx0.v[0] + (T)A.scal[S_ALPHA] * rp2.v[0];
+            rx.v[1] = rx0.v[1] + (T)A.scal[S_ALPHA + 1] * rp2.v[1];
+            vc = rx.v[0] - ua.v[0];
+            vp = rx.v[1] - ua.v[1];
+            rc = (T)A.scal[S_RHO];
+            rp = (T)A.scal[S_RHO + 1];
+        }
+        evaluate<T>(spec, kmax, kh, kl, mh, ml, wh, wl, vc, vp, rc, rp, P);
+        lm_solve<T>(spec, kmax, kh, kl, mh, ml, wh, wl, vc, vp, rc, rp, A.iters, (T)A.mu0, P);
+        V2 an;
+        an.v[0] = P.ac;
+        an.v[1] = P.ap;
+        a2[i] = an;
+        if constexpr (MODE == 0) {
+            if (A.cost) A.cost[i] = P.phi;
+        } else if constexpr (MODE == 1) {
+            reinterpret_cast<V2*>(A.t)[i] = an;  // u^a = R x = 0
+        } else {
+            V2 un, tn, dn;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                un.v[c] = ua.v[c] + an.v[c] - rx.v[c];        // Eq. (11), a-block
+                tn.v[c] = an.v[c] + un.v[c] - rx.v[c];        // next R^T right-hand side
+                dn.v[c] = an.v[c] - a_prev.v[c];
+                part[c] = (double)(an.v[c] - rx.v[c]) * (double)(an.v[c] - rx.v[c]);
+            }
+            reinterpret_cast<V2*>(A.ua)[i] = un;
+            reinterpret_cast<V2*>(A.Rx)[i] = rx;
+            reinterpret_cast<V2*>(A.t)[i] = tn;
+            reinterpret_cast<V2*>(A.da)[i] = dn;
+            const T rh = P.fh - mh, rl = P.fl - ml;
+            part[2] = 0.5 * ((double)wh * (double)rh * (double)rh + (double)wl * (double)rl * (double)rl);
+            const bool finite = (P.ac - P.ac == T(0)) && (P.ap - P.ap == T(0)) &&
+                                (part[2] - part[2] == 0.0);
+            part[3] = finite ? 0.0 : 1.0;
+        }
+    }
+    if constexpr (MODE == 2) block_sum_store<4>(part, A.partials + (size_t)blockIdx.x * kPartialSlots);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_ingest(long M, const T* __restrict__ ch,
+                                                const T* __restrict__ cl, T i0h, T i0l, T* mh,
+                                                T* ml, T* wh, T* wl) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    const T h = ch[i], l = cl[i];
+    mh[i] = log(i0h / fmax(h, T(1)));
+    ml[i] = log(i0l / fmax(l, T(1)));
+    wh[i] = h / i0h;
+    wl[i] = l / i0l;
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_udm(const dect_plan* p, int mode, const UdmArgs<T>& a, hipStream_t s) {
+    dim3 g((unsigned)((a.M + 255) / 256));
+    const T* spec = static_cast<const T*>(p->spec);
+    ProfScope ps(mode == 1 ? "udm_init" : "udm", s);
+    if (mode == 0)
+        hipLaunchKernelGGL((k_udm<T, 0>), g, dim3(256), 0, s, a, spec, p->kmax, p->kh, p->kl);
+    else if (mode == 1)
+        hipLaunchKernelGGL((k_udm<T, 1>), g, dim3(256), 0, s, a, spec, p->kmax, p->kh, p->kl);
+    else
+        hipLaunchKernelGGL((k_udm<T, 2>), g, dim3(256), 0, s, a, spec, p->kmax, p->kh, p->kl);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_ingest(const dect_plan* p, const void* ch, const void* cl, double i0h,
+                         double i0l, void* mh, void* ml, void* wh, void* wl, hipStream_t s) {
+    dim3 g((unsigned)((p->M + 255) / 256));
+    hipLaunchKernelGGL((k_ingest<T>), g, dim3(256), 0, s, p->M, static_cast<const T*>(ch),
+                       static_cast<const T*>(cl), (T)i0h, (T)i0l, static_cast<T*>(mh),
+                       static_cast<T*>(ml), static_cast<T*>(wh), static_cast<T*>(wl));
+    return hipGetLastError();
+}
+
+template hipError_t launch_udm<float>(const dect_plan*, int, const UdmArgs<float>&, hipStream_t);
+template hipError_t launch_udm<double>(const dect_plan*, int, const UdmArgs<double>&, hipStream_t);
+template hipError_t launch_ingest<float>(const dect_plan*, const void*, const void*, double, double,
+                                         void*, void*, void*, void*, hipStream_t);
+template hipError_t launch_ingest<double>(const dect_plan*, const void*, const void*, double,
+                                          double, void*, void*, void*, void*, hipStream_t);
+
+}  // namespace dect

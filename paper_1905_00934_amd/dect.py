@@ -1,0 +1,319 @@
+"""Python binding of libdect.so: argument marshalling only.
+
+Device memory comes from torch tensors (their data_ptr()), the stream is
+torch's current HIP stream.  Every computation runs in the library's HIP
+kernels; if the library is missing this module raises instead of falling back.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libdect.so")
+
+DECT_OK, DECT_NOT_READY = 0, 1
+STATUS = {-1: "DECT_E_ARG", -2: "DECT_E_SHAPE", -3: "DECT_E_NOMEM", -4: "DECT_E_DEVICE",
+          -5: "DECT_E_NONFINITE", -6: "DECT_E_CAPACITY"}
+F32, F64 = 0, 1
+RHO_FIXED, RHO_ADAPTIVE, RHO_SCHEDULE = 0, 1, 2
+
+
+class DectError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int),
+                ("pixel_cm", ctypes.c_double), ("n_views", ctypes.c_int),
+                ("n_det", ctypes.c_int), ("det_cm", ctypes.c_double),
+                ("det_offset", ctypes.c_double), ("src_iso_cm", ctypes.c_double),
+                ("src_det_cm", ctypes.c_double), ("angle0", ctypes.c_double),
+                ("span", ctypes.c_double)]
+
+
+class Spectra(ctypes.Structure):
+    _fields_ = [("n_bins", ctypes.c_int)] + [
+        (k, ctypes.POINTER(ctypes.c_double))
+        for k in ("energy_kev", "s_high", "s_low", "f_kn", "f_p")]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("lambda_c", ctypes.c_double), ("lambda_p", ctypes.c_double),
+                ("rho_c", ctypes.c_double), ("rho_p", ctypes.c_double),
+                ("lm_iters", ctypes.c_int), ("cg_iters", ctypes.c_int),
+                ("rho_mode", ctypes.c_int), ("bal_mu", ctypes.c_double),
+                ("bal_tau", ctypes.c_double), ("lm_mu0", ctypes.c_double),
+                ("rho_schedule", ctypes.POINTER(ctypes.c_double)),
+                ("rho_schedule_len", ctypes.c_int)]
+
+
+class IterLog(ctypes.Structure):
+    _fields_ = [("iter", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("rho", ctypes.c_double * 2), ("r_primal", ctypes.c_double * 2),
+                ("s_dual", ctypes.c_double * 2), ("data_cost", ctypes.c_double),
+                ("tv_cost", ctypes.c_double)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("n_pixels", "n_rays", "samples", "taps")]
+
+
+class KernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("total_ms", ctypes.c_double),
+                ("launches", ctypes.c_int32)]
+
+
+class Layout(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_size_t) for k in
+                ("bytes", "x", "y", "uy", "z", "uz", "a", "ua", "Rx", "scalars")]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "paper_1905_00934_amd/build.py (no CPU fallback exists)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+        sig = {
+            "dect_plan_create": [ctypes.POINTER(Geometry), ctypes.POINTER(Spectra), i,
+                                 ctypes.POINTER(vp)],
+            "dect_plan_destroy": [vp],
+            "dect_project": [vp, vp, vp, i, vp],
+            "dect_backproject": [vp, vp, vp, i, vp],
+            "dect_decompose_rays": [vp, vp, vp, vp, vp, vp, d, d, i, vp, vp, vp],
+            "dect_ingest_counts": [vp, vp, vp, d, d, vp, vp, vp, vp, vp],
+            "dect_state_bytes": [vp],
+            "dect_plan_get_info": [vp, ctypes.POINTER(PlanInfo)],
+            "dect_profile_start": [],
+            "dect_profile_stop": [ctypes.POINTER(KernelTime), i, ctypes.POINTER(i)],
+            "dect_state_layout": [vp, ctypes.POINTER(Layout)],
+            "dect_admm_init": [vp, vp, vp, vp, vp, vp, ctypes.POINTER(Params), vp],
+            "dect_admm_iterate": [vp, vp, vp, vp, vp, vp, ctypes.POINTER(Params), i,
+                                  ctypes.POINTER(IterLog), vp],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+        L.dect_plan_destroy.restype = None
+        L.dect_state_bytes.restype = ctypes.c_size_t
+        L.dect_last_error.restype = ctypes.c_char_p
+        L.dect_last_error.argtypes = []
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != DECT_OK:
+        raise DectError(status, lib().dect_last_error().decode())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def profile_start():
+    _check(lib().dect_profile_start())
+
+
+def profile_stop() -> dict:
+    """{kernel name: (total ms, launches)} of the launches since profile_start()."""
+    buf = (KernelTime * 64)()
+    n = ctypes.c_int()
+    _check(lib().dect_profile_stop(buf, 64, ctypes.byref(n)))
+    return {buf[k].name.decode(): (buf[k].total_ms, buf[k].launches) for k in range(min(n.value, 64))}
+
+
+def make_geometry(g: dict) -> Geometry:
+    G = Geometry()
+    G.kind = 0 if g["kind"] == "parallel" else 1
+    for k in ("nx", "ny", "n_views", "n_det"):
+        setattr(G, k, int(g[k]))
+    G.pixel_cm = g["pixel_cm"]
+    G.det_cm = g["det_cm"]
+    G.det_offset = g.get("det_offset", 0.0)
+    G.src_iso_cm = g.get("src_iso_cm", 0.0)
+    G.src_det_cm = g.get("src_det_cm", 0.0)
+    G.angle0 = g.get("angle0", 0.0)
+    G.span = g["span"]
+    return G
+
+
+@dataclass
+class AdmmParams:
+    lam: tuple = (1e-5, 1e-5)
+    rho0: tuple = (1e-3, 1e-3)
+    lm_iters: int = 1
+    cg_iters: int = 1
+    rho_mode: int = RHO_ADAPTIVE
+    bal_mu: float = 10.0
+    bal_tau: float = 2.0
+    lm_mu0: float = 1e-3
+    rho_schedule: object = None   # sequence of (rho_c, rho_p) per iteration
+
+    def c_struct(self):
+        P = Params()
+        P.lambda_c, P.lambda_p = self.lam
+        P.rho_c, P.rho_p = self.rho0
+        P.lm_iters, P.cg_iters, P.rho_mode = self.lm_iters, self.cg_iters, self.rho_mode
+        P.bal_mu, P.bal_tau, P.lm_mu0 = self.bal_mu, self.bal_tau, self.lm_mu0
+        keep = None
+        if self.rho_schedule is not None:
+            flat = [float(v) for pair in self.rho_schedule for v in pair]
+            keep = (ctypes.c_double * len(flat))(*flat)
+            P.rho_schedule = keep
+            P.rho_schedule_len = len(flat) // 2
+        return P, keep
+
+
+class State:
+    """One slice's ADMM state: a single device buffer plus typed views into it."""
+
+    def __init__(self, plan: "Plan"):
+        L = Layout()
+        _check(lib().dect_state_layout(plan.handle, ctypes.byref(L)))
+        self.layout = L
+        self.buf = torch.empty(L.bytes + 256, dtype=torch.uint8, device=plan.device)
+        off = (-self.buf.data_ptr()) % 256
+        self.buf = self.buf[off:off + L.bytes]
+        self.plan = plan
+        ny, nx, V, D = plan.ny, plan.nx, plan.V, plan.D
+
+        def view(o, shape):
+            n = 1
+            for s in shape:
+                n *= s
+            return self.buf[o:o + n * plan.elem].view(plan.dtype).view(*shape)
+
+        self.x = view(L.x, (ny, nx, 2))
+        self.y = view(L.y, (ny, nx, 4))
+        self.uy = view(L.uy, (ny, nx, 4))
+        self.z = view(L.z, (ny, nx, 2))
+        self.uz = view(L.uz, (ny, nx, 2))
+        self.a = view(L.a, (V, D, 2))
+        self.ua = view(L.ua, (V, D, 2))
+        self.Rx = view(L.Rx, (V, D, 2))
+        self.scalars = self.buf[L.scalars:L.scalars + 24 * 8].view(torch.float64)
+
+    @property
+    def ptr(self):
+        return ctypes.c_void_p(self.buf.data_ptr())
+
+
+class Plan:
+    """Geometry, spectra and precision, with the library's device tables."""
+
+    def __init__(self, geom: dict, spec, dtype=torch.float32, device="cuda"):
+        self.geom = dict(geom)
+        self.dtype = dtype
+        self.elem = 4 if dtype == torch.float32 else 8
+        self.device = torch.device(device)
+        self.nx, self.ny = int(geom["nx"]), int(geom["ny"])
+        self.V, self.D = int(geom["n_views"]), int(geom["n_det"])
+        G = make_geometry(geom)
+        import numpy as np
+        self._spec_arrays = [np.ascontiguousarray(a, dtype=np.float64) for a in
+                             (spec.energy_kev, spec.s_high, spec.s_low, spec.f_kn, spec.f_p)]
+        S = Spectra()
+        S.n_bins = int(self._spec_arrays[0].size)
+        for name, arr in zip(("energy_kev", "s_high", "s_low", "f_kn", "f_p"), self._spec_arrays):
+            setattr(S, name, arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().dect_plan_create(ctypes.byref(G), ctypes.byref(S),
+                                          F32 if dtype == torch.float32 else F64,
+                                          ctypes.byref(h)))
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            _lib.dect_plan_destroy(h)
+            self.handle = None
+
+    def _t(self, shape):
+        return torch.empty(shape, dtype=self.dtype, device=self.device)
+
+    def _chk(self, t, shape, name):
+        if t.dtype != self.dtype or tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name}: expected {self.dtype} {tuple(shape)}, "
+                             f"got {t.dtype} {tuple(t.shape)}")
+
+    def project(self, img: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        ch = 1 if img.dim() == 2 else img.shape[-1]
+        self._chk(img, (self.ny, self.nx) + ((ch,) if img.dim() == 3 else ()), "img")
+        out = self._t((self.V, self.D) + ((ch,) if img.dim() == 3 else ())) if out is None else out
+        _check(lib().dect_project(self.handle, _ptr(img), _ptr(out), ch, _stream()))
+        return out
+
+    def backproject(self, sino: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        ch = 1 if sino.dim() == 2 else sino.shape[-1]
+        self._chk(sino, (self.V, self.D) + ((ch,) if sino.dim() == 3 else ()), "sino")
+        out = self._t((self.ny, self.nx) + ((ch,) if sino.dim() == 3 else ())) if out is None else out
+        _check(lib().dect_backproject(self.handle, _ptr(sino), _ptr(out), ch, _stream()))
+        return out
+
+    def decompose_rays(self, m_h, m_l, w_h, w_l, a, v=None, rho=(0.0, 0.0), lm_iters=1,
+                       cost=None):
+        for t, n in ((m_h, "m_h"), (m_l, "m_l"), (w_h, "w_h"), (w_l, "w_l")):
+            self._chk(t, (self.V, self.D), n)
+        self._chk(a, (self.V, self.D, 2), "a")
+        if v is not None:
+            self._chk(v, (self.V, self.D, 2), "v")
+        _check(lib().dect_decompose_rays(self.handle, _ptr(m_h), _ptr(m_l), _ptr(w_h),
+                                         _ptr(w_l), _ptr(v), float(rho[0]), float(rho[1]),
+                                         int(lm_iters), _ptr(a), _ptr(cost), _stream()))
+        return a
+
+    def ingest(self, counts_h, counts_l, i0_h, i0_l=None):
+        i0_l = i0_h if i0_l is None else i0_l
+        outs = [self._t((self.V, self.D)) for _ in range(4)]
+        _check(lib().dect_ingest_counts(self.handle, _ptr(counts_h), _ptr(counts_l),
+                                        float(i0_h), float(i0_l), *(_ptr(o) for o in outs),
+                                        _stream()))
+        return tuple(outs)
+
+    def info(self) -> dict:
+        I = PlanInfo()
+        _check(lib().dect_plan_get_info(self.handle, ctypes.byref(I)))
+        return dict(n_pixels=I.n_pixels, n_rays=I.n_rays, samples=I.samples, taps=I.taps)
+
+    def new_state(self) -> State:
+        return State(self)
+
+    def admm_init(self, meas, state: State, params: AdmmParams):
+        P, keep = params.c_struct()
+        _check(lib().dect_admm_init(self.handle, *(_ptr(m) for m in meas), state.ptr,
+                                    ctypes.byref(P), _stream()))
+
+    def admm_iterate(self, meas, state: State, params: AdmmParams, n_iters: int,
+                     log: bool = False):
+        P, keep = params.c_struct()
+        L = (IterLog * max(n_iters, 1))() if log else None
+        _check(lib().dect_admm_iterate(self.handle, *(_ptr(m) for m in meas), state.ptr,
+                                       ctypes.byref(P), int(n_iters), L, _stream()))
+        if not log:
+            return None
+        return [dict(iter=e.iter, flags=e.flags, rho=tuple(e.rho), r=tuple(e.r_primal),
+                     s=tuple(e.s_dual), data=e.data_cost, tv=e.tv_cost) for e in L[:n_iters]]
