@@ -70,14 +70,15 @@ __global__ __launch_bounds__(256) void k_cg_step(long N, T* __restrict__ x, cons
 
 // R x += alpha R p (tracking, so no extra projection of x is needed).
 template <typename T>
-__global__ __launch_bounds__(256) void k_rx_step(long M, T* __restrict__ Rx,
-                                                 const T* __restrict__ Rp,
+__global__ __launch_bounds__(256) void k_rx_step(long M, int sym, int Vb, int D,
+                                                 T* __restrict__ Rx, const T* __restrict__ Rp,
                                                  const double* __restrict__ scal) {
     using V2 = vec<T, 2>;
-    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= M) return;
+    const long l = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= M) return;
+    const long i = std_ray(l, sym, Vb, D);
     V2 a = reinterpret_cast<V2*>(Rx)[i];
-    const V2 b = reinterpret_cast<const V2*>(Rp)[i];
+    const V2 b = reinterpret_cast<const V2*>(Rp)[l];
     a.v[0] += (T)scal[S_ALPHA] * b.v[0];
     a.v[1] += (T)scal[S_ALPHA + 1] * b.v[1];
     reinterpret_cast<V2*>(Rx)[i] = a;
@@ -173,8 +174,9 @@ __global__ __launch_bounds__(256) void k_tv_dual(int nx, int ny, const T* __rest
 
 // Scaled duals follow rho: u *= rho_old / rho_new, and t = a + u^a - R x again.
 template <typename T>
-__global__ __launch_bounds__(256) void k_rescale(long M, long N, T* __restrict__ ua,
-                                                 T* __restrict__ t, const T* __restrict__ a,
+__global__ __launch_bounds__(256) void k_rescale(long M, long N, int sym, int Vb, int D,
+                                                 T* __restrict__ ua, T* __restrict__ t,
+                                                 const T* __restrict__ a,
                                                  const T* __restrict__ Rx, T* __restrict__ uy,
                                                  T* __restrict__ uz,
                                                  const double* __restrict__ scal) {
@@ -185,16 +187,17 @@ __global__ __launch_bounds__(256) void k_rescale(long M, long N, T* __restrict__
     const T kc[2] = {(T)k0, (T)k1};
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < M) {
-        V2 u = reinterpret_cast<V2*>(ua)[i];
-        const V2 av = reinterpret_cast<const V2*>(a)[i];
-        const V2 rv = reinterpret_cast<const V2*>(Rx)[i];
+        const long si = std_ray(i, sym, Vb, D);
+        V2 u = reinterpret_cast<V2*>(ua)[si];
+        const V2 av = reinterpret_cast<const V2*>(a)[si];
+        const V2 rv = reinterpret_cast<const V2*>(Rx)[si];
         V2 tv;
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
             u.v[c] *= kc[c];
             tv.v[c] = av.v[c] + u.v[c] - rv.v[c];
         }
-        reinterpret_cast<V2*>(ua)[i] = u;
+        reinterpret_cast<V2*>(ua)[si] = u;
         reinterpret_cast<V2*>(t)[i] = tv;
     }
     if (i < N) {
@@ -336,7 +339,8 @@ dect_status iterate_T(const dect_plan* p, const void* mh, const void* ml, const 
     T* Rx = at<T>(st, L.Rx);
     double* scal = at<double>(st, L.scalars);
     T* pp = at<T>(st, p->off_p);
-    T* pT = at<T>(st, p->off_pT);
+    T* pO = at<T>(st, p->off_pO);
+    T* pOT = at<T>(st, p->off_pOT);
     T* r = at<T>(st, p->off_r);
     T* q = at<T>(st, p->off_q);
     T* dy = at<T>(st, p->off_dy);
@@ -400,7 +404,7 @@ dect_status iterate_T(const dect_plan* p, const void* mh, const void* ml, const 
         DECT_OK_OR(launch_backproject<T>(p, 2, EPI_RHS, b, s));
         DECT_OK_OR(reduce(RED_GAMMA, it));
         for (int c = 0; c < n; ++c) {
-            DECT_OK_OR(launch_project_pair<T>(p, pp, pT, Rp, s));
+            DECT_OK_OR(launch_project_pair<T>(p, pp, pO, pOT, Rp, s));
             BpArgs<T> bq{};
             bq.sino = Rp;
             bq.out = n > 1 ? q : nullptr;
@@ -410,8 +414,8 @@ dect_status iterate_T(const dect_plan* p, const void* mh, const void* ml, const 
             DECT_OK_OR(reduce(RED_ALPHA, it));
             if (c < n - 1) {
                 ProfScope ps("cg_vector", s);
-                hipLaunchKernelGGL((k_rx_step<T>), dim3(nblk(p->M)), dim3(256), 0, s, p->M, Rx,
-                                   Rp, scal);
+                hipLaunchKernelGGL((k_rx_step<T>), dim3(nblk(p->M)), dim3(256), 0, s, p->M,
+                                   p->sym, p->Vb, p->D, Rx, Rp, scal);
                 hipLaunchKernelGGL((k_cg_step<T, true>), dim3(nblk(p->N)), dim3(256), 0, s,
                                    p->N, x, pp, r, q, scal, P.img);
                 DECT_OK_OR(reduce(RED_BETA, it));
@@ -427,6 +431,9 @@ dect_status iterate_T(const dect_plan* p, const void* mh, const void* ml, const 
         // a-update (Eq. (13)) fused with R x += alpha R p, u^a and the next t.
         UdmArgs<T> u{};
         u.M = p->M;
+        u.sym = p->sym;
+        u.Vb = p->Vb;
+        u.D = p->D;
         u.mh = static_cast<const T*>(mh);
         u.ml = static_cast<const T*>(ml);
         u.wh = static_cast<const T*>(wh);
@@ -460,8 +467,8 @@ dect_status iterate_T(const dect_plan* p, const void* mh, const void* ml, const 
         if (prm->rho_mode != DECT_RHO_FIXED) {
             const long nmax = p->M > p->N ? p->M : p->N;
             ProfScope ps("rescale", s);
-            hipLaunchKernelGGL((k_rescale<T>), dim3(nblk(nmax)), dim3(256), 0, s, p->M, p->N, ua,
-                               t, a, Rx, uy, uz, scal);
+            hipLaunchKernelGGL((k_rescale<T>), dim3(nblk(nmax)), dim3(256), 0, s, p->M, p->N,
+                               p->sym, p->Vb, p->D, ua, t, a, Rx, uy, uz, scal);
             DECT_OK_OR(hipGetLastError());
         }
     }
@@ -502,6 +509,9 @@ dect_status init_T(const dect_plan* p, const void* mh, const void* ml, const voi
                        prm->rho_c, prm->rho_p, prm->lambda_c, prm->lambda_p);
     UdmArgs<T> u{};
     u.M = p->M;
+    u.sym = p->sym;
+    u.Vb = p->Vb;
+    u.D = p->D;
     u.mh = static_cast<const T*>(mh);
     u.ml = static_cast<const T*>(ml);
     u.wh = static_cast<const T*>(wh);
@@ -588,6 +598,9 @@ dect_status dect_decompose_rays(const dect_plan* p, const void* m_h, const void*
     if (p->dtype == DECT_F32) {
         UdmArgs<float> u{};
         u.M = p->M;
+        u.sym = 1;
+        u.Vb = p->V;
+        u.D = p->D;
         u.mh = static_cast<const float*>(m_h);
         u.ml = static_cast<const float*>(m_l);
         u.wh = static_cast<const float*>(w_h);
@@ -603,6 +616,9 @@ dect_status dect_decompose_rays(const dect_plan* p, const void* m_h, const void*
     } else {
         UdmArgs<double> u{};
         u.M = p->M;
+        u.sym = 1;
+        u.Vb = p->V;
+        u.D = p->D;
         u.mh = static_cast<const double*>(m_h);
         u.ml = static_cast<const double*>(m_l);
         u.wh = static_cast<const double*>(w_h);

@@ -82,22 +82,39 @@ struct dect_plan {
     size_t elem;            // bytes per scalar
     int nx, ny, V, D;
     long N, M;              // pixels, rays
+    // Rotational symmetry order (4: views v + k V/4 are quarter turns of base
+    // view v; 1: none) and the number of base views Vb = V / sym.
+    int sym = 1, Vb = 0;
+    double margin = 0.05;   // footprint margin of the transpose, in bins
     // device tables
-    void* rays = nullptr;   // RayParam<T>[M]
-    void* views = nullptr;  // ViewParam<T>[V]
+    void* rays = nullptr;   // RayParam<T>[Vb * D]
+    void* views = nullptr;  // ViewParam<T>[Vb]
     void* spec = nullptr;   // T[6 * Kmax]: lw_h, kc_h, kp_h, lw_l, kc_l, kp_l
     int kh = 0, kl = 0, kmax = 0;
     double mean_f[2][2];    // spectrum-mean (f_KN, f_p) per spectrum (h, l)
-    // plan-owned scratch: a transposed copy of the image being projected
-    void* scratch_imgT = nullptr;  // T[N * 4]
+    // plan-owned scratch: orbit images of the image being projected (up to 4 channels)
+    void* scratch_O = nullptr;   // T[N * 4 * sym]
+    void* scratch_OT = nullptr;  // T[N * 4 * sym]
     // state layout (bytes)
     dect_layout layout;
-    size_t off_p, off_pT, off_r, off_q, off_dy, off_dz, off_Rp, off_t, off_da, off_partials,
-        off_log;
+    size_t off_p, off_pO, off_pOT, off_r, off_q, off_dy, off_dz, off_Rp, off_t, off_da,
+        off_partials, off_log;
     int nb_sino, nb_img, nb_tiles;  // block counts of the reducing kernels
 };
 
 namespace dect {
+
+// Workgroups of the transposed projector (8x8 pixel orbits each).
+int bp_blocks(const dect_plan* p);
+
+// Standard sinogram index of internal (quad-interleaved when sym = 4) index l:
+// internal order is [Vb][D][sym], standard order [V][D] with view vb + k Vb.
+__host__ __device__ inline long std_ray(long l, int sym, int Vb, int D) {
+    if (sym == 1) return l;
+    const long base = l / sym;
+    const int k = (int)(l % sym);
+    return ((base / D) + (long)k * Vb) * D + base % D;
+}
 
 constexpr int kLogCap = 256;      // iterations kept in the device log ring
 constexpr int kLogStride = 12;    // doubles per log entry

@@ -17,7 +17,8 @@ template <typename T>
 struct BpArgs {
     const RayParam<T>* rays;
     const ViewParam<T>* views;
-    int nx, ny, V, D;
+    int nx, ny, V, Vb, D;
+    double margin;
     const T* sino;
     T* out;
     T* out2;
@@ -49,9 +50,11 @@ __device__ inline void block_sum_store(double (&v)[K], double* out) {
 
 template <typename T>
 hipError_t launch_project(const dect_plan* p, const void* img, void* sino, int ch, hipStream_t s);
+// Two-channel projection of the ADMM direction into quad-interleaved records;
+// O and OT are orbit-image scratch of N * 2 * sym elements each.
 template <typename T>
-hipError_t launch_project_pair(const dect_plan* p, const void* img, void* imgT, void* sino,
-                               hipStream_t s);
+hipError_t launch_project_pair(const dect_plan* p, const void* img, void* O, void* OT,
+                               void* sino, hipStream_t s);
 template <typename T>
 hipError_t launch_backproject(const dect_plan* p, int ch, int epi, const BpArgs<T>& a,
                               hipStream_t s);
@@ -60,6 +63,7 @@ hipError_t launch_backproject(const dect_plan* p, int ch, int epi, const BpArgs<
 template <typename T>
 struct UdmArgs {
     long M;
+    int sym, Vb, D;  // internal (quad) ray order of t, da, Rp; sym = 1: standard order
     const T* mh;
     const T* ml;
     const T* wh;

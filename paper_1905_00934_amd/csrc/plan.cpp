@@ -85,7 +85,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 template <typename T>
 dect_status build_tables(dect_plan* p, const dect_spectra* spec) {
     const dect_geometry& g = p->geom;
-    const int V = p->V, D = p->D;
+    const int V = p->Vb, D = p->D;  // base views only; the others are their rotations
     std::vector<RayParam<T>> rays((size_t)V * D);
     std::vector<ViewParam<T>> views(V);
     const double d = g.pixel_cm;
@@ -172,7 +172,8 @@ dect_status build_tables(dect_plan* p, const dect_spectra* spec) {
                 packed[(size_t)(3 * h + q) * p->kmax + k] = tab[h][q][k];
     st = upload<T>(packed.data(), packed.size() * sizeof(T), &p->spec);
     if (st) return st;
-    DECT_HIP(hipMalloc(&p->scratch_imgT, (size_t)p->N * 4 * sizeof(T)));
+    DECT_HIP(hipMalloc(&p->scratch_O, (size_t)p->N * 4 * p->sym * sizeof(T)));
+    DECT_HIP(hipMalloc(&p->scratch_OT, (size_t)p->N * 4 * p->sym * sizeof(T)));
     return DECT_OK;
 }
 
@@ -196,7 +197,8 @@ void make_layout(dect_plan* p) {
     L.Rx = take(M * 2 * e);
     L.scalars = take(S_COUNT * sizeof(double));
     p->off_p = take(N * 2 * e);
-    p->off_pT = take(N * 2 * e);
+    p->off_pO = take(N * 2 * p->sym * e);
+    p->off_pOT = take(N * 2 * p->sym * e);
     p->off_r = take(N * 2 * e);
     p->off_q = take(N * 2 * e);
     p->off_dy = take(N * 4 * e);
@@ -206,7 +208,7 @@ void make_layout(dect_plan* p) {
     p->off_da = take(M * 2 * e);
     p->nb_sino = (int)((M + 255) / 256);
     p->nb_img = (int)((N + 255) / 256);
-    p->nb_tiles = ((p->nx + 15) / 16) * ((p->ny + 15) / 16);
+    p->nb_tiles = bp_blocks(p);
     p->off_partials =
         take((size_t)(p->nb_sino + p->nb_img + p->nb_tiles) * kPartialSlots * sizeof(double));
     p->off_log = take((size_t)kLogCap * kLogStride * sizeof(double));
@@ -214,6 +216,12 @@ void make_layout(dect_plan* p) {
 }
 
 }  // namespace
+
+int bp_blocks(const dect_plan* p) {
+    const int dx = p->sym == 4 ? p->nx / 2 : p->nx, dy = p->sym == 4 ? p->ny / 2 : p->ny;
+    return ((dx + 7) / 8) * ((dy + 7) / 8);
+}
+
 }  // namespace dect
 
 using namespace dect;
@@ -271,6 +279,26 @@ dect_status dect_plan_create(const dect_geometry* geom, const dect_spectra* spec
     p->D = g.n_det;
     p->N = (long)g.nx * g.ny;
     p->M = (long)g.n_views * g.n_det;
+    // Quarter-turn symmetry: fan beam over a full turn, views in multiples of 4,
+    // square image with an even side (so the pixel grid maps onto itself).
+    const double two_pi = 6.283185307179586;
+    p->sym = (g.kind == DECT_FAN && std::fabs(g.span - two_pi) < 1e-12 && g.n_views % 4 == 0 &&
+              g.nx == g.ny && g.nx % 2 == 0)
+                 ? 4
+                 : 1;
+    p->Vb = g.n_views / p->sym;
+    // Footprint margin of the transpose: the detector coordinate of the two-pixel
+    // segment around a pixel is linearised at its centre; for a fan the error is at
+    // most |d beta| * pixel / (distance to source - pixel).  Plus 0.02 bins for
+    // rounding of the tables and of the footprint itself.
+    p->margin = 0.02;
+    if (g.kind == DECT_FAN) {
+        const double rc = 0.5 * g.pixel_cm * std::hypot((double)g.nx, (double)g.ny);
+        const double dmin = g.src_iso_cm - rc - 2.0 * g.pixel_cm;
+        const double K = g.src_det_cm / g.det_cm;
+        const double dbeta = (K * g.pixel_cm + K * rc / dmin * g.pixel_cm) / dmin;
+        p->margin += 1.5 * dbeta * g.pixel_cm / (dmin - g.pixel_cm);
+    }
     if (hipGetDevice(&p->device) != hipSuccess) {
         delete p;
         return fail(DECT_E_DEVICE, "no HIP device");
@@ -290,7 +318,8 @@ void dect_plan_destroy(dect_plan* p) {
     (void)hipFree(p->rays);
     (void)hipFree(p->views);
     (void)hipFree(p->spec);
-    (void)hipFree(p->scratch_imgT);
+    (void)hipFree(p->scratch_O);
+    (void)hipFree(p->scratch_OT);
     delete p;
 }
 
@@ -300,15 +329,16 @@ dect_status dect_plan_get_info(const dect_plan* p, dect_plan_info* out) {
     info.n_pixels = p->N;
     info.n_rays = p->M;
     // Same sampling rule as the projector, in double precision.
-    for (int v = 0; v < p->V; ++v)
+    // Views beyond the base views are rotations of them: same counts.
+    for (int v = 0; v < p->Vb; ++v)
         for (int b = 0; b < p->D; ++b) {
             HostRay r = host_ray(p->geom, v, b);
             const int n_steps = r.xstep ? p->nx : p->ny, n_lines = r.xstep ? p->ny : p->nx;
             for (int k = 0; k < n_steps; ++k) {
                 const double j0 = std::floor(r.phi0 + r.slope * k);
                 const int in0 = (j0 >= 0 && j0 < n_lines), in1 = (j0 + 1 >= 0 && j0 + 1 < n_lines);
-                info.samples += (in0 | in1);
-                info.taps += in0 + in1;
+                info.samples += p->sym * (in0 | in1);
+                info.taps += p->sym * (in0 + in1);
             }
         }
     *out = info;

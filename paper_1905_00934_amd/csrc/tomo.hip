@@ -1,17 +1,27 @@
 // Joseph projector R (ray-driven) and its exact transpose R^T (pixel-driven
 // gather, no atomics), for gfx950.
 //
-// Projector: one lane per ray, a workgroup covers 256 consecutive bins of one
-// view, so sinogram writes are coalesced along the detector.  A ray that steps
-// along columns reads the transposed image [nx][ny] so that neighbouring lanes
-// (neighbouring bins) read neighbouring addresses of one image line.
+// Rotational symmetry.  For a fan beam over a full turn with n_views divisible
+// by 4 and a square image, view v + k V/4 is view v turned by k quarter turns,
+// and the pixel grid maps onto itself.  The plan then defines the rays of those
+// views as exact rotations of the V/4 base views (SYM = 4): one Joseph weight
+// computation serves four views.  Otherwise SYM = 1 and every view is a base view.
 //
-// Transpose: one lane per pixel of a 16x16 tile; for every view the lane finds
-// the bins whose Joseph samples can touch its pixel from the central projection
-// of the two-pixel segment around it, then re-evaluates each candidate's
-// interpolation weight with the projector's own fma on the same table values.
-// The weights are therefore bit-identical to the projector's, and R^T is the
-// transpose of R up to summation order.
+// Projector: one lane per base ray; a workgroup covers 256 consecutive bins of
+// one base view, so output writes are coalesced along the detector.  It reads
+// an "orbit" image O[j][i] = (X[rot^k (i, j)], k < SYM) -- the SYM rotated
+// copies interleaved per pixel -- or its transpose for x-stepped rays, so that
+// one load per tap serves all SYM views and neighbouring lanes read
+// neighbouring addresses.
+//
+// Transpose: one lane owns the rotation orbit of a pixel.  For every base view
+// and every orbit member it locates, from the central projection of the
+// two-pixel segment around the pixel, the bins whose samples can touch it, and
+// re-evaluates each candidate's interpolation weight with the projector's own
+// fma on the same table values; each weight serves SYM (pixel, view) pairs.
+// The weights are bit-identical to the projector's, so R^T is the transpose of R
+// up to summation order.  The views are split over the waves of a workgroup and
+// the wave sums are added in a fixed order through LDS.
 #include "common.h"
 #include "kernels.h"
 #include "profile.h"
@@ -20,22 +30,54 @@ namespace dect {
 
 namespace {
 
-// Extra bins scanned on each side of a pixel's analytic footprint.  Rounding of
-// the table values and of the footprint moves bin coordinates by < 1e-3 bins.
-constexpr float kFootprintMargin = 0.05f;
-
-template <typename T, int CH>
-__device__ inline void zero(vec<T, CH>& a) {
+template <typename T, int N>
+__device__ inline void vzero(vec<T, N>& a) {
 #pragma unroll
-    for (int c = 0; c < CH; ++c) a.v[c] = T(0);
+    for (int c = 0; c < N; ++c) a.v[c] = T(0);
 }
 
-template <typename T, int CH>
+// Pixel (i, j) turned by k quarter turns about the image centre (n x n image).
+__device__ inline void rot(int k, int n, int i, int j, int& io, int& jo) {
+    switch (k & 3) {
+        case 0: io = i; jo = j; break;
+        case 1: io = n - 1 - j; jo = i; break;
+        case 2: io = n - 1 - i; jo = n - 1 - j; break;
+        default: io = j; jo = n - 1 - i; break;
+    }
+}
+
+// Orbit image (TR = false: O[j][i]; TR = true: its transpose OT[i][j]) with
+// component k*CH + c = channel c of X at rot^k(i, j).  SYM = 1 gives X or X^T.
+template <typename T, int CH, int SYM, bool TR>
+__global__ __launch_bounds__(256) void k_orbit(const vec<T, CH>* __restrict__ X,
+                                               vec<T, CH * SYM>* __restrict__ out, int nx,
+                                               int ny) {
+    const int lines = TR ? nx : ny, len = TR ? ny : nx;
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)lines * len) return;
+    const int line = (int)(idx / len), pos = (int)(idx % len);
+    const int i = TR ? line : pos, j = TR ? pos : line;
+    vec<T, CH * SYM> o;
+#pragma unroll
+    for (int k = 0; k < SYM; ++k) {
+        int io, jo;
+        rot(k, nx, i, j, io, jo);
+        const vec<T, CH> x = X[(size_t)jo * nx + io];
+#pragma unroll
+        for (int c = 0; c < CH; ++c) o.v[k * CH + c] = x.v[c];
+    }
+    out[idx] = o;
+}
+
+// R for base rays: QUAD = true writes [Vb][D][SYM][CH] records, false writes the
+// standard [V][D][CH] layout (view v + k*Vb for rotation k).
+template <typename T, int CH, int SYM, bool QUAD>
 __global__ __launch_bounds__(256) void k_project(const RayParam<T>* __restrict__ rays,
-                                                 const vec<T, CH>* __restrict__ img,
-                                                 const vec<T, CH>* __restrict__ imgT,
-                                                 vec<T, CH>* __restrict__ sino, int nx, int ny,
+                                                 const vec<T, CH * SYM>* __restrict__ O,
+                                                 const vec<T, CH * SYM>* __restrict__ OT,
+                                                 T* __restrict__ sino, int nx, int ny, int Vb,
                                                  int D) {
+    constexpr int W = CH * SYM;
     const int v = blockIdx.y;
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= D) return;
@@ -43,8 +85,7 @@ __global__ __launch_bounds__(256) void k_project(const RayParam<T>* __restrict__
     const bool xs = r.pad == T(0);
     const int n_steps = xs ? nx : ny;   // samples along the ray
     const int n_lines = xs ? ny : nx;   // interpolation axis
-    const vec<T, CH>* src = xs ? imgT : img;  // [n_steps][n_lines]
-    // Samples can touch the image only where phi lies in [-1, n_lines).
+    const vec<T, W>* src = xs ? OT : O;  // [n_steps][n_lines]
     // Outside [k0, k1] both taps of every sample are outside the image, so the
     // restriction changes no term; the one-step margin absorbs rounding.
     int k0 = 0, k1 = n_steps - 1;
@@ -59,253 +100,352 @@ __global__ __launch_bounds__(256) void k_project(const RayParam<T>* __restrict__
     } else if (!(r.phi0 >= T(-1) && r.phi0 < T(n_lines))) {
         k1 = -1;
     }
-    T acc[CH];
+    T acc[W];
 #pragma unroll
-    for (int c = 0; c < CH; ++c) acc[c] = T(0);
-    for (int k = k0; k <= k1; ++k) {
-        const T phi = fma(r.slope, (T)k, r.phi0);
-        T fl = floor(phi);
-        const T al = phi - fl;
-        fl = fmin(fmax(fl, T(-2)), T(n_lines + 1));
-        const int j0 = (int)fl;
-        const vec<T, CH>* line = src + (size_t)k * n_lines;
-        vec<T, CH> a0, a1;
-        zero(a0);
-        zero(a1);
-        if ((unsigned)j0 < (unsigned)n_lines) a0 = line[j0];
-        if ((unsigned)(j0 + 1) < (unsigned)n_lines) a1 = line[j0 + 1];
+    for (int c = 0; c < W; ++c) acc[c] = T(0);
+    int k = k0;
+    // Two samples per trip so that four loads are in flight per lane.
+    for (; k + 1 <= k1; k += 2) {
+        const T pa = fma(r.slope, (T)k, r.phi0);
+        const T pb = fma(r.slope, (T)(k + 1), r.phi0);
+        T fa = floor(pa), fb = floor(pb);
+        const T aa = pa - fa, ab = pb - fb;
+        fa = fmin(fmax(fa, T(-2)), T(n_lines + 1));
+        fb = fmin(fmax(fb, T(-2)), T(n_lines + 1));
+        const int ja = (int)fa, jb = (int)fb;
+        const vec<T, W>* la = src + (size_t)k * n_lines;
+        const vec<T, W>* lb = la + n_lines;
+        vec<T, W> a0, a1, b0, b1;
+        vzero(a0); vzero(a1); vzero(b0); vzero(b1);
+        if ((unsigned)ja < (unsigned)n_lines) a0 = la[ja];
+        if ((unsigned)(ja + 1) < (unsigned)n_lines) a1 = la[ja + 1];
+        if ((unsigned)jb < (unsigned)n_lines) b0 = lb[jb];
+        if ((unsigned)(jb + 1) < (unsigned)n_lines) b1 = lb[jb + 1];
 #pragma unroll
-        for (int c = 0; c < CH; ++c) acc[c] += a0.v[c] + al * (a1.v[c] - a0.v[c]);
+        for (int c = 0; c < W; ++c)
+            acc[c] += (a0.v[c] + aa * (a1.v[c] - a0.v[c])) + (b0.v[c] + ab * (b1.v[c] - b0.v[c]));
     }
-    vec<T, CH> out;
+    if (k <= k1) {
+        const T pa = fma(r.slope, (T)k, r.phi0);
+        T fa = floor(pa);
+        const T aa = pa - fa;
+        fa = fmin(fmax(fa, T(-2)), T(n_lines + 1));
+        const int ja = (int)fa;
+        const vec<T, W>* la = src + (size_t)k * n_lines;
+        vec<T, W> a0, a1;
+        vzero(a0); vzero(a1);
+        if ((unsigned)ja < (unsigned)n_lines) a0 = la[ja];
+        if ((unsigned)(ja + 1) < (unsigned)n_lines) a1 = la[ja + 1];
 #pragma unroll
-    for (int c = 0; c < CH; ++c) out.v[c] = acc[c] * r.step;
-    sino[(size_t)v * D + b] = out;
-}
-
-// Image transpose [ny][nx] -> [nx][ny] through LDS, 32x32 tiles.
-template <typename T, int CH>
-__global__ __launch_bounds__(256) void k_transpose(const vec<T, CH>* __restrict__ in,
-                                                   vec<T, CH>* __restrict__ out, int nx, int ny) {
-    __shared__ vec<T, CH> tile[32][33];
-    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
-    const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
-    for (int r = ty; r < 32; r += 8) {
-        const int j = by + r, i = bx + tx;
-        if (j < ny && i < nx) tile[r][tx] = in[(size_t)j * nx + i];
+        for (int c = 0; c < W; ++c) acc[c] += a0.v[c] + aa * (a1.v[c] - a0.v[c]);
     }
-    __syncthreads();
-    for (int r = ty; r < 32; r += 8) {
-        const int i = bx + r, j = by + tx;
-        if (i < nx && j < ny) out[(size_t)i * ny + j] = tile[tx][r];
-    }
-}
-
-// Gather of all Joseph weights of pixel (i, j) times the sinogram.
-template <typename T, int CH>
-__device__ inline void gather_pixel(const RayParam<T>* __restrict__ rays,
-                                    const ViewParam<T>* __restrict__ views,
-                                    const vec<T, CH>* __restrict__ sino, int V, int D, int i,
-                                    int j, T ip, T jp, T (&acc)[CH]) {
-    const T fi = (T)i, fj = (T)j;
-    for (int v = 0; v < V; ++v) {
-        const ViewParam<T> w = views[v];
-        const T num = w.ni * ip + w.nj * jp;
-        const T den = w.d0 + w.di * ip + w.dj * jp;
-        const RayParam<T>* rv = rays + (size_t)v * D;
-        const vec<T, CH>* sv = sino + (size_t)v * D;
-        if (w.xb1 > w.xb0) {
-            // Column i: bins whose row coordinate lies in [j-1, j+1).
-            const T b1 = (num - w.nj) / (den - w.dj) + w.boff;
-            const T b2 = (num + w.nj) / (den + w.dj) + w.boff;
-            const T bl = (b1 < b2 ? b1 : b2) - T(kFootprintMargin);
-            const T bh = (b1 < b2 ? b2 : b1) + T(kFootprintMargin);
-            int lo = (int)ceil(fmax(bl, T(-1)));
-            int hi = (int)floor(fmin(bh, T(D)));
-            lo = lo > w.xb0 ? lo : w.xb0;
-            hi = hi < w.xb1 - 1 ? hi : w.xb1 - 1;
-            for (int b = lo; b <= hi; ++b) {
-                const RayParam<T> r = rv[b];
-                const T phi = fma(r.slope, fi, r.phi0);
-                const T fl = floor(phi);
-                const T al = phi - fl;
-                T wt = fl == fj ? T(1) - al : (fl == fj - T(1) ? al : T(0));
-                wt *= r.step;
-                const vec<T, CH> s = sv[b];
+    if constexpr (QUAD) {
+        vec<T, W> out;
 #pragma unroll
-                for (int c = 0; c < CH; ++c) acc[c] += wt * s.v[c];
-            }
-        }
-        if (w.yb1 > w.yb0) {
-            // Row j: bins whose column coordinate lies in [i-1, i+1).
-            const T b1 = (num - w.ni) / (den - w.di) + w.boff;
-            const T b2 = (num + w.ni) / (den + w.di) + w.boff;
-            const T bl = (b1 < b2 ? b1 : b2) - T(kFootprintMargin);
-            const T bh = (b1 < b2 ? b2 : b1) + T(kFootprintMargin);
-            int lo = (int)ceil(fmax(bl, T(-1)));
-            int hi = (int)floor(fmin(bh, T(D)));
-            lo = lo > w.yb0 ? lo : w.yb0;
-            hi = hi < w.yb1 - 1 ? hi : w.yb1 - 1;
-            for (int b = lo; b <= hi; ++b) {
-                const RayParam<T> r = rv[b];
-                const T phi = fma(r.slope, fj, r.phi0);
-                const T fl = floor(phi);
-                const T al = phi - fl;
-                T wt = fl == fi ? T(1) - al : (fl == fi - T(1) ? al : T(0));
-                wt *= r.step;
-                const vec<T, CH> s = sv[b];
+        for (int c = 0; c < W; ++c) out.v[c] = acc[c] * r.step;
+        reinterpret_cast<vec<T, W>*>(sino)[(size_t)v * D + b] = out;
+    } else {
 #pragma unroll
-                for (int c = 0; c < CH; ++c) acc[c] += wt * s.v[c];
-            }
+        for (int s = 0; s < SYM; ++s) {
+            vec<T, CH> out;
+#pragma unroll
+            for (int c = 0; c < CH; ++c) out.v[c] = acc[s * CH + c] * r.step;
+            reinterpret_cast<vec<T, CH>*>(sino)[(size_t)(v + s * Vb) * D + b] = out;
         }
     }
 }
 
-}  // namespace
+// Candidate bins [lo, hi] of a segment for the point at detector coordinate bc
+// whose two-pixel neighbourhood spans +-db bins (linearised, margin m).
+template <typename T>
+__device__ inline void bin_range(T bc, T db, T m, int seg0, int seg1, int D, int& lo, int& hi) {
+    const T h = fabs(db) + m;
+    const T bl = fmax(bc - h, T(-1)), bh = fmin(bc + h, T(D));
+    lo = (int)ceil(bl);
+    hi = (int)floor(bh);
+    lo = lo > seg0 ? lo : seg0;
+    hi = hi < seg1 - 1 ? hi : seg1 - 1;
+}
 
-namespace {
+// Sum over the base views of this wave (v = wave, wave + VS, ...) for the orbit
+// of pixel (i, j).  Pixel rot^k(p) seen from view v + k' Vb has the weight of
+// base view v at pixel rot^(k - k')(p), so for every orbit member p_m = rot^m(p)
+// the base-view weights are evaluated once and routed to acc[(m + k') mod SYM]
+// with sinogram row v + k' Vb, for all k'.
+template <typename T, int CH, int SYM, bool QUAD, int VS>
+__device__ inline void gather_orbit(const BpArgs<T>& a, int wave, int i, int j,
+                                    T (&acc)[SYM][CH]) {
+    const T m = (T)a.margin;
+    const int D = a.D, Vb = a.Vb;
+    const T cx = T(0.5) * (T)(a.nx - 1), cy = T(0.5) * (T)(a.ny - 1);
+    for (int v = wave; v < Vb; v += VS) {
+        const ViewParam<T> w = a.views[v];
+        const RayParam<T>* rv = a.rays + (size_t)v * D;
+#pragma unroll
+        for (int mm = 0; mm < SYM; ++mm) {
+            int im, jm;
+            rot(mm, a.nx, i, j, im, jm);
+            const T fi = (T)im, fj = (T)jm;
+            const T ip = fi - cx, jp = fj - cy;
+            const T num = w.ni * ip + w.nj * jp;
+            const T den = w.d0 + w.di * ip + w.dj * jp;
+            const T inv = T(1) / den;
+            const T bq = num * inv;
+            const T bc = bq + w.boff;
+            // d(beta) for one pixel step along y (x-stepped rays) and along x.
+            const T dby = (w.nj - bq * w.dj) * inv;
+            const T dbx = (w.ni - bq * w.di) * inv;
+            int lo, hi;
+            for (int seg = 0; seg < 2; ++seg) {
+                const bool xseg = seg == 0;
+                if (xseg) bin_range<T>(bc, dby, m, w.xb0, w.xb1, D, lo, hi);
+                else bin_range<T>(bc, dbx, m, w.yb0, w.yb1, D, lo, hi);
+                const T fs = xseg ? fi : fj;   // sampling coordinate
+                const T fp = xseg ? fj : fi;   // interpolated coordinate of the pixel
+                for (int b = lo; b <= hi; ++b) {
+                    const RayParam<T> r = rv[b];
+                    const T phi = fma(r.slope, fs, r.phi0);
+                    const T fl = floor(phi);
+                    const T al = phi - fl;
+                    T wt = fl == fp ? T(1) - al : (fl == fp - T(1) ? al : T(0));
+                    wt *= r.step;
+                    if constexpr (QUAD) {
+                        const vec<T, SYM * CH> s =
+                            reinterpret_cast<const vec<T, SYM * CH>*>(a.sino)[(size_t)v * D + b];
+#pragma unroll
+                        for (int kp = 0; kp < SYM; ++kp)
+#pragma unroll
+                            for (int c = 0; c < CH; ++c)
+                                acc[(mm + kp) % SYM][c] += wt * s.v[kp * CH + c];
+                    } else {
+#pragma unroll
+                        for (int kp = 0; kp < SYM; ++kp) {
+                            const vec<T, CH> s = reinterpret_cast<const vec<T, CH>*>(
+                                a.sino)[(size_t)(v + kp * Vb) * D + b];
+#pragma unroll
+                            for (int c = 0; c < CH; ++c) acc[(mm + kp) % SYM][c] += wt * s.v[c];
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
 
-// R^T followed by an optional image-side epilogue (basis pairs, CH = 2 except EPI_NONE).
-template <typename T, int CH, int EPI>
-__global__ __launch_bounds__(256) void k_backproject(BpArgs<T> a) {
+// Image-side terms added to R^T at pixel (i, j) for the ADMM epilogues (CH = 2).
+// Adds the per-channel partial sums of the finished values to part.
+template <typename T, int EPI>
+__device__ inline void epilogue(const BpArgs<T>& a, int i, int j, T (&res)[2], double (&part)[2]) {
     using V2 = vec<T, 2>;
     using V4 = vec<T, 4>;
-    const int i = blockIdx.x * 16 + (threadIdx.x & 15);
-    const int j = blockIdx.y * 16 + (threadIdx.x >> 4);
     const int nx = a.nx, ny = a.ny;
-    const bool inside = i < nx && j < ny;
-    T acc[CH];
-#pragma unroll
-    for (int c = 0; c < CH; ++c) acc[c] = T(0);
-    if (inside)
-        gather_pixel<T, CH>(a.rays, a.views, reinterpret_cast<const vec<T, CH>*>(a.sino), a.V,
-                            a.D, i, j, (T)i - T(0.5) * (T)(nx - 1), (T)j - T(0.5) * (T)(ny - 1),
-                            acc);
     const size_t pix = (size_t)j * nx + i;
-    if constexpr (EPI == EPI_NONE) {
-        if (inside) {
-            vec<T, CH> o;
+    const V2* x2 = reinterpret_cast<const V2*>(a.x);
+    if constexpr (EPI == EPI_RHS) {
+        // r0 = R^T t + D^T (y + u^y - D x) + (z + u^z - x), Eq. (12).
+        const V4* y4 = reinterpret_cast<const V4*>(a.y);
+        const V4* u4 = reinterpret_cast<const V4*>(a.uy);
+        const V2 xc = x2[pix];
+        const V2 z = reinterpret_cast<const V2*>(a.z)[pix];
+        const V2 uz = reinterpret_cast<const V2*>(a.uz)[pix];
+        const V4 yc = y4[pix], uc = u4[pix];
 #pragma unroll
-            for (int c = 0; c < CH; ++c) o.v[c] = acc[c];
-            reinterpret_cast<vec<T, CH>*>(a.out)[pix] = o;
+        for (int c = 0; c < 2; ++c) res[c] += z.v[c] + uz.v[c] - xc.v[c];
+        if (i < nx - 1) {
+            const V2 xr = x2[pix + 1];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) res[c] -= yc.v[c] + uc.v[c] - (xr.v[c] - xc.v[c]);
         }
-    } else {
-        double part[2] = {0.0, 0.0};
-        if (inside) {
-            T res[2] = {acc[0], acc[1]};
-            const V2* x2 = reinterpret_cast<const V2*>(a.x);
-            auto X = [&](int jj, int ii) { return x2[(size_t)jj * nx + ii]; };
-            if constexpr (EPI == EPI_RHS) {
-                // r0 = R^T t + D^T (y + u^y - D x) + (z + u^z - x), Eq. (12).
-                const V4* y4 = reinterpret_cast<const V4*>(a.y);
-                const V4* u4 = reinterpret_cast<const V4*>(a.uy);
-                const V2 xc = X(j, i);
-                const V2 z = reinterpret_cast<const V2*>(a.z)[pix];
-                const V2 uz = reinterpret_cast<const V2*>(a.uz)[pix];
-                const V4 yc = y4[pix], uc = u4[pix];
+        if (i > 0) {
+            const V2 xl = x2[pix - 1];
+            const V4 yl = y4[pix - 1], ul = u4[pix - 1];
 #pragma unroll
-                for (int c = 0; c < 2; ++c) res[c] += z.v[c] + uz.v[c] - xc.v[c];
-                if (i < nx - 1) {  // -W_h(j, i)
-                    const V2 xr = X(j, i + 1);
-#pragma unroll
-                    for (int c = 0; c < 2; ++c)
-                        res[c] -= yc.v[c] + uc.v[c] - (xr.v[c] - xc.v[c]);
-                }
-                if (i > 0) {  // +W_h(j, i-1)
-                    const V2 xl = X(j, i - 1);
-                    const V4 yl = y4[pix - 1], ul = u4[pix - 1];
-#pragma unroll
-                    for (int c = 0; c < 2; ++c)
-                        res[c] += yl.v[c] + ul.v[c] - (xc.v[c] - xl.v[c]);
-                }
-                if (j < ny - 1) {  // -W_v(j, i)
-                    const V2 xd = X(j + 1, i);
-#pragma unroll
-                    for (int c = 0; c < 2; ++c)
-                        res[c] -= yc.v[2 + c] + uc.v[2 + c] - (xd.v[c] - xc.v[c]);
-                }
-                if (j > 0) {  // +W_v(j-1, i)
-                    const V2 xu = X(j - 1, i);
-                    const V4 yu = y4[pix - nx], uu = u4[pix - nx];
-#pragma unroll
-                    for (int c = 0; c < 2; ++c)
-                        res[c] += yu.v[2 + c] + uu.v[2 + c] - (xc.v[c] - xu.v[c]);
-                }
-                V2 o;
-                o.v[0] = res[0];
-                o.v[1] = res[1];
-                reinterpret_cast<V2*>(a.out)[pix] = o;
-                if (a.out2) reinterpret_cast<V2*>(a.out2)[pix] = o;
-                part[0] = (double)res[0] * (double)res[0];
-                part[1] = (double)res[1] * (double)res[1];
-            } else if constexpr (EPI == EPI_Q) {
-                // q = R^T R p + D^T D p + p; a.x holds p.
-                const V2 pc = X(j, i);
-#pragma unroll
-                for (int c = 0; c < 2; ++c) res[c] += pc.v[c];
-                if (i < nx - 1) { const V2 q = X(j, i + 1); for (int c = 0; c < 2; ++c) res[c] += pc.v[c] - q.v[c]; }
-                if (i > 0) { const V2 q = X(j, i - 1); for (int c = 0; c < 2; ++c) res[c] += pc.v[c] - q.v[c]; }
-                if (j < ny - 1) { const V2 q = X(j + 1, i); for (int c = 0; c < 2; ++c) res[c] += pc.v[c] - q.v[c]; }
-                if (j > 0) { const V2 q = X(j - 1, i); for (int c = 0; c < 2; ++c) res[c] += pc.v[c] - q.v[c]; }
-                if (a.out) {
-                    V2 o;
-                    o.v[0] = res[0];
-                    o.v[1] = res[1];
-                    reinterpret_cast<V2*>(a.out)[pix] = o;
-                }
-                part[0] = (double)pc.v[0] * (double)res[0];
-                part[1] = (double)pc.v[1] * (double)res[1];
-            } else {  // EPI_DUAL: s = R^T da + D^T dy + dz
-                const V4* d4 = reinterpret_cast<const V4*>(a.y);
-                const V4 dc = d4[pix];
-                const V2 dz = reinterpret_cast<const V2*>(a.z)[pix];
-#pragma unroll
-                for (int c = 0; c < 2; ++c) res[c] += dz.v[c];
-                if (i < nx - 1) for (int c = 0; c < 2; ++c) res[c] -= dc.v[c];
-                if (i > 0) { const V4 dl = d4[pix - 1]; for (int c = 0; c < 2; ++c) res[c] += dl.v[c]; }
-                if (j < ny - 1) for (int c = 0; c < 2; ++c) res[c] -= dc.v[2 + c];
-                if (j > 0) { const V4 du = d4[pix - nx]; for (int c = 0; c < 2; ++c) res[c] += du.v[2 + c]; }
-                part[0] = (double)res[0] * (double)res[0];
-                part[1] = (double)res[1] * (double)res[1];
-            }
+            for (int c = 0; c < 2; ++c) res[c] += yl.v[c] + ul.v[c] - (xc.v[c] - xl.v[c]);
         }
-        double p4[2] = {part[0], part[1]};
-        block_sum_store<2>(p4, a.partials + (size_t)(blockIdx.y * gridDim.x + blockIdx.x) * kPartialSlots);
+        if (j < ny - 1) {
+            const V2 xd = x2[pix + nx];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) res[c] -= yc.v[2 + c] + uc.v[2 + c] - (xd.v[c] - xc.v[c]);
+        }
+        if (j > 0) {
+            const V2 xu = x2[pix - nx];
+            const V4 yu = y4[pix - nx], uu = u4[pix - nx];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) res[c] += yu.v[2 + c] + uu.v[2 + c] - (xc.v[c] - xu.v[c]);
+        }
+        V2 o;
+        o.v[0] = res[0];
+        o.v[1] = res[1];
+        reinterpret_cast<V2*>(a.out)[pix] = o;
+        if (a.out2) reinterpret_cast<V2*>(a.out2)[pix] = o;
+        part[0] += (double)res[0] * (double)res[0];
+        part[1] += (double)res[1] * (double)res[1];
+    } else if constexpr (EPI == EPI_Q) {
+        // q = R^T R p + D^T D p + p; a.x holds p.
+        const V2 pc = x2[pix];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) res[c] += pc.v[c];
+        if (i < nx - 1) { const V2 q = x2[pix + 1]; for (int c = 0; c < 2; ++c) res[c] += pc.v[c] - q.v[c]; }
+        if (i > 0) { const V2 q = x2[pix - 1]; for (int c = 0; c < 2; ++c) res[c] += pc.v[c] - q.v[c]; }
+        if (j < ny - 1) { const V2 q = x2[pix + nx]; for (int c = 0; c < 2; ++c) res[c] += pc.v[c] - q.v[c]; }
+        if (j > 0) { const V2 q = x2[pix - nx]; for (int c = 0; c < 2; ++c) res[c] += pc.v[c] - q.v[c]; }
+        if (a.out) {
+            V2 o;
+            o.v[0] = res[0];
+            o.v[1] = res[1];
+            reinterpret_cast<V2*>(a.out)[pix] = o;
+        }
+        part[0] += (double)pc.v[0] * (double)res[0];
+        part[1] += (double)pc.v[1] * (double)res[1];
+    } else {  // EPI_DUAL: s = R^T da + D^T dy + dz
+        const V4* d4 = reinterpret_cast<const V4*>(a.y);
+        const V4 dc = d4[pix];
+        const V2 dz = reinterpret_cast<const V2*>(a.z)[pix];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) res[c] += dz.v[c];
+        if (i < nx - 1) for (int c = 0; c < 2; ++c) res[c] -= dc.v[c];
+        if (i > 0) { const V4 dl = d4[pix - 1]; for (int c = 0; c < 2; ++c) res[c] += dl.v[c]; }
+        if (j < ny - 1) for (int c = 0; c < 2; ++c) res[c] -= dc.v[2 + c];
+        if (j > 0) { const V4 du = d4[pix - nx]; for (int c = 0; c < 2; ++c) res[c] += du.v[2 + c]; }
+        part[0] += (double)res[0] * (double)res[0];
+        part[1] += (double)res[1] * (double)res[1];
     }
 }
 
-}  // namespace
+// R^T (+ epilogue).  A workgroup owns an 8x8 block of pixel orbits (the block
+// lies in the first quadrant when SYM = 4) and has VS waves, each summing a
+// disjoint subset of the base views; wave 0 adds the others' sums in order.
+template <typename T, int CH, int SYM, bool QUAD, int EPI, int VS>
+__global__ __launch_bounds__(64 * VS) void k_backproject(BpArgs<T> a) {
+    __shared__ T red[VS > 1 ? VS - 1 : 1][64][SYM * CH];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i = blockIdx.x * 8 + (lane & 7);
+    const int j = blockIdx.y * 8 + (lane >> 3);
+    const int dom_x = SYM == 4 ? a.nx / 2 : a.nx, dom_y = SYM == 4 ? a.ny / 2 : a.ny;
+    const bool inside = i < dom_x && j < dom_y;
+    T acc[SYM][CH];
+#pragma unroll
+    for (int k = 0; k < SYM; ++k)
+#pragma unroll
+        for (int c = 0; c < CH; ++c) acc[k][c] = T(0);
+    if (inside) gather_orbit<T, CH, SYM, QUAD, VS>(a, wave, i, j, acc);
+    if constexpr (VS > 1) {
+        if (wave > 0)
+#pragma unroll
+            for (int k = 0; k < SYM; ++k)
+#pragma unroll
+                for (int c = 0; c < CH; ++c) red[wave - 1][lane][k * CH + c] = acc[k][c];
+        __syncthreads();
+        if (wave == 0)
+            for (int w = 0; w < VS - 1; ++w)
+#pragma unroll
+                for (int k = 0; k < SYM; ++k)
+#pragma unroll
+                    for (int c = 0; c < CH; ++c) acc[k][c] += red[w][lane][k * CH + c];
+    }
+    if (wave != 0) return;
+    double part[2] = {0.0, 0.0};
+    if (inside) {
+#pragma unroll
+        for (int k = 0; k < SYM; ++k) {
+            int io, jo;
+            rot(k, a.nx, i, j, io, jo);
+            if constexpr (EPI == EPI_NONE) {
+                vec<T, CH> o;
+#pragma unroll
+                for (int c = 0; c < CH; ++c) o.v[c] = acc[k][c];
+                reinterpret_cast<vec<T, CH>*>(a.out)[(size_t)jo * a.nx + io] = o;
+            } else {
+                T res[2] = {acc[k][0], acc[k][CH > 1 ? 1 : 0]};
+                epilogue<T, EPI>(a, io, jo, res, part);
+            }
+        }
+    }
+    if constexpr (EPI != EPI_NONE) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+            for (int off = 32; off > 0; off >>= 1) part[c] += __shfl_down(part[c], off, 64);
+        if (lane == 0) {
+            double* o = a.partials + (size_t)(blockIdx.y * gridDim.x + blockIdx.x) * kPartialSlots;
+            o[0] = part[0];
+            o[1] = part[1];
+        }
+    }
+}
 
-template <typename T, int CH>
-hipError_t project_ch(const dect_plan* p, const void* img, void* imgT, void* sino, hipStream_t s) {
-    using VV = vec<T, CH>;
-    const int nx = p->nx, ny = p->ny;
+constexpr int kViewSplit = 4;
+
+template <typename T, int CH, int SYM, bool QUAD>
+hipError_t project_t(const dect_plan* p, const void* img, void* O, void* OT, void* sino,
+                     hipStream_t s) {
+    using VI = vec<T, CH>;
+    using VO = vec<T, CH * SYM>;
+    const long N = p->N;
     {
-        ProfScope pt("transpose", s);
-        hipLaunchKernelGGL((k_transpose<T, CH>), dim3((nx + 31) / 32, (ny + 31) / 32), dim3(256),
-                           0, s, static_cast<const VV*>(img), static_cast<VV*>(imgT), nx, ny);
+        ProfScope pt("orbit", s);
+        hipLaunchKernelGGL((k_orbit<T, CH, SYM, false>), dim3((unsigned)((N + 255) / 256)),
+                           dim3(256), 0, s, static_cast<const VI*>(img), static_cast<VO*>(O),
+                           p->nx, p->ny);
+        hipLaunchKernelGGL((k_orbit<T, CH, SYM, true>), dim3((unsigned)((N + 255) / 256)),
+                           dim3(256), 0, s, static_cast<const VI*>(img), static_cast<VO*>(OT),
+                           p->nx, p->ny);
     }
     ProfScope pp("project", s);
-    hipLaunchKernelGGL((k_project<T, CH>), dim3((p->D + 255) / 256, p->V), dim3(256), 0, s,
-                       static_cast<const RayParam<T>*>(p->rays), static_cast<const VV*>(img),
-                       static_cast<const VV*>(imgT), static_cast<VV*>(sino), nx, ny, p->D);
+    hipLaunchKernelGGL((k_project<T, CH, SYM, QUAD>), dim3((p->D + 255) / 256, p->Vb), dim3(256),
+                       0, s, static_cast<const RayParam<T>*>(p->rays), static_cast<const VO*>(O),
+                       static_cast<const VO*>(OT), static_cast<T*>(sino), p->nx, p->ny, p->Vb,
+                       p->D);
     return hipGetLastError();
 }
 
+template <typename T, int CH, int SYM, bool QUAD>
+hipError_t bp_t(const dect_plan* p, int epi, const BpArgs<T>& a, hipStream_t s) {
+    const int dx = SYM == 4 ? p->nx / 2 : p->nx, dy = SYM == 4 ? p->ny / 2 : p->ny;
+    dim3 g((dx + 7) / 8, (dy + 7) / 8);
+    dim3 blk(64 * kViewSplit);
+    switch (epi) {
+        case EPI_NONE:
+            hipLaunchKernelGGL((k_backproject<T, CH, SYM, QUAD, EPI_NONE, kViewSplit>), g, blk, 0, s, a);
+            break;
+        case EPI_RHS:
+            hipLaunchKernelGGL((k_backproject<T, 2, SYM, QUAD, EPI_RHS, kViewSplit>), g, blk, 0, s, a);
+            break;
+        case EPI_Q:
+            hipLaunchKernelGGL((k_backproject<T, 2, SYM, QUAD, EPI_Q, kViewSplit>), g, blk, 0, s, a);
+            break;
+        default:
+            hipLaunchKernelGGL((k_backproject<T, 2, SYM, QUAD, EPI_DUAL, kViewSplit>), g, blk, 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
 template <typename T>
 hipError_t launch_project(const dect_plan* p, const void* img, void* sino, int ch, hipStream_t s) {
-    switch (ch) {
-        case 1: return project_ch<T, 1>(p, img, p->scratch_imgT, sino, s);
-        case 2: return project_ch<T, 2>(p, img, p->scratch_imgT, sino, s);
-        case 4: return project_ch<T, 4>(p, img, p->scratch_imgT, sino, s);
-        default: return hipErrorInvalidValue;
+    void* O = p->scratch_O;
+    void* OT = p->scratch_OT;
+    if (p->sym == 4) {
+        switch (ch) {
+            case 1: return project_t<T, 1, 4, false>(p, img, O, OT, sino, s);
+            case 2: return project_t<T, 2, 4, false>(p, img, O, OT, sino, s);
+            case 4: return project_t<T, 4, 4, false>(p, img, O, OT, sino, s);
+        }
+    } else {
+        switch (ch) {
+            case 1: return project_t<T, 1, 1, false>(p, img, O, OT, sino, s);
+            case 2: return project_t<T, 2, 1, false>(p, img, O, OT, sino, s);
+            case 4: return project_t<T, 4, 1, false>(p, img, O, OT, sino, s);
+        }
     }
+    return hipErrorInvalidValue;
 }
 
 template <typename T>
-hipError_t launch_project_pair(const dect_plan* p, const void* img, void* imgT, void* sino,
-                               hipStream_t s) {
-    return project_ch<T, 2>(p, img, imgT, sino, s);
+hipError_t launch_project_pair(const dect_plan* p, const void* img, void* O, void* OT,
+                               void* sino, hipStream_t s) {
+    return p->sym == 4 ? project_t<T, 2, 4, true>(p, img, O, OT, sino, s)
+                       : project_t<T, 2, 1, true>(p, img, O, OT, sino, s);
 }
 
 template <typename T>
@@ -317,32 +457,35 @@ hipError_t launch_backproject(const dect_plan* p, int ch, int epi, const BpArgs<
     a.nx = p->nx;
     a.ny = p->ny;
     a.V = p->V;
+    a.Vb = p->Vb;
     a.D = p->D;
-    dim3 g((p->nx + 15) / 16, (p->ny + 15) / 16);
+    a.margin = p->margin;
     static const char* names[4] = {"backproject", "backproject_rhs", "backproject_q",
                                    "backproject_dual"};
     ProfScope ps(names[epi & 3], s);
-    if (epi == EPI_NONE) {
+    const bool quad = epi != EPI_NONE;  // the ADMM's own sinograms are quad records
+    if (p->sym == 4) {
+        if (quad) return bp_t<T, 2, 4, true>(p, epi, a, s);
         switch (ch) {
-            case 1: hipLaunchKernelGGL((k_backproject<T, 1, EPI_NONE>), g, dim3(256), 0, s, a); break;
-            case 2: hipLaunchKernelGGL((k_backproject<T, 2, EPI_NONE>), g, dim3(256), 0, s, a); break;
-            case 4: hipLaunchKernelGGL((k_backproject<T, 4, EPI_NONE>), g, dim3(256), 0, s, a); break;
-            default: return hipErrorInvalidValue;
+            case 1: return bp_t<T, 1, 4, false>(p, epi, a, s);
+            case 2: return bp_t<T, 2, 4, false>(p, epi, a, s);
+            case 4: return bp_t<T, 4, 4, false>(p, epi, a, s);
         }
-    } else if (epi == EPI_RHS) {
-        hipLaunchKernelGGL((k_backproject<T, 2, EPI_RHS>), g, dim3(256), 0, s, a);
-    } else if (epi == EPI_Q) {
-        hipLaunchKernelGGL((k_backproject<T, 2, EPI_Q>), g, dim3(256), 0, s, a);
     } else {
-        hipLaunchKernelGGL((k_backproject<T, 2, EPI_DUAL>), g, dim3(256), 0, s, a);
+        if (quad) return bp_t<T, 2, 1, true>(p, epi, a, s);
+        switch (ch) {
+            case 1: return bp_t<T, 1, 1, false>(p, epi, a, s);
+            case 2: return bp_t<T, 2, 1, false>(p, epi, a, s);
+            case 4: return bp_t<T, 4, 1, false>(p, epi, a, s);
+        }
     }
-    return hipGetLastError();
+    return hipErrorInvalidValue;
 }
 
 template hipError_t launch_project<float>(const dect_plan*, const void*, void*, int, hipStream_t);
 template hipError_t launch_project<double>(const dect_plan*, const void*, void*, int, hipStream_t);
-template hipError_t launch_project_pair<float>(const dect_plan*, const void*, void*, void*, hipStream_t);
-template hipError_t launch_project_pair<double>(const dect_plan*, const void*, void*, void*, hipStream_t);
+template hipError_t launch_project_pair<float>(const dect_plan*, const void*, void*, void*, void*, hipStream_t);
+template hipError_t launch_project_pair<double>(const dect_plan*, const void*, void*, void*, void*, hipStream_t);
 template hipError_t launch_backproject<float>(const dect_plan*, int, int, const BpArgs<float>&, hipStream_t);
 template hipError_t launch_backproject<double>(const dect_plan*, int, int, const BpArgs<double>&, hipStream_t);
 

@@ -116,9 +116,11 @@ template <typename T, int MODE>
 __global__ __launch_bounds__(256) void k_udm(UdmArgs<T> A, const T* __restrict__ spec, int kmax,
                                              int kh, int kl) {
     using V2 = vec<T, 2>;
-    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    // l: internal ray index (t, da, R p); i: standard [V][D] index (m, w, a, u^a, R x).
+    const long l = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long i = l < A.M ? std_ray(l, A.sym, A.Vb, A.D) : 0;
     double part[4] = {0.0, 0.0, 0.0, 0.0};
-    if (i < A.M) {
+    if (l < A.M) {
         const T mh = A.mh[i], ml = A.ml[i], wh = A.wh[i], wl = A.wl[i];
         V2* a2 = reinterpret_cast<V2*>(A.a);
         Point<T> P;
@@ -145,7 +147,7 @@ __global__ __launch_bounds__(256) void k_udm(UdmArgs<T> A, const T* __restrict__
         } else if constexpr (MODE == 2) {
             // R x after the last CG step (tracked: R x += alpha R p), v = R x - u^a.
             const V2 rx0 = reinterpret_cast<const V2*>(A.Rx)[i];
-            const V2 rp2 = reinterpret_cast<const V2*>(A.Rp)[i];
+            const V2 rp2 = reinterpret_cast<const V2*>(A.Rp)[l];
             ua = reinterpret_cast<const V2*>(A.ua)[i];
             rx.v[0] = rx0.v[0] + (T)A.scal[S_ALPHA] * rp2.v[0];
             rx.v[1] = rx0.v[1] + (T)A.scal[S_ALPHA + 1] * rp2.v[1];
@@ -163,7 +165,7 @@ __global__ __launch_bounds__(256) void k_udm(UdmArgs<T> A, const T* __restrict__
         if constexpr (MODE == 0) {
             if (A.cost) A.cost[i] = P.phi;
         } else if constexpr (MODE == 1) {
-            reinterpret_cast<V2*>(A.t)[i] = an;  // u^a = R x = 0
+            reinterpret_cast<V2*>(A.t)[l] = an;  // u^a = R x = 0
         } else {
             V2 un, tn, dn;
 #pragma unroll
@@ -175,8 +177,8 @@ __global__ __launch_bounds__(256) void k_udm(UdmArgs<T> A, const T* __restrict__
             }
             reinterpret_cast<V2*>(A.ua)[i] = un;
             reinterpret_cast<V2*>(A.Rx)[i] = rx;
-            reinterpret_cast<V2*>(A.t)[i] = tn;
-            reinterpret_cast<V2*>(A.da)[i] = dn;
+            reinterpret_cast<V2*>(A.t)[l] = tn;
+            reinterpret_cast<V2*>(A.da)[l] = dn;
             const T rh = P.fh - mh, rl = P.fl - ml;
             part[2] = 0.5 * ((double)wh * (double)rh * (double)rh + (double)wl * (double)rl * (double)rl);
             const bool finite = (P.ac - P.ac == T(0)) && (P.ap - P.ap == T(0)) &&

@@ -48,6 +48,11 @@ GEOMS = {
     "single_view_fan": S.geometry("fan", 16, 16, 1.0, 1, 257, 0.3, src_iso_cm=40.0,
                                   src_det_cm=70.0),
     "two_by_two": S.geometry("parallel", 2, 2, 1.0, 7, 5, 0.8),
+    # Full-turn fans with n_views % 4 == 0 on square images use the quarter-turn
+    # symmetric operator (views v + k V/4 are rotations of base views).
+    "sym_fan": S.fan_geometry_fov(64, 120, 100, fov_cm=25.6, src_iso_cm=40.0, src_det_cm=70.0),
+    "sym_fan_offset": S.geometry("fan", 32, 32, 0.5, 44, 57, 0.6, det_offset=0.37,
+                                 src_iso_cm=30.0, src_det_cm=50.0, angle0=0.2),
 }
 
 
