@@ -32,6 +32,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=2)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 256 MiB device-to-device copy (reference for "
+                         "hardware byte counters)")
     return ap.parse_args()
 
 
@@ -142,6 +145,12 @@ def main():
                      "rho": log[-1]["rho"]},
         "wall_s": round(wall, 4),
     }
+    if args.calibrate_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = src.numel() * 4
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pr, args.cpu_iters)
     print(json.dumps(out))

@@ -444,6 +444,7 @@ dect_status iterate_T(const dect_plan* p, const void* mh, const void* ml, const 
         u.Rp = Rp;
         u.t = t;
         u.da = da;
+        u.fg = at<T>(st, p->off_fg);
         u.scal = scal;
         u.partials = P.sino;
         u.iters = prm->lm_iters;
@@ -518,6 +519,7 @@ dect_status init_T(const dect_plan* p, const void* mh, const void* ml, const voi
     u.wl = static_cast<const T*>(wl);
     u.a = at<T>(st, p->layout.a);
     u.t = at<T>(st, p->off_t);
+    u.fg = at<T>(st, p->off_fg);
     u.iters = 10;
     u.mu0 = prm->lm_mu0;
     // Inverse of the linearisation at a = 0: rows (mean f_KN, mean f_p) per spectrum.

@@ -91,13 +91,14 @@ struct dect_plan {
     void* views = nullptr;  // ViewParam<T>[Vb]
     void* spec = nullptr;   // T[6 * Kmax]: lw_h, kc_h, kp_h, lw_l, kc_l, kp_l
     int kh = 0, kl = 0, kmax = 0;
+    double kc_max = 0.0, kp_max = 0.0;  // largest f_KN, f_p times log2(e) over used bins
     double mean_f[2][2];    // spectrum-mean (f_KN, f_p) per spectrum (h, l)
     // plan-owned scratch: orbit images of the image being projected (up to 4 channels)
     void* scratch_O = nullptr;   // T[N * 4 * sym]
     void* scratch_OT = nullptr;  // T[N * 4 * sym]
     // state layout (bytes)
     dect_layout layout;
-    size_t off_p, off_pO, off_pOT, off_r, off_q, off_dy, off_dz, off_Rp, off_t, off_da,
+    size_t off_p, off_pO, off_pOT, off_r, off_q, off_dy, off_dz, off_Rp, off_t, off_da, off_fg,
         off_partials, off_log;
     int nb_sino, nb_img, nb_tiles;  // block counts of the reducing kernels
 };

@@ -77,6 +77,7 @@ struct UdmArgs {
     const T* Rp;   // [M][2]
     T* t;          // [M][2] next right-hand side a + u^a - R x
     T* da;         // [M][2] a - a_prev
+    T* fg;         // [M][8] f_h, f_l, grad f_h, grad f_l at the current a (internal order)
     const double* scal;  // device scalars (rho, alpha)
     double* partials;
     double rho_c, rho_p;  // standalone/init penalties

@@ -156,6 +156,8 @@ dect_status build_tables(dect_plan* p, const dect_spectra* spec) {
             tab[h][0].push_back((T)std::log2(om));
             tab[h][1].push_back((T)(spec->f_kn[k] * log2e));
             tab[h][2].push_back((T)(spec->f_p[k] * log2e));
+            p->kc_max = std::fmax(p->kc_max, std::fabs(spec->f_kn[k] * log2e));
+            p->kp_max = std::fmax(p->kp_max, std::fabs(spec->f_p[k] * log2e));
             mkn += om * spec->f_kn[k];
             mp += om * spec->f_p[k];
         }
@@ -206,6 +208,7 @@ void make_layout(dect_plan* p) {
     p->off_Rp = take(M * 2 * e);
     p->off_t = take(M * 2 * e);
     p->off_da = take(M * 2 * e);
+    p->off_fg = take(M * 8 * e);
     p->nb_sino = (int)((M + 255) / 256);
     p->nb_img = (int)((N + 255) / 256);
     p->nb_tiles = bp_blocks(p);

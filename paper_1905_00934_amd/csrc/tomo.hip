@@ -70,18 +70,24 @@ __global__ __launch_bounds__(256) void k_orbit(const vec<T, CH>* __restrict__ X,
 }
 
 // R for base rays: QUAD = true writes [Vb][D][SYM][CH] records, false writes the
-// standard [V][D][CH] layout (view v + k*Vb for rotation k).
-template <typename T, int CH, int SYM, bool QUAD>
-__global__ __launch_bounds__(256) void k_project(const RayParam<T>* __restrict__ rays,
-                                                 const vec<T, CH * SYM>* __restrict__ O,
-                                                 const vec<T, CH * SYM>* __restrict__ OT,
-                                                 T* __restrict__ sino, int nx, int ny, int Vb,
-                                                 int D) {
+// standard [V][D][CH] layout (view v + k*Vb for rotation k).  A workgroup owns
+// 64 consecutive bins of one base view; its KS waves step through KS disjoint
+// ranges of image lines (so the lanes of a wave read one image line together)
+// and wave 0 adds the KS partial sums in order.
+template <typename T, int CH, int SYM, bool QUAD, int KS>
+__global__ __launch_bounds__(64 * KS) void k_project(const RayParam<T>* __restrict__ rays,
+                                                     const vec<T, CH * SYM>* __restrict__ O,
+                                                     const vec<T, CH * SYM>* __restrict__ OT,
+                                                     T* __restrict__ sino, int nx, int ny, int Vb,
+                                                     int D) {
     constexpr int W = CH * SYM;
+    __shared__ T red[KS > 1 ? KS - 1 : 1][64][W];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int v = blockIdx.y;
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= D) return;
-    const RayParam<T> r = rays[(size_t)v * D + b];
+    const int b = blockIdx.x * 64 + lane;
+    const bool valid = b < D;
+    RayParam<T> r = rays[(size_t)v * D + (valid ? b : D - 1)];
     const bool xs = r.pad == T(0);
     const int n_steps = xs ? nx : ny;   // samples along the ray
     const int n_lines = xs ? ny : nx;   // interpolation axis
@@ -100,6 +106,11 @@ __global__ __launch_bounds__(256) void k_project(const RayParam<T>* __restrict__
     } else if (!(r.phi0 >= T(-1) && r.phi0 < T(n_lines))) {
         k1 = -1;
     }
+    // This wave's share of the lines.
+    const int c0 = (int)((long)wave * n_steps / KS), c1 = (int)((long)(wave + 1) * n_steps / KS) - 1;
+    k0 = k0 > c0 ? k0 : c0;
+    k1 = k1 < c1 ? k1 : c1;
+    if (!valid) k1 = -1;
     T acc[W];
 #pragma unroll
     for (int c = 0; c < W; ++c) acc[c] = T(0);
@@ -139,6 +150,17 @@ __global__ __launch_bounds__(256) void k_project(const RayParam<T>* __restrict__
 #pragma unroll
         for (int c = 0; c < W; ++c) acc[c] += a0.v[c] + aa * (a1.v[c] - a0.v[c]);
     }
+    if constexpr (KS > 1) {
+        if (wave > 0)
+#pragma unroll
+            for (int c = 0; c < W; ++c) red[wave - 1][lane][c] = acc[c];
+        __syncthreads();
+        if (wave != 0) return;
+        for (int w = 0; w < KS - 1; ++w)
+#pragma unroll
+            for (int c = 0; c < W; ++c) acc[c] += red[w][lane][c];
+    }
+    if (!valid) return;
     if constexpr (QUAD) {
         vec<T, W> out;
 #pragma unroll
@@ -167,65 +189,74 @@ __device__ inline void bin_range(T bc, T db, T m, int seg0, int seg1, int D, int
     hi = hi < seg1 - 1 ? hi : seg1 - 1;
 }
 
+template <typename T>
+__device__ inline T fast_rcp(T x) { return T(1) / x; }
+template <>
+__device__ inline float fast_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // Sum over the base views of this wave (v = wave, wave + VS, ...) for the orbit
 // of pixel (i, j).  Pixel rot^k(p) seen from view v + k' Vb has the weight of
 // base view v at pixel rot^(k - k')(p), so for every orbit member p_m = rot^m(p)
 // the base-view weights are evaluated once and routed to acc[(m + k') mod SYM]
-// with sinogram row v + k' Vb, for all k'.
+// with sinogram row v + k' Vb, for all k'.  The footprint needs only ~1e-3-bin
+// accuracy (the margin covers it), hence the hardware reciprocal.
 template <typename T, int CH, int SYM, bool QUAD, int VS>
 __device__ inline void gather_orbit(const BpArgs<T>& a, int wave, int i, int j,
                                     T (&acc)[SYM][CH]) {
     const T m = (T)a.margin;
-    const int D = a.D, Vb = a.Vb;
+    const int D = a.D, Vb = a.Vb, n = a.nx;
     const T cx = T(0.5) * (T)(a.nx - 1), cy = T(0.5) * (T)(a.ny - 1);
     for (int v = wave; v < Vb; v += VS) {
         const ViewParam<T> w = a.views[v];
-        const RayParam<T>* rv = a.rays + (size_t)v * D;
+        const RayParam<T>* __restrict__ rv = a.rays + (size_t)v * D;
+        const vec<T, CH>* __restrict__ sv = reinterpret_cast<const vec<T, CH>*>(a.sino);
+        const vec<T, SYM * CH>* __restrict__ sq =
+            reinterpret_cast<const vec<T, SYM * CH>*>(a.sino) + (size_t)v * D;
 #pragma unroll
         for (int mm = 0; mm < SYM; ++mm) {
             int im, jm;
-            rot(mm, a.nx, i, j, im, jm);
+            rot(mm, n, i, j, im, jm);
             const T fi = (T)im, fj = (T)jm;
             const T ip = fi - cx, jp = fj - cy;
             const T num = w.ni * ip + w.nj * jp;
             const T den = w.d0 + w.di * ip + w.dj * jp;
-            const T inv = T(1) / den;
+            const T inv = fast_rcp<T>(den);
             const T bq = num * inv;
             const T bc = bq + w.boff;
             // d(beta) for one pixel step along y (x-stepped rays) and along x.
             const T dby = (w.nj - bq * w.dj) * inv;
             const T dbx = (w.ni - bq * w.di) * inv;
-            int lo, hi;
+#pragma unroll
             for (int seg = 0; seg < 2; ++seg) {
                 const bool xseg = seg == 0;
+                int lo, hi;
                 if (xseg) bin_range<T>(bc, dby, m, w.xb0, w.xb1, D, lo, hi);
                 else bin_range<T>(bc, dbx, m, w.yb0, w.yb1, D, lo, hi);
                 const T fs = xseg ? fi : fj;   // sampling coordinate
                 const T fp = xseg ? fj : fi;   // interpolated coordinate of the pixel
                 for (int b = lo; b <= hi; ++b) {
                     const RayParam<T> r = rv[b];
+                    vec<T, SYM * CH> s;
+                    if constexpr (QUAD) {
+                        s = sq[b];
+                    } else {
+#pragma unroll
+                        for (int kp = 0; kp < SYM; ++kp) {
+                            const vec<T, CH> t = sv[(size_t)(v + kp * Vb) * D + b];
+#pragma unroll
+                            for (int c = 0; c < CH; ++c) s.v[kp * CH + c] = t.v[c];
+                        }
+                    }
                     const T phi = fma(r.slope, fs, r.phi0);
                     const T fl = floor(phi);
                     const T al = phi - fl;
                     T wt = fl == fp ? T(1) - al : (fl == fp - T(1) ? al : T(0));
                     wt *= r.step;
-                    if constexpr (QUAD) {
-                        const vec<T, SYM * CH> s =
-                            reinterpret_cast<const vec<T, SYM * CH>*>(a.sino)[(size_t)v * D + b];
 #pragma unroll
-                        for (int kp = 0; kp < SYM; ++kp)
+                    for (int kp = 0; kp < SYM; ++kp)
 #pragma unroll
-                            for (int c = 0; c < CH; ++c)
-                                acc[(mm + kp) % SYM][c] += wt * s.v[kp * CH + c];
-                    } else {
-#pragma unroll
-                        for (int kp = 0; kp < SYM; ++kp) {
-                            const vec<T, CH> s = reinterpret_cast<const vec<T, CH>*>(
-                                a.sino)[(size_t)(v + kp * Vb) * D + b];
-#pragma unroll
-                            for (int c = 0; c < CH; ++c) acc[(mm + kp) % SYM][c] += wt * s.v[c];
-                        }
-                    }
+                        for (int c = 0; c < CH; ++c)
+                            acc[(mm + kp) % SYM][c] += wt * s.v[kp * CH + c];
                 }
             }
         }
@@ -318,7 +349,8 @@ __device__ inline void epilogue(const BpArgs<T>& a, int i, int j, T (&res)[2], d
 template <typename T, int CH, int SYM, bool QUAD, int EPI, int VS>
 __global__ __launch_bounds__(64 * VS) void k_backproject(BpArgs<T> a) {
     __shared__ T red[VS > 1 ? VS - 1 : 1][64][SYM * CH];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int i = blockIdx.x * 8 + (lane & 7);
     const int j = blockIdx.y * 8 + (lane >> 3);
     const int dom_x = SYM == 4 ? a.nx / 2 : a.nx, dom_y = SYM == 4 ? a.ny / 2 : a.ny;
@@ -373,7 +405,14 @@ __global__ __launch_bounds__(64 * VS) void k_backproject(BpArgs<T> a) {
     }
 }
 
-constexpr int kViewSplit = 4;
+#ifndef DECT_VIEW_SPLIT
+#define DECT_VIEW_SPLIT 4
+#endif
+#ifndef DECT_LINE_SPLIT
+#define DECT_LINE_SPLIT 4
+#endif
+constexpr int kViewSplit = DECT_VIEW_SPLIT;  // waves per transpose workgroup
+constexpr int kLineSplit = DECT_LINE_SPLIT;  // waves per projector workgroup
 
 template <typename T, int CH, int SYM, bool QUAD>
 hipError_t project_t(const dect_plan* p, const void* img, void* O, void* OT, void* sino,
@@ -391,8 +430,8 @@ hipError_t project_t(const dect_plan* p, const void* img, void* O, void* OT, voi
                            p->nx, p->ny);
     }
     ProfScope pp("project", s);
-    hipLaunchKernelGGL((k_project<T, CH, SYM, QUAD>), dim3((p->D + 255) / 256, p->Vb), dim3(256),
-                       0, s, static_cast<const RayParam<T>*>(p->rays), static_cast<const VO*>(O),
+    hipLaunchKernelGGL((k_project<T, CH, SYM, QUAD, kLineSplit>), dim3((p->D + 63) / 64, p->Vb),
+                       dim3(64 * kLineSplit), 0, s, static_cast<const RayParam<T>*>(p->rays), static_cast<const VO*>(O),
                        static_cast<const VO*>(OT), static_cast<T*>(sino), p->nx, p->ny, p->Vb,
                        p->D);
     return hipGetLastError();

@@ -19,27 +19,38 @@ namespace {
 
 template <typename T> struct Cst;
 template <> struct Cst<float> {
-    __device__ static float exp2(float x) { return exp2f(x); }
-    __device__ static float log2(float x) { return log2f(x); }
+    // Raw hardware exp2/log2: arguments stay in the normal range by construction
+    // (the largest exponent is shifted to <= 0 and the sum of terms is >= 2^-110),
+    // and a result below 2^-126 only drops a term smaller than 2^-126 of the sum.
+    __device__ static float exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+    __device__ static float log2(float x) { return __builtin_amdgcn_logf(x); }
 };
 template <> struct Cst<double> {
     __device__ static double exp2(double x) { return ::exp2(x); }
     __device__ static double log2(double x) { return ::log2(x); }
 };
 
-// f and gradient of one spectrum at (ac, ap), tables in base-2 units.
+// f and gradient of one spectrum at (ac, ap), tables in base-2 units:
+//   f = -ln2 (M + log2 sum_k 2^(e_k - M)),  e_k = lw_k - kc_k ac - kp_k ap,
+//   grad f = ln2 sum_k 2^(e_k - M) (kc_k, kp_k) / sum_k 2^(e_k - M).
+// Any shift M gives the same value; M must keep every e_k - M below the
+// overflow threshold and the largest above underflow.  With exact = true M is
+// the largest exponent (one extra pass); otherwise the caller's M is used.
 template <typename T>
 __device__ inline void spectrum_eval(const T* __restrict__ lw, const T* __restrict__ kc,
-                                     const T* __restrict__ kp, int n, T ac, T ap, T& f, T& gc,
-                                     T& gp) {
+                                     const T* __restrict__ kp, int n, T ac, T ap, T shift,
+                                     bool exact, T& f, T& gc, T& gp) {
     constexpr T ln2 = T(0.6931471805599453);
-    T m = -INFINITY;
+    T m = shift;
+    if (exact) {
+        m = -INFINITY;
 #pragma unroll 4
-    for (int k = 0; k < n; ++k) m = fmax(m, lw[k] - kc[k] * ac - kp[k] * ap);
+        for (int k = 0; k < n; ++k) m = fmax(m, lw[k] - kc[k] * ac - kp[k] * ap);
+    }
     T z = T(0), sc = T(0), sp = T(0);
 #pragma unroll 4
     for (int k = 0; k < n; ++k) {
-        const T q = Cst<T>::exp2(lw[k] - kc[k] * ac - kp[k] * ap - m);
+        const T q = Cst<T>::exp2((lw[k] - m) - kc[k] * ac - kp[k] * ap);
         z += q;
         sc += q * kc[k];
         sp += q * kp[k];
@@ -56,12 +67,19 @@ struct Point {
     T ac, ap, fh, fl, ghc, ghp, glc, glp, phi;
 };
 
+// Largest |kc| and |kp| over both spectra (bounds the exponent change of a step).
+struct StepBound {
+    float kcmax, kpmax;
+};
+
 template <typename T>
 __device__ inline void evaluate(const T* __restrict__ spec, int kmax, int kh, int kl, T mh, T ml,
-                                T wh, T wl, T vc, T vp, T rc, T rp, Point<T>& P) {
-    spectrum_eval<T>(spec, spec + kmax, spec + 2 * kmax, kh, P.ac, P.ap, P.fh, P.ghc, P.ghp);
-    spectrum_eval<T>(spec + 3 * kmax, spec + 4 * kmax, spec + 5 * kmax, kl, P.ac, P.ap, P.fl,
-                     P.glc, P.glp);
+                                T wh, T wl, T vc, T vp, T rc, T rp, T shift_h, T shift_l,
+                                bool exact, Point<T>& P) {
+    spectrum_eval<T>(spec, spec + kmax, spec + 2 * kmax, kh, P.ac, P.ap, shift_h, exact, P.fh,
+                     P.ghc, P.ghp);
+    spectrum_eval<T>(spec + 3 * kmax, spec + 4 * kmax, spec + 5 * kmax, kl, P.ac, P.ap, shift_l,
+                     exact, P.fl, P.glc, P.glp);
     const T rh = P.fh - mh, rl = P.fl - ml, dc = P.ac - vc, dp = P.ap - vp;
     P.phi = T(0.5) * (wh * rh * rh + wl * rl * rl) + T(0.5) * (rc * dc * dc + rp * dp * dp);
 }
@@ -75,11 +93,16 @@ __device__ inline T det2(T a, T d, T b, T c) {
     return f + e;
 }
 
-// m Levenberg-Marquardt iterations from P (evaluated); P ends at the last accepted point.
+// m Levenberg-Marquardt iterations from P (evaluated); P ends at the last accepted
+// point.  A trial point is evaluated in one pass, shifted by the log-sum-exp of
+// the current point: the exponents then change by at most
+// B = kcmax |d_c| + kpmax |d_p|, so for B <= 96 nothing overflows and the largest
+// term stays above 2^-(96 + log2 K).  Larger steps take the two-pass form.
 template <typename T>
 __device__ inline void lm_solve(const T* __restrict__ spec, int kmax, int kh, int kl, T mh, T ml,
                                 T wh, T wl, T vc, T vp, T rc, T rp, int iters, T mu,
-                                Point<T>& P) {
+                                StepBound sb, Point<T>& P) {
+    constexpr T log2e = T(1.4426950408889634);
     for (int it = 0; it < iters; ++it) {
         const T rh = P.fh - mh, rl = P.fl - ml;
         const T Gc = wh * rh * P.ghc + wl * rl * P.glc + rc * (P.ac - vc);
@@ -100,9 +123,15 @@ __device__ inline void lm_solve(const T* __restrict__ spec, int kmax, int kh, in
         const T Dcc = (T(1) + mu) * Hcc, Dpp = (T(1) + mu) * Hpp;
         const T id = T(1) / det;
         Point<T> Q;
-        Q.ac = P.ac - (Dpp * Gc - Hcp * Gp) * id;
-        Q.ap = P.ap - (Dcc * Gp - Hcp * Gc) * id;
-        evaluate<T>(spec, kmax, kh, kl, mh, ml, wh, wl, vc, vp, rc, rp, Q);
+        const T dc = -(Dpp * Gc - Hcp * Gp) * id;
+        const T dp = -(Dcc * Gp - Hcp * Gc) * id;
+        Q.ac = P.ac + dc;
+        Q.ap = P.ap + dp;
+        const T bound = (T)sb.kcmax * fabs(dc) + (T)sb.kpmax * fabs(dp);
+        // A non-finite current value gives no usable shift either.
+        const bool exact = !(bound <= T(96)) || !(P.fh - P.fh == T(0)) || !(P.fl - P.fl == T(0));
+        evaluate<T>(spec, kmax, kh, kl, mh, ml, wh, wl, vc, vp, rc, rp, -P.fh * log2e,
+                    -P.fl * log2e, exact, Q);
         if (Q.phi < P.phi) {
             P = Q;
             mu *= T(0.1);
@@ -114,9 +143,11 @@ __device__ inline void lm_solve(const T* __restrict__ spec, int kmax, int kh, in
 
 template <typename T, int MODE>
 __global__ __launch_bounds__(256) void k_udm(UdmArgs<T> A, const T* __restrict__ spec, int kmax,
-                                             int kh, int kl) {
+                                             int kh, int kl, StepBound sb) {
     using V2 = vec<T, 2>;
-    // l: internal ray index (t, da, R p); i: standard [V][D] index (m, w, a, u^a, R x).
+    using V4 = vec<T, 4>;
+    // l: internal ray index (t, da, R p, f cache); i: standard [V][D] index (m, w, a,
+    // u^a, R x).
     const long l = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const long i = l < A.M ? std_ray(l, A.sym, A.Vb, A.D) : 0;
     double part[4] = {0.0, 0.0, 0.0, 0.0};
@@ -156,12 +187,39 @@ __global__ __launch_bounds__(256) void k_udm(UdmArgs<T> A, const T* __restrict__
             rc = (T)A.scal[S_RHO];
             rp = (T)A.scal[S_RHO + 1];
         }
-        evaluate<T>(spec, kmax, kh, kl, mh, ml, wh, wl, vc, vp, rc, rp, P);
-        lm_solve<T>(spec, kmax, kh, kl, mh, ml, wh, wl, vc, vp, rc, rp, A.iters, (T)A.mu0, P);
+        if constexpr (MODE == 2) {
+            // f and its gradient at the current a were computed by the previous
+            // a-update (a has not changed since) and are kept per ray.
+            const V4 c0 = reinterpret_cast<const V4*>(A.fg)[2 * l];
+            const V2 c1 = reinterpret_cast<const V2*>(A.fg)[4 * l + 2];
+            P.fh = c0.v[0];
+            P.fl = c0.v[1];
+            P.ghc = c0.v[2];
+            P.ghp = c0.v[3];
+            P.glc = c1.v[0];
+            P.glp = c1.v[1];
+            const T rh = P.fh - mh, rl = P.fl - ml, dc = P.ac - vc, dp = P.ap - vp;
+            P.phi = T(0.5) * (wh * rh * rh + wl * rl * rl) + T(0.5) * (rc * dc * dc + rp * dp * dp);
+        } else {
+            evaluate<T>(spec, kmax, kh, kl, mh, ml, wh, wl, vc, vp, rc, rp, T(0), T(0), true, P);
+        }
+        lm_solve<T>(spec, kmax, kh, kl, mh, ml, wh, wl, vc, vp, rc, rp, A.iters, (T)A.mu0, sb, P);
         V2 an;
         an.v[0] = P.ac;
         an.v[1] = P.ap;
         a2[i] = an;
+        if constexpr (MODE != 0) {
+            V4 c0;
+            V2 c1;
+            c0.v[0] = P.fh;
+            c0.v[1] = P.fl;
+            c0.v[2] = P.ghc;
+            c0.v[3] = P.ghp;
+            c1.v[0] = P.glc;
+            c1.v[1] = P.glp;
+            reinterpret_cast<V4*>(A.fg)[2 * l] = c0;
+            reinterpret_cast<V2*>(A.fg)[4 * l + 2] = c1;
+        }
         if constexpr (MODE == 0) {
             if (A.cost) A.cost[i] = P.phi;
         } else if constexpr (MODE == 1) {
@@ -208,13 +266,14 @@ template <typename T>
 hipError_t launch_udm(const dect_plan* p, int mode, const UdmArgs<T>& a, hipStream_t s) {
     dim3 g((unsigned)((a.M + 255) / 256));
     const T* spec = static_cast<const T*>(p->spec);
+    const StepBound sb{(float)p->kc_max, (float)p->kp_max};
     ProfScope ps(mode == 1 ? "udm_init" : "udm", s);
     if (mode == 0)
-        hipLaunchKernelGGL((k_udm<T, 0>), g, dim3(256), 0, s, a, spec, p->kmax, p->kh, p->kl);
+        hipLaunchKernelGGL((k_udm<T, 0>), g, dim3(256), 0, s, a, spec, p->kmax, p->kh, p->kl, sb);
     else if (mode == 1)
-        hipLaunchKernelGGL((k_udm<T, 1>), g, dim3(256), 0, s, a, spec, p->kmax, p->kh, p->kl);
+        hipLaunchKernelGGL((k_udm<T, 1>), g, dim3(256), 0, s, a, spec, p->kmax, p->kh, p->kl, sb);
     else
-        hipLaunchKernelGGL((k_udm<T, 2>), g, dim3(256), 0, s, a, spec, p->kmax, p->kh, p->kl);
+        hipLaunchKernelGGL((k_udm<T, 2>), g, dim3(256), 0, s, a, spec, p->kmax, p->kh, p->kl, sb);
     return hipGetLastError();
 }
 
