@@ -25,6 +25,23 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
 
 
+def _gen(job):
+    """Counts of one synthetic slice (runs in a worker process)."""
+    from paper_1905_00934_amd import synth
+    kind, idx = job
+    pr = (synth.slice_problem(idx, with_image=False) if kind == "stack"
+          else synth.uneven_problem(idx, with_image=False))
+    return kind, idx, pr.geom, pr.i0, pr.counts_high.astype("float32"), pr.counts_low.astype("float32")
+
+
+def generate(jobs, workers):
+    """Seeded inputs of many slices, in parallel, before the GPU is touched."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("fork")) as ex:
+        return list(ex.map(_gen, jobs))
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -32,6 +49,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=2)
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 64-slice stack and the 96-slice uneven batch")
+    ap.add_argument("--batch-steps", type=int, default=20,
+                    help="timed iterations of the batched workloads")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device-to-device copy (reference for "
                          "hardware byte counters)")
@@ -55,6 +76,58 @@ def cpu_baseline(pr, iters: int):
                       f"512x512 slice after its initialisation; {dt:.1f} s"}
 
 
+def batch_workload(dect, torch, dev, items, params, steps, warmup):
+    """Plain one-slice-at-a-time launches against one batch (HIP graph) of the same
+    slices; both start from the same initial states."""
+    from paper_1905_00934_amd import synth
+    spec = synth.default_spectra()
+    plans, slices = {}, []
+    for _, _, geom, i0, ch, cl in items:
+        key = (geom["nx"], geom["ny"], geom["n_views"], geom["n_det"])
+        if key not in plans:
+            plans[key] = dect.Plan(geom, spec, torch.float32, device=dev)
+        plan = plans[key]
+        c = [torch.from_numpy(x).to(dev) for x in (ch, cl)]
+        meas = list(plan.ingest(c[0], c[1], i0))
+        sa, sb = plan.new_state(), plan.new_state()
+        plan.admm_init(meas, sa, params)
+        plan.admm_init(meas, sb, params)
+        slices.append((plan, meas, sa, sb))
+    batch = dect.Batch([(p, m, sb) for p, m, _, sb in slices], params, graph=True)
+
+    def plain(n):
+        for plan, meas, sa, _ in slices:
+            plan.admm_iterate(meas, sa, params, n)
+
+    plain(warmup)
+    batch.iterate(warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name, fn in (("plain", plain), ("batched_graph", batch.iterate)):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        rate = len(slices) * steps / (ms / 1e3)
+        out[name] = {"slice_iters_per_s": round(rate, 1),
+                     "slices_per_s_at_50_iters": round(rate / 50, 3),
+                     "ms_per_batch_iter": round(ms / steps, 4)}
+    identical = all(torch.equal(sa.buf, sb.buf) for _, _, sa, sb in slices)
+    dect.profile_start()
+    batch.iterate(2)
+    kt = dect.profile_stop()
+    batch.close()
+    out["speedup"] = round(out["batched_graph"]["slice_iters_per_s"] /
+                           out["plain"]["slice_iters_per_s"], 4)
+    out["identical_states"] = identical
+    out["groups"] = len(plans)
+    out["kernels_per_batch_iter_us"] = {k: round(1e3 * v[0] / 2, 2) for k, v in kt.items()}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -62,6 +135,12 @@ def main():
               "(slices are independent and would shard across GPUs without communication)",
               file=sys.stderr)
         sys.exit(2)
+    batch_items = {}
+    if not args.no_batch:
+        workers = min(16, os.cpu_count() or 1)
+        jobs = [("stack", k) for k in range(64)] + [("uneven", k) for k in range(96)]
+        for item in generate(jobs, workers):
+            batch_items.setdefault(item[0], []).append(item)
     import numpy as np
     import torch
 
@@ -145,6 +224,19 @@ def main():
                      "rho": log[-1]["rho"]},
         "wall_s": round(wall, 4),
     }
+    if batch_items:
+        params_b = dect.AdmmParams()
+        out["batched"] = {
+            "stack64": {"workload": "64 independent 512x512 fan-beam luggage slices, 720 "
+                                    "views x 1024 bins, UDM1-CG1, adaptive rho",
+                        **batch_workload(dect, torch, dev, batch_items["stack"], params_b,
+                                         args.batch_steps, 2)},
+            "uneven96": {"workload": "96 slices, 256x256/360x512, 384x384/540x768 and "
+                                     "512x512/720x1024 in ratio 1:1:1, 10-40 objects, 0-3 "
+                                     "steel, UDM1-CG1, adaptive rho",
+                         **batch_workload(dect, torch, dev, batch_items["uneven"], params_b,
+                                          args.batch_steps, 2)},
+        }
     if args.calibrate_copy:
         src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)

@@ -205,6 +205,43 @@ dect_status dect_admm_iterate(const dect_plan* plan, const void* m_h, const void
                               const dect_params* params, int n_iters, dect_iter_log* log,
                               void* stream);
 
+/* Records of iterations [first, first + n) of a state, from its device log ring
+ * (the last 256 iterations are kept).  Synchronises the stream; DECT_E_ARG if
+ * a requested iteration has not run yet or has left the ring.  log: host array
+ * of n records. */
+dect_status dect_state_log(const dect_plan* plan, const void* state, int64_t first, int n,
+                           dect_iter_log* log, void* stream);
+
+/* ---------------------------------------------------------------- batch --- */
+
+/* Independent slices (Sec. 3.3 per slice: each detector row or table position
+ * is its own problem) advanced together.  A batch groups its slices by shape
+ * (image, views, bins); every kernel of an outer iteration is ONE launch per
+ * group, all slices of the group at once, and with use_graph one outer
+ * iteration of all groups is captured once into a HIP graph and replayed.  A
+ * slice's arithmetic and reduction order do not depend on the other slices:
+ * its state after k batch iterations is bitwise that of k dect_admm_iterate
+ * calls on it alone.
+ *
+ * plans[k], m_h[k] .. w_l[k], states[k]: slice k's plan, measurements and state
+ * (initialised by dect_admm_init); plans may repeat, states may not; all plans
+ * share one dtype.  params: fixed or adaptive rho (no schedule).  The batch
+ * keeps the pointers: every buffer must outlive it.  The batch owns small
+ * device argument tables and, with a graph, a private capture stream. */
+typedef struct dect_batch dect_batch;
+
+dect_status dect_batch_create(int n, const dect_plan* const* plans, const void* const* m_h,
+                              const void* const* m_l, const void* const* w_h,
+                              const void* const* w_l, void* const* states,
+                              const dect_params* params, int use_graph, dect_batch** out);
+/* n_iters outer iterations of every slice, enqueued on stream.  async.  While
+ * per-kernel timing is on (dect_profile_start) the kernels are launched
+ * directly instead of through the graph. */
+dect_status dect_batch_iterate(dect_batch* batch, int n_iters, void* stream);
+/* Number of shape groups (launches per kernel per iteration). */
+int dect_batch_groups(const dect_batch* batch);
+void dect_batch_destroy(dect_batch* batch);
+
 /* --------------------------------------------------------------- timing --- */
 
 /* Per-kernel timing for benchmarks: between dect_profile_start and

@@ -39,63 +39,61 @@ __global__ void k_set_scalars(double* s, double rc, double rp, double lc, double
 }
 
 // x += alpha p; with FULL also r -= alpha q and block partials of r.r.
-template <typename T, bool FULL>
-__global__ __launch_bounds__(256) void k_cg_step(long N, T* __restrict__ x, const T* __restrict__ p,
-                                                 T* __restrict__ r, const T* __restrict__ q,
-                                                 const double* __restrict__ scal,
-                                                 double* __restrict__ partials) {
+template <typename T, bool FULL, bool BATCH>
+__global__ __launch_bounds__(256) void k_cg_step(const VecArgs<T>* __restrict__ dev, VecArgs<T> one) {
     using V2 = vec<T, 2>;
+    const VecArgs<T> A = pick_args<BATCH>(dev, one);
+    if ((long)blockIdx.x * blockDim.x >= A.N) return;  // beyond this slice (whole block)
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    const T al[2] = {(T)scal[S_ALPHA], (T)scal[S_ALPHA + 1]};
+    const T al[2] = {(T)A.scal[S_ALPHA], (T)A.scal[S_ALPHA + 1]};
     double part[2] = {0.0, 0.0};
-    if (i < N) {
-        V2 xv = reinterpret_cast<V2*>(x)[i];
-        const V2 pv = reinterpret_cast<const V2*>(p)[i];
+    if (i < A.N) {
+        V2 xv = reinterpret_cast<V2*>(A.x)[i];
+        const V2 pv = reinterpret_cast<const V2*>(A.p)[i];
 #pragma unroll
         for (int c = 0; c < 2; ++c) xv.v[c] += al[c] * pv.v[c];
-        reinterpret_cast<V2*>(x)[i] = xv;
+        reinterpret_cast<V2*>(A.x)[i] = xv;
         if constexpr (FULL) {
-            V2 rv = reinterpret_cast<V2*>(r)[i];
-            const V2 qv = reinterpret_cast<const V2*>(q)[i];
+            V2 rv = reinterpret_cast<V2*>(A.r)[i];
+            const V2 qv = reinterpret_cast<const V2*>(A.q)[i];
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
                 rv.v[c] -= al[c] * qv.v[c];
                 part[c] = (double)rv.v[c] * (double)rv.v[c];
             }
-            reinterpret_cast<V2*>(r)[i] = rv;
+            reinterpret_cast<V2*>(A.r)[i] = rv;
         }
     }
-    if constexpr (FULL) block_sum_store<2>(part, partials + (size_t)blockIdx.x * kPartialSlots);
+    if constexpr (FULL) block_sum_store<2>(part, A.partials + (size_t)blockIdx.x * kPartialSlots);
 }
 
 // R x += alpha R p (tracking, so no extra projection of x is needed).
-template <typename T>
-__global__ __launch_bounds__(256) void k_rx_step(long M, int sym, int Vb, int D,
-                                                 T* __restrict__ Rx, const T* __restrict__ Rp,
-                                                 const double* __restrict__ scal) {
+template <typename T, bool BATCH>
+__global__ __launch_bounds__(256) void k_rx_step(const VecArgs<T>* __restrict__ dev, VecArgs<T> one) {
     using V2 = vec<T, 2>;
+    const VecArgs<T> A = pick_args<BATCH>(dev, one);
     const long l = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (l >= M) return;
-    const long i = std_ray(l, sym, Vb, D);
-    V2 a = reinterpret_cast<V2*>(Rx)[i];
-    const V2 b = reinterpret_cast<const V2*>(Rp)[l];
-    a.v[0] += (T)scal[S_ALPHA] * b.v[0];
-    a.v[1] += (T)scal[S_ALPHA + 1] * b.v[1];
-    reinterpret_cast<V2*>(Rx)[i] = a;
+    if (l >= A.M) return;
+    const long i = std_ray(l, A.sym, A.Vb, A.D);
+    V2 a = reinterpret_cast<V2*>(A.Rx)[i];
+    const V2 b = reinterpret_cast<const V2*>(A.Rp)[l];
+    a.v[0] += (T)A.scal[S_ALPHA] * b.v[0];
+    a.v[1] += (T)A.scal[S_ALPHA + 1] * b.v[1];
+    reinterpret_cast<V2*>(A.Rx)[i] = a;
 }
 
 // p = r + beta p.
-template <typename T>
-__global__ __launch_bounds__(256) void k_p_step(long N, T* __restrict__ p, const T* __restrict__ r,
-                                                const double* __restrict__ scal) {
+template <typename T, bool BATCH>
+__global__ __launch_bounds__(256) void k_p_step(const VecArgs<T>* __restrict__ dev, VecArgs<T> one) {
     using V2 = vec<T, 2>;
+    const VecArgs<T> A = pick_args<BATCH>(dev, one);
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    V2 a = reinterpret_cast<V2*>(p)[i];
-    const V2 b = reinterpret_cast<const V2*>(r)[i];
-    a.v[0] = b.v[0] + (T)scal[S_BETA] * a.v[0];
-    a.v[1] = b.v[1] + (T)scal[S_BETA + 1] * a.v[1];
-    reinterpret_cast<V2*>(p)[i] = a;
+    if (i >= A.N) return;
+    V2 a = reinterpret_cast<V2*>(A.p)[i];
+    const V2 b = reinterpret_cast<const V2*>(A.r)[i];
+    a.v[0] = b.v[0] + (T)A.scal[S_BETA] * a.v[0];
+    a.v[1] = b.v[1] + (T)A.scal[S_BETA + 1] * a.v[1];
+    reinterpret_cast<V2*>(A.p)[i] = a;
 }
 
 template <typename T>
@@ -107,16 +105,22 @@ __device__ inline T soft(T v, T t) {
 // y = shrink(D x - u^y, lambda/rho) (Eq. (9)), z = max(0, x - u^z) (Eq. (10)),
 // u^y += y - D x, u^z += z - x (Eq. (11)); dy, dz = changes of y, z.
 // Partials: |y - Dx|^2 + |z - x|^2 per basis, |y_c|_1, |y_p|_1.
-template <typename T>
-__global__ __launch_bounds__(256) void k_tv_dual(int nx, int ny, const T* __restrict__ x,
-                                                 T* __restrict__ y, T* __restrict__ uy,
-                                                 T* __restrict__ dy, T* __restrict__ z,
-                                                 T* __restrict__ uz, T* __restrict__ dz,
-                                                 const double* __restrict__ scal,
-                                                 double* __restrict__ partials) {
+template <typename T, bool BATCH>
+__global__ __launch_bounds__(256) void k_tv_dual(const TvArgs<T>* __restrict__ dev, TvArgs<T> one) {
     using V2 = vec<T, 2>;
     using V4 = vec<T, 4>;
+    const TvArgs<T> A = pick_args<BATCH>(dev, one);
+    const int nx = A.nx, ny = A.ny;
     const long N = (long)nx * ny;
+    if ((long)blockIdx.x * blockDim.x >= N) return;  // beyond this slice (whole block)
+    const T* __restrict__ x = A.x;
+    T* __restrict__ y = A.y;
+    T* __restrict__ uy = A.uy;
+    T* __restrict__ dy = A.dy;
+    T* __restrict__ z = A.z;
+    T* __restrict__ uz = A.uz;
+    T* __restrict__ dz = A.dz;
+    const double* __restrict__ scal = A.scal;
     const long pix = (long)blockIdx.x * blockDim.x + threadIdx.x;
     double part[4] = {0.0, 0.0, 0.0, 0.0};
     if (pix < N) {
@@ -169,20 +173,26 @@ __global__ __launch_bounds__(256) void k_tv_dual(int nx, int ny, const T* __rest
         reinterpret_cast<V2*>(uz)[pix] = w;
         reinterpret_cast<V2*>(dz)[pix] = dzv;
     }
-    block_sum_store<4>(part, partials + (size_t)blockIdx.x * kPartialSlots);
+    block_sum_store<4>(part, A.partials + (size_t)blockIdx.x * kPartialSlots);
 }
 
 // Scaled duals follow rho: u *= rho_old / rho_new, and t = a + u^a - R x again.
-template <typename T>
-__global__ __launch_bounds__(256) void k_rescale(long M, long N, int sym, int Vb, int D,
-                                                 T* __restrict__ ua, T* __restrict__ t,
-                                                 const T* __restrict__ a,
-                                                 const T* __restrict__ Rx, T* __restrict__ uy,
-                                                 T* __restrict__ uz,
-                                                 const double* __restrict__ scal) {
+template <typename T, bool BATCH>
+__global__ __launch_bounds__(256) void k_rescale(const RescaleArgs<T>* __restrict__ dev,
+                                                 RescaleArgs<T> one) {
     using V2 = vec<T, 2>;
     using V4 = vec<T, 4>;
-    const double k0 = scal[S_KAPPA], k1 = scal[S_KAPPA + 1];
+    const RescaleArgs<T> A = pick_args<BATCH>(dev, one);
+    const long M = A.M, N = A.N;
+    const int sym = A.sym, Vb = A.Vb, D = A.D;
+    T* __restrict__ ua = A.ua;
+    T* __restrict__ t = A.t;
+    const T* __restrict__ a = A.a;
+    const T* __restrict__ Rx = A.Rx;
+    T* __restrict__ uy = A.uy;
+    T* __restrict__ uz = A.uz;
+    if ((long)blockIdx.x * blockDim.x >= (M > N ? M : N)) return;
+    const double k0 = A.scal[S_KAPPA], k1 = A.scal[S_KAPPA + 1];
     if (k0 == 1.0 && k1 == 1.0) return;
     const T kc[2] = {(T)k0, (T)k1};
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -212,21 +222,6 @@ __global__ __launch_bounds__(256) void k_rescale(long M, long N, int sym, int Vb
     }
 }
 
-struct RedArgs {
-    const double* tiles;
-    int nb_tiles;
-    const double* img;
-    int nb_img;
-    const double* sino;
-    int nb_sino;
-    double* scal;
-    double* log;
-    int mode;
-    int rho_mode;
-    int dual;  // dual-residual partials present
-    double bal_mu, bal_tau, next_rho_c, next_rho_p;
-};
-
 // Fixed-order sum of K slots over nb block partials; the result reaches all threads.
 template <int K>
 __device__ inline void section_sum(const double* base, int nb, double (&out)[K]) {
@@ -244,16 +239,20 @@ __device__ inline void section_sum(const double* base, int nb, double (&out)[K])
     __syncthreads();
 }
 
-__global__ __launch_bounds__(256) void k_reduce(RedArgs A) {
+template <bool BATCH>
+__global__ __launch_bounds__(256) void k_reduce(const RedArgs* __restrict__ dev, RedArgs one,
+                                                int mode) {
+    const RedArgs A = pick_args<BATCH>(dev, one);
     double* s = A.scal;
-    if (A.mode == RED_GAMMA) {
+    if (!s) return;  // empty slot
+    if (mode == RED_GAMMA) {
         double g[2];
         section_sum<2>(A.tiles, A.nb_tiles, g);
         if (threadIdx.x == 0) {
             s[S_GAMMA] = g[0];
             s[S_GAMMA + 1] = g[1];
         }
-    } else if (A.mode == RED_ALPHA) {
+    } else if (mode == RED_ALPHA) {
         double pq[2];
         section_sum<2>(A.tiles, A.nb_tiles, pq);
         if (threadIdx.x == 0)
@@ -261,7 +260,7 @@ __global__ __launch_bounds__(256) void k_reduce(RedArgs A) {
                 s[S_PQ + c] = pq[c];
                 s[S_ALPHA + c] = (pq[c] > 0.0 && s[S_GAMMA + c] > 0.0) ? s[S_GAMMA + c] / pq[c] : 0.0;
             }
-    } else if (A.mode == RED_BETA) {
+    } else if (mode == RED_BETA) {
         double g[2];
         section_sum<2>(A.img, A.nb_img, g);
         if (threadIdx.x == 0)
@@ -324,10 +323,11 @@ T* at(void* base, size_t off) {
 
 unsigned nblk(long n) { return (unsigned)((n + 255) / 256); }
 
+}  // namespace
+
 template <typename T>
-dect_status iterate_T(const dect_plan* p, const void* mh, const void* ml, const void* wh,
-                      const void* wl, void* st, const dect_params* prm, int n_iters,
-                      dect_iter_log* log, hipStream_t s) {
+SliceJob<T> make_job(const dect_plan* p, const void* mh, const void* ml, const void* wh,
+                     const void* wl, void* st, const dect_params* prm) {
     const dect_layout& L = p->layout;
     T* x = at<T>(st, L.x);
     T* y = at<T>(st, L.y);
@@ -349,12 +349,173 @@ dect_status iterate_T(const dect_plan* p, const void* mh, const void* ml, const 
     T* t = at<T>(st, p->off_t);
     T* da = at<T>(st, p->off_da);
     double* part = at<double>(st, p->off_partials);
-    Partials P{part, part + (size_t)p->nb_sino * kPartialSlots,
-               part + (size_t)(p->nb_sino + p->nb_img) * kPartialSlots};
-    double* dlog = at<double>(st, p->off_log);
+    const Partials P{part, part + (size_t)p->nb_sino * kPartialSlots,
+                     part + (size_t)(p->nb_sino + p->nb_img) * kPartialSlots};
+    const int n = prm->cg_iters;
+
+    SliceJob<T> J{};
+    J.N = p->N;
+    J.M = p->M;
+    J.sym = p->sym;
+    J.pj_gx = (p->D + 63) / 64;
+    J.pj_gy = p->Vb;
+    J.orb = OrbitArgs<T>{pp, pO, pOT, p->nx, p->ny};
+    J.prj = ProjArgs<T>{static_cast<const RayParam<T>*>(p->rays), pO, pOT, Rp, p->nx, p->ny,
+                        p->Vb, p->D};
+    // Right-hand side of Eq. (12) and the initial CG residual.
+    BpArgs<T> b{};
+    fill_bp_plan<T>(p, b);
+    J.bp_gx = b.gx;
+    J.bp_gy = b.gy;
+    b.partials = P.tiles;
+    J.rhs = b;
+    J.rhs.sino = t;
+    J.rhs.out = pp;
+    J.rhs.out2 = n > 1 ? r : nullptr;
+    J.rhs.x = x;
+    J.rhs.y = y;
+    J.rhs.uy = uy;
+    J.rhs.z = z;
+    J.rhs.uz = uz;
+    // (R^T R + D^T D + I) p and p . q
+    J.q = b;
+    J.q.sino = Rp;
+    J.q.out = n > 1 ? q : nullptr;
+    J.q.x = pp;
+    // Dual residual R^T da + D^T dy + dz
+    J.dual = b;
+    J.dual.sino = da;
+    J.dual.y = dy;
+    J.dual.z = dz;
+    // a-update (Eq. (13)) fused with R x += alpha R p, u^a and the next t.
+    UdmArgs<T>& u = J.udm;
+    fill_udm_tables<T>(p, u);
+    u.M = p->M;
+    u.sym = p->sym;
+    u.Vb = p->Vb;
+    u.D = p->D;
+    u.mh = static_cast<const T*>(mh);
+    u.ml = static_cast<const T*>(ml);
+    u.wh = static_cast<const T*>(wh);
+    u.wl = static_cast<const T*>(wl);
+    u.a = a;
+    u.ua = ua;
+    u.Rx = Rx;
+    u.Rp = Rp;
+    u.t = t;
+    u.da = da;
+    u.fg = at<T>(st, p->off_fg);
+    u.scal = scal;
+    u.partials = P.sino;
+    u.iters = prm->lm_iters;
+    u.mu0 = prm->lm_mu0;
+    J.vec = VecArgs<T>{p->N, p->M, p->sym, p->Vb, p->D, x, pp, r, q, Rx, Rp, scal, P.img};
+    J.tv = TvArgs<T>{p->nx, p->ny, x, y, uy, dy, z, uz, dz, scal, P.img};
+    J.resc = RescaleArgs<T>{p->M, p->N, p->sym, p->Vb, p->D, ua, t, a, Rx, uy, uz, scal};
+    J.red = RedArgs{P.tiles, p->nb_tiles, P.img, p->nb_img, P.sino, p->nb_sino, scal,
+                    at<double>(st, p->off_log), prm->rho_mode,
+                    prm->rho_mode == DECT_RHO_ADAPTIVE ? 1 : 0, prm->bal_mu, prm->bal_tau,
+                    0.0, 0.0};
+    return J;
+}
+
+namespace {
+
+template <typename T, bool BATCH>
+hipError_t iteration_t(const SliceJob<T>& J, const JobArrays<T>* dev, int nsl,
+                       const dect_params* prm, long it, hipStream_t s) {
     const int n = prm->cg_iters;
     const bool adaptive = prm->rho_mode == DECT_RHO_ADAPTIVE;
+    const unsigned z = (unsigned)nsl;
+    auto reduce = [&](int mode) -> hipError_t {
+        RedArgs A = J.red;
+        if (mode == RED_FINAL && prm->rho_mode == DECT_RHO_SCHEDULE) {
+            A.next_rho_c = prm->rho_schedule[2 * (it + 1)];
+            A.next_rho_p = prm->rho_schedule[2 * (it + 1) + 1];
+        }
+        ProfScope ps("reduce", s);
+        hipLaunchKernelGGL(k_reduce<BATCH>, dim3(1, 1, z), dim3(256), 0, s,
+                           dev ? dev->red : nullptr, A, mode);
+        return hipGetLastError();
+    };
+#define DECT_TRY(e)                          \
+    do {                                     \
+        hipError_t e_ = (e);                 \
+        if (e_ != hipSuccess) return e_;     \
+    } while (0)
+    const dim3 gN(nblk(J.N), 1, z), gM(nblk(J.M), 1, z);
+    const VecArgs<T>* dvec = dev ? dev->vec : nullptr;
+    DECT_TRY(launch_backproject_admm<T>(J.sym, EPI_RHS, dev ? dev->rhs : nullptr, J.rhs, nsl,
+                                        J.bp_gx, J.bp_gy, s));
+    DECT_TRY(reduce(RED_GAMMA));
+    for (int c = 0; c < n; ++c) {
+        DECT_TRY(launch_project_pair<T>(J.sym, dev ? dev->orb : nullptr, J.orb,
+                                        dev ? dev->prj : nullptr, J.prj, nsl, J.N, J.pj_gx,
+                                        J.pj_gy, s));
+        DECT_TRY(launch_backproject_admm<T>(J.sym, EPI_Q, dev ? dev->q : nullptr, J.q, nsl,
+                                            J.bp_gx, J.bp_gy, s));
+        DECT_TRY(reduce(RED_ALPHA));
+        if (c < n - 1) {
+            ProfScope ps("cg_vector", s);
+            hipLaunchKernelGGL((k_rx_step<T, BATCH>), gM, dim3(256), 0, s, dvec, J.vec);
+            hipLaunchKernelGGL((k_cg_step<T, true, BATCH>), gN, dim3(256), 0, s, dvec, J.vec);
+            DECT_TRY(reduce(RED_BETA));
+            hipLaunchKernelGGL((k_p_step<T, BATCH>), gN, dim3(256), 0, s, dvec, J.vec);
+        } else {
+            ProfScope ps("cg_vector", s);
+            hipLaunchKernelGGL((k_cg_step<T, false, BATCH>), gN, dim3(256), 0, s, dvec, J.vec);
+        }
+        DECT_TRY(hipGetLastError());
+    }
+    if (dev)
+        DECT_TRY(launch_udm_batch<T>(dev->udm, nsl, (int)nblk(J.M), s));
+    else
+        DECT_TRY(launch_udm<T>(nullptr, 2, J.udm, s));
+    {
+        ProfScope ps("tv_dual", s);
+        hipLaunchKernelGGL((k_tv_dual<T, BATCH>), gN, dim3(256), 0, s, dev ? dev->tv : nullptr, J.tv);
+    }
+    DECT_TRY(hipGetLastError());
+    if (adaptive)
+        DECT_TRY(launch_backproject_admm<T>(J.sym, EPI_DUAL, dev ? dev->dual : nullptr, J.dual,
+                                            nsl, J.bp_gx, J.bp_gy, s));
+    DECT_TRY(reduce(RED_FINAL));
+    if (prm->rho_mode != DECT_RHO_FIXED) {
+        ProfScope ps("rescale", s);
+        hipLaunchKernelGGL((k_rescale<T, BATCH>), dim3(nblk(J.M > J.N ? J.M : J.N), 1, z), dim3(256), 0,
+                           s, dev ? dev->resc : nullptr, J.resc);
+        DECT_TRY(hipGetLastError());
+    }
+#undef DECT_TRY
+    return hipSuccess;
+}
 
+}  // namespace
+
+template <typename T>
+hipError_t launch_iteration(const SliceJob<T>& J, const JobArrays<T>* dev, int nsl,
+                            const dect_params* prm, long it, hipStream_t s) {
+    return dev ? iteration_t<T, true>(J, dev, nsl, prm, it, s)
+               : iteration_t<T, false>(J, dev, nsl, prm, it, s);
+}
+
+#define DECT_INST(T)                                                                            \
+    template SliceJob<T> make_job<T>(const dect_plan*, const void*, const void*, const void*,    \
+                                     const void*, void*, const dect_params*);                    \
+    template hipError_t launch_iteration<T>(const SliceJob<T>&, const JobArrays<T>*, int,        \
+                                            const dect_params*, long, hipStream_t);
+DECT_INST(float)
+DECT_INST(double)
+#undef DECT_INST
+
+namespace {
+
+template <typename T>
+dect_status iterate_T(const dect_plan* p, const void* mh, const void* ml, const void* wh,
+                      const void* wl, void* st, const dect_params* prm, int n_iters,
+                      dect_iter_log* log, hipStream_t s) {
+    double* scal = at<double>(st, p->layout.scalars);
+    double* dlog = at<double>(st, p->off_log);
     long it0 = 0;
     if (prm->rho_mode == DECT_RHO_SCHEDULE || log) {
         DECT_HIP(hipStreamSynchronize(s));
@@ -366,114 +527,12 @@ dect_status iterate_T(const dect_plan* p, const void* mh, const void* ml, const 
         (!prm->rho_schedule || it0 + n_iters >= (long)prm->rho_schedule_len))
         return fail(DECT_E_ARG, "rho schedule of length %d does not reach iteration %ld",
                     prm->rho_schedule_len, it0 + n_iters);
-
-    RedArgs R{P.tiles, p->nb_tiles, P.img, p->nb_img, P.sino, p->nb_sino, scal, dlog, 0,
-              prm->rho_mode, adaptive ? 1 : 0, prm->bal_mu, prm->bal_tau, 0.0, 0.0};
-    auto reduce = [&](int mode, long it) -> hipError_t {
-        RedArgs A = R;
-        A.mode = mode;
-        if (mode == RED_FINAL && prm->rho_mode == DECT_RHO_SCHEDULE) {
-            A.next_rho_c = prm->rho_schedule[2 * (it + 1)];
-            A.next_rho_p = prm->rho_schedule[2 * (it + 1) + 1];
-        }
-        ProfScope ps("reduce", s);
-        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, A);
-        return hipGetLastError();
-    };
-#define DECT_OK_OR(e)                                                                    \
-    do {                                                                                 \
-        hipError_t e_ = (e);                                                             \
-        if (e_ != hipSuccess)                                                            \
-            return fail(DECT_E_DEVICE, "launch failed: %s (%s:%d)", hipGetErrorString(e_), \
-                        __FILE__, __LINE__);                                             \
-    } while (0)
-
+    const SliceJob<T> J = make_job<T>(p, mh, ml, wh, wl, st, prm);
     for (int k = 0; k < n_iters; ++k) {
-        const long it = it0 + k;
-        // Right-hand side of Eq. (12) and the initial CG residual.
-        BpArgs<T> b{};
-        b.sino = t;
-        b.out = pp;
-        b.out2 = n > 1 ? r : nullptr;
-        b.x = x;
-        b.y = y;
-        b.uy = uy;
-        b.z = z;
-        b.uz = uz;
-        b.partials = P.tiles;
-        DECT_OK_OR(launch_backproject<T>(p, 2, EPI_RHS, b, s));
-        DECT_OK_OR(reduce(RED_GAMMA, it));
-        for (int c = 0; c < n; ++c) {
-            DECT_OK_OR(launch_project_pair<T>(p, pp, pO, pOT, Rp, s));
-            BpArgs<T> bq{};
-            bq.sino = Rp;
-            bq.out = n > 1 ? q : nullptr;
-            bq.x = pp;
-            bq.partials = P.tiles;
-            DECT_OK_OR(launch_backproject<T>(p, 2, EPI_Q, bq, s));
-            DECT_OK_OR(reduce(RED_ALPHA, it));
-            if (c < n - 1) {
-                ProfScope ps("cg_vector", s);
-                hipLaunchKernelGGL((k_rx_step<T>), dim3(nblk(p->M)), dim3(256), 0, s, p->M,
-                                   p->sym, p->Vb, p->D, Rx, Rp, scal);
-                hipLaunchKernelGGL((k_cg_step<T, true>), dim3(nblk(p->N)), dim3(256), 0, s,
-                                   p->N, x, pp, r, q, scal, P.img);
-                DECT_OK_OR(reduce(RED_BETA, it));
-                hipLaunchKernelGGL((k_p_step<T>), dim3(nblk(p->N)), dim3(256), 0, s, p->N, pp,
-                                   r, scal);
-            } else {
-                ProfScope ps("cg_vector", s);
-                hipLaunchKernelGGL((k_cg_step<T, false>), dim3(nblk(p->N)), dim3(256), 0, s,
-                                   p->N, x, pp, r, q, scal, P.img);
-            }
-            DECT_OK_OR(hipGetLastError());
-        }
-        // a-update (Eq. (13)) fused with R x += alpha R p, u^a and the next t.
-        UdmArgs<T> u{};
-        u.M = p->M;
-        u.sym = p->sym;
-        u.Vb = p->Vb;
-        u.D = p->D;
-        u.mh = static_cast<const T*>(mh);
-        u.ml = static_cast<const T*>(ml);
-        u.wh = static_cast<const T*>(wh);
-        u.wl = static_cast<const T*>(wl);
-        u.a = a;
-        u.ua = ua;
-        u.Rx = Rx;
-        u.Rp = Rp;
-        u.t = t;
-        u.da = da;
-        u.fg = at<T>(st, p->off_fg);
-        u.scal = scal;
-        u.partials = P.sino;
-        u.iters = prm->lm_iters;
-        u.mu0 = prm->lm_mu0;
-        DECT_OK_OR(launch_udm<T>(p, 2, u, s));
-        {
-            ProfScope ps("tv_dual", s);
-            hipLaunchKernelGGL((k_tv_dual<T>), dim3(nblk(p->N)), dim3(256), 0, s, p->nx, p->ny, x,
-                               y, uy, dy, z, uz, dz, scal, P.img);
-        }
-        DECT_OK_OR(hipGetLastError());
-        if (adaptive) {
-            BpArgs<T> bd{};
-            bd.sino = da;
-            bd.y = dy;
-            bd.z = dz;
-            bd.partials = P.tiles;
-            DECT_OK_OR(launch_backproject<T>(p, 2, EPI_DUAL, bd, s));
-        }
-        DECT_OK_OR(reduce(RED_FINAL, it));
-        if (prm->rho_mode != DECT_RHO_FIXED) {
-            const long nmax = p->M > p->N ? p->M : p->N;
-            ProfScope ps("rescale", s);
-            hipLaunchKernelGGL((k_rescale<T>), dim3(nblk(nmax)), dim3(256), 0, s, p->M, p->N,
-                               p->sym, p->Vb, p->D, ua, t, a, Rx, uy, uz, scal);
-            DECT_OK_OR(hipGetLastError());
-        }
+        const hipError_t e = launch_iteration<T>(J, nullptr, 1, prm, it0 + k, s);
+        if (e != hipSuccess)
+            return fail(DECT_E_DEVICE, "launch failed: %s", hipGetErrorString(e));
     }
-#undef DECT_OK_OR
     if (log) {
         DECT_HIP(hipStreamSynchronize(s));
         std::vector<double> h((size_t)kLogCap * kLogStride);
@@ -578,12 +637,12 @@ dect_status dect_backproject(const dect_plan* p, const void* sino, void* img, in
         BpArgs<float> a{};
         a.sino = static_cast<const float*>(sino);
         a.out = static_cast<float*>(img);
-        e = launch_backproject<float>(p, ch, EPI_NONE, a, s);
+        e = launch_backproject<float>(p, ch, a, s);
     } else {
         BpArgs<double> a{};
         a.sino = static_cast<const double*>(sino);
         a.out = static_cast<double*>(img);
-        e = launch_backproject<double>(p, ch, EPI_NONE, a, s);
+        e = launch_backproject<double>(p, ch, a, s);
     }
     if (e != hipSuccess) return fail(DECT_E_DEVICE, "launch failed: %s", hipGetErrorString(e));
     return DECT_OK;
@@ -681,6 +740,40 @@ dect_status dect_admm_iterate(const dect_plan* p, const void* m_h, const void* m
     return p->dtype == DECT_F32
                ? iterate_T<float>(p, m_h, m_l, w_h, w_l, state, prm, n_iters, log, s)
                : iterate_T<double>(p, m_h, m_l, w_h, w_l, state, prm, n_iters, log, s);
+}
+
+dect_status dect_state_log(const dect_plan* p, const void* state, int64_t first, int n,
+                           dect_iter_log* log, void* stream) {
+    if (!p || !state || (!log && n > 0)) return fail(DECT_E_ARG, "null argument");
+    if (n < 0 || first < 0) return fail(DECT_E_ARG, "first and n must be >= 0");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    DECT_HIP(hipStreamSynchronize(s));
+    const char* base = static_cast<const char*>(state);
+    double done = 0.0;
+    DECT_HIP(hipMemcpy(&done, base + p->layout.scalars + S_ITER * sizeof(double), sizeof done,
+                       hipMemcpyDeviceToHost));
+    const int64_t it_done = (int64_t)done;
+    if (first + n > it_done || first < it_done - kLogCap)
+        return fail(DECT_E_ARG, "iterations [%lld, %lld) are not in the log (%lld done, last %d kept)",
+                    (long long)first, (long long)(first + n), (long long)it_done, kLogCap);
+    std::vector<double> h((size_t)kLogCap * kLogStride);
+    DECT_HIP(hipMemcpy(h.data(), base + p->off_log, h.size() * sizeof(double),
+                       hipMemcpyDeviceToHost));
+    for (int k = 0; k < n; ++k) {
+        const double* e = &h[(size_t)((first + k) % kLogCap) * kLogStride];
+        dect_iter_log& o = log[k];
+        o.iter = (int32_t)e[0];
+        o.flags = (int32_t)e[1];
+        o.rho[0] = e[2];
+        o.rho[1] = e[3];
+        o.r_primal[0] = e[4];
+        o.r_primal[1] = e[5];
+        o.s_dual[0] = e[6];
+        o.s_dual[1] = e[7];
+        o.data_cost = e[8];
+        o.tv_cost = e[9];
+    }
+    return DECT_OK;
 }
 
 }  // extern "C"

@@ -13,11 +13,51 @@ enum Epilogue : int { EPI_NONE = 0, EPI_RHS = 1, EPI_Q = 2, EPI_DUAL = 3 };
 //            partials = per-channel |out|^2
 //  EPI_Q   : out (if set) = R^T sino + D^T D x + x, with x = p; partials = p . out
 //  EPI_DUAL: y = dy, z = dz; partials = |R^T sino + D^T dy + dz|^2
+// Every kernel takes its per-slice arguments either by value (BATCH = false: one
+// slice) or as a device array indexed by blockIdx.z (BATCH = true: several
+// slices of one shape in one launch).  The array is read word by word through
+// the constant address space, so the block-uniform loads go through the scalar
+// unit into SGPRs, as a by-value argument does.  The single-slice kernels are
+// separate instantiations that never touch the array.
+template <bool BATCH, typename A>
+__device__ inline A pick_args(const A* __restrict__ dev, const A& one) {
+    static_assert(sizeof(A) % 4 == 0 && alignof(A) >= 4, "argument blocks are whole words");
+    if constexpr (!BATCH) {
+        return one;
+    } else {
+        using CW = const __attribute__((address_space(4))) uint32_t;
+        CW* src = (CW*)(dev + blockIdx.z);
+        A out;
+        uint32_t* dst = reinterpret_cast<uint32_t*>(&out);
+#pragma unroll
+        for (unsigned k = 0; k < sizeof(A) / 4; ++k) dst[k] = src[k];
+        return out;
+    }
+}
+
+template <typename T>
+struct OrbitArgs {
+    const T* X;   // [ny][nx][ch]
+    T* O;         // orbit image [ny][nx][ch * sym]
+    T* OT;        // its transpose [nx][ny][ch * sym]
+    int nx, ny;
+};
+
+template <typename T>
+struct ProjArgs {
+    const RayParam<T>* rays;
+    const T* O;
+    const T* OT;
+    T* sino;
+    int nx, ny, Vb, D;
+};
+
 template <typename T>
 struct BpArgs {
     const RayParam<T>* rays;
     const ViewParam<T>* views;
     int nx, ny, V, Vb, D;
+    int gx, gy;   // this slice's grid of 8x8 orbit blocks
     double margin;
     const T* sino;
     T* out;
@@ -50,18 +90,30 @@ __device__ inline void block_sum_store(double (&v)[K], double* out) {
 
 template <typename T>
 hipError_t launch_project(const dect_plan* p, const void* img, void* sino, int ch, hipStream_t s);
-// Two-channel projection of the ADMM direction into quad-interleaved records;
-// O and OT are orbit-image scratch of N * 2 * sym elements each.
+// Two-channel projection of the ADMM direction into quad-interleaved records, for
+// one slice (dev == nullptr: `one`) or n slices (dev: device arrays); the grid is
+// (gx, gy) projector blocks and `pixels` orbit-image threads per slice.
 template <typename T>
-hipError_t launch_project_pair(const dect_plan* p, const void* img, void* O, void* OT,
-                               void* sino, hipStream_t s);
+hipError_t launch_project_pair(int sym, const OrbitArgs<T>* odev, const OrbitArgs<T>& oone,
+                               const ProjArgs<T>* pdev, const ProjArgs<T>& pone, int n,
+                               long pixels, int gx, int gy, hipStream_t s);
+// Plain R^T of a standard-order sinogram with ch channels (one slice).
 template <typename T>
-hipError_t launch_backproject(const dect_plan* p, int ch, int epi, const BpArgs<T>& a,
-                              hipStream_t s);
+hipError_t launch_backproject(const dect_plan* p, int ch, const BpArgs<T>& a, hipStream_t s);
+// ADMM epilogue variants of R^T on quad records, one or n slices.
+template <typename T>
+hipError_t launch_backproject_admm(int sym, int epi, const BpArgs<T>* dev, const BpArgs<T>& one,
+                                   int n, int gx, int gy, hipStream_t s);
+// Fill the plan-dependent fields of BpArgs.
+template <typename T>
+void fill_bp_plan(const dect_plan* p, BpArgs<T>& a);
 
 // Per-ray decomposition.  mode 0: standalone call; 1: ADMM initialisation; 2: ADMM a-step.
 template <typename T>
 struct UdmArgs {
+    const T* spec;     // spectral tables (plan)
+    int kmax, kh, kl;
+    float kc_max, kp_max;
     long M;
     int sym, Vb, D;  // internal (quad) ray order of t, da, Rp; sym = 1: standard order
     const T* mh;
@@ -87,7 +139,114 @@ struct UdmArgs {
 };
 
 template <typename T>
+void fill_udm_tables(const dect_plan* p, UdmArgs<T>& a);
+// p: plan whose spectral tables are filled into a (nullptr: a carries them).
+template <typename T>
 hipError_t launch_udm(const dect_plan* p, int mode, const UdmArgs<T>& a, hipStream_t s);
+// Batched a-step over n slices (args: device array), grid of `blocks` x n.
+template <typename T>
+hipError_t launch_udm_batch(const UdmArgs<T>* args, int n, int blocks, hipStream_t s);
+// Image-vector CG steps: x += alpha p, r -= alpha q, p = r + beta p, R x += alpha R p.
+template <typename T>
+struct VecArgs {
+    long N, M;
+    int sym, Vb, D;
+    T* x;
+    T* p;
+    T* r;
+    const T* q;
+    T* Rx;
+    const T* Rp;
+    const double* scal;
+    double* partials;   // image partials
+};
+
+// Shrinkage, nonnegativity and the y, z duals (Eq. (9)-(11)).
+template <typename T>
+struct TvArgs {
+    int nx, ny;
+    const T* x;
+    T* y;
+    T* uy;
+    T* dy;
+    T* z;
+    T* uz;
+    T* dz;
+    const double* scal;
+    double* partials;
+};
+
+// Dual rescale after a change of rho.
+template <typename T>
+struct RescaleArgs {
+    long M, N;
+    int sym, Vb, D;
+    T* ua;
+    T* t;
+    const T* a;
+    const T* Rx;
+    T* uy;
+    T* uz;
+    const double* scal;
+};
+
+// Fixed-order reductions of block partials and the scalar updates (one block per
+// slice).  scal == nullptr marks an empty slot.
+struct RedArgs {
+    const double* tiles;
+    int nb_tiles;
+    const double* img;
+    int nb_img;
+    const double* sino;
+    int nb_sino;
+    double* scal;
+    double* log;
+    int rho_mode;
+    int dual;  // dual-residual partials present
+    double bal_mu, bal_tau, next_rho_c, next_rho_p;
+};
+
+// Every argument block of one slice's outer iteration, and its launch extents.
+template <typename T>
+struct SliceJob {
+    OrbitArgs<T> orb;
+    ProjArgs<T> prj;
+    BpArgs<T> rhs, q, dual;
+    UdmArgs<T> udm;
+    VecArgs<T> vec;
+    TvArgs<T> tv;
+    RescaleArgs<T> resc;
+    RedArgs red;
+    long N, M;
+    int sym, bp_gx, bp_gy, pj_gx, pj_gy;
+};
+
+// Device copies of the argument blocks of n slices of one shape, in slice order.
+template <typename T>
+struct JobArrays {
+    OrbitArgs<T>* orb;
+    ProjArgs<T>* prj;
+    BpArgs<T>* rhs;
+    BpArgs<T>* q;
+    BpArgs<T>* dual;
+    UdmArgs<T>* udm;
+    VecArgs<T>* vec;
+    TvArgs<T>* tv;
+    RescaleArgs<T>* resc;
+    RedArgs* red;
+};
+
+// The argument blocks of one slice for its plan, measurements and state.
+template <typename T>
+SliceJob<T> make_job(const dect_plan* p, const void* mh, const void* ml, const void* wh,
+                     const void* wl, void* st, const dect_params* prm);
+// Enqueue one outer iteration on s: of `one` (dev == nullptr) or of n slices of the
+// same shape as `one` whose argument blocks are in dev.  it: iteration index (for
+// a rho schedule, single slice only).
+template <typename T>
+hipError_t launch_iteration(const SliceJob<T>& one, const JobArrays<T>* dev, int n,
+                            const dect_params* prm, long it, hipStream_t s);
+
 template <typename T>
 hipError_t launch_ingest(const dect_plan* p, const void* ch, const void* cl, double i0h,
                          double i0l, void* mh, void* ml, void* wh, void* wl, hipStream_t s);

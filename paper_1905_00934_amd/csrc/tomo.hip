@@ -48,10 +48,13 @@ __device__ inline void rot(int k, int n, int i, int j, int& io, int& jo) {
 
 // Orbit image (TR = false: O[j][i]; TR = true: its transpose OT[i][j]) with
 // component k*CH + c = channel c of X at rot^k(i, j).  SYM = 1 gives X or X^T.
-template <typename T, int CH, int SYM, bool TR>
-__global__ __launch_bounds__(256) void k_orbit(const vec<T, CH>* __restrict__ X,
-                                               vec<T, CH * SYM>* __restrict__ out, int nx,
-                                               int ny) {
+template <typename T, int CH, int SYM, bool TR, bool BATCH>
+__global__ __launch_bounds__(256) void k_orbit(const OrbitArgs<T>* __restrict__ dev,
+                                               OrbitArgs<T> one) {
+    const OrbitArgs<T> A = pick_args<BATCH>(dev, one);
+    const int nx = A.nx, ny = A.ny;
+    const vec<T, CH>* __restrict__ X = reinterpret_cast<const vec<T, CH>*>(A.X);
+    vec<T, CH * SYM>* __restrict__ out = reinterpret_cast<vec<T, CH * SYM>*>(TR ? A.OT : A.O);
     const int lines = TR ? nx : ny, len = TR ? ny : nx;
     const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (long)lines * len) return;
@@ -74,14 +77,18 @@ __global__ __launch_bounds__(256) void k_orbit(const vec<T, CH>* __restrict__ X,
 // 64 consecutive bins of one base view; its KS waves step through KS disjoint
 // ranges of image lines (so the lanes of a wave read one image line together)
 // and wave 0 adds the KS partial sums in order.
-template <typename T, int CH, int SYM, bool QUAD, int KS>
-__global__ __launch_bounds__(64 * KS) void k_project(const RayParam<T>* __restrict__ rays,
-                                                     const vec<T, CH * SYM>* __restrict__ O,
-                                                     const vec<T, CH * SYM>* __restrict__ OT,
-                                                     T* __restrict__ sino, int nx, int ny, int Vb,
-                                                     int D) {
+template <typename T, int CH, int SYM, bool QUAD, int KS, bool BATCH>
+__global__ __launch_bounds__(64 * KS) void k_project(const ProjArgs<T>* __restrict__ dev,
+                                                     ProjArgs<T> one) {
     constexpr int W = CH * SYM;
     __shared__ T red[KS > 1 ? KS - 1 : 1][64][W];
+    const ProjArgs<T> A = pick_args<BATCH>(dev, one);
+    const int nx = A.nx, ny = A.ny, Vb = A.Vb, D = A.D;
+    if ((int)blockIdx.x * 64 >= D || (int)blockIdx.y >= Vb) return;  // beyond this slice
+    const RayParam<T>* __restrict__ rays = A.rays;
+    const vec<T, W>* __restrict__ O = reinterpret_cast<const vec<T, W>*>(A.O);
+    const vec<T, W>* __restrict__ OT = reinterpret_cast<const vec<T, W>*>(A.OT);
+    T* __restrict__ sino = A.sino;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int v = blockIdx.y;
@@ -346,9 +353,12 @@ __device__ inline void epilogue(const BpArgs<T>& a, int i, int j, T (&res)[2], d
 // R^T (+ epilogue).  A workgroup owns an 8x8 block of pixel orbits (the block
 // lies in the first quadrant when SYM = 4) and has VS waves, each summing a
 // disjoint subset of the base views; wave 0 adds the others' sums in order.
-template <typename T, int CH, int SYM, bool QUAD, int EPI, int VS>
-__global__ __launch_bounds__(64 * VS) void k_backproject(BpArgs<T> a) {
+template <typename T, int CH, int SYM, bool QUAD, int EPI, int VS, bool BATCH>
+__global__ __launch_bounds__(64 * VS) void k_backproject(const BpArgs<T>* __restrict__ dev,
+                                                         BpArgs<T> one) {
     __shared__ T red[VS > 1 ? VS - 1 : 1][64][SYM * CH];
+    const BpArgs<T> a = pick_args<BATCH>(dev, one);
+    if ((int)blockIdx.x >= a.gx || (int)blockIdx.y >= a.gy) return;  // beyond this slice
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int i = blockIdx.x * 8 + (lane & 7);
@@ -398,7 +408,7 @@ __global__ __launch_bounds__(64 * VS) void k_backproject(BpArgs<T> a) {
         for (int c = 0; c < 2; ++c)
             for (int off = 32; off > 0; off >>= 1) part[c] += __shfl_down(part[c], off, 64);
         if (lane == 0) {
-            double* o = a.partials + (size_t)(blockIdx.y * gridDim.x + blockIdx.x) * kPartialSlots;
+            double* o = a.partials + (size_t)(blockIdx.y * a.gx + blockIdx.x) * kPartialSlots;
             o[0] = part[0];
             o[1] = part[1];
         }
@@ -414,83 +424,77 @@ __global__ __launch_bounds__(64 * VS) void k_backproject(BpArgs<T> a) {
 constexpr int kViewSplit = DECT_VIEW_SPLIT;  // waves per transpose workgroup
 constexpr int kLineSplit = DECT_LINE_SPLIT;  // waves per projector workgroup
 
-template <typename T, int CH, int SYM, bool QUAD>
-hipError_t project_t(const dect_plan* p, const void* img, void* O, void* OT, void* sino,
-                     hipStream_t s) {
-    using VI = vec<T, CH>;
-    using VO = vec<T, CH * SYM>;
-    const long N = p->N;
+template <typename T, int CH, int SYM, bool QUAD, bool BATCH>
+void project_launch(const OrbitArgs<T>* odev, const OrbitArgs<T>& oone, const ProjArgs<T>* pdev,
+                    const ProjArgs<T>& pone, int n, long pixels, int gx, int gy, hipStream_t s) {
+    const dim3 og((unsigned)((pixels + 255) / 256), 1, n);
     {
         ProfScope pt("orbit", s);
-        hipLaunchKernelGGL((k_orbit<T, CH, SYM, false>), dim3((unsigned)((N + 255) / 256)),
-                           dim3(256), 0, s, static_cast<const VI*>(img), static_cast<VO*>(O),
-                           p->nx, p->ny);
-        hipLaunchKernelGGL((k_orbit<T, CH, SYM, true>), dim3((unsigned)((N + 255) / 256)),
-                           dim3(256), 0, s, static_cast<const VI*>(img), static_cast<VO*>(OT),
-                           p->nx, p->ny);
+        hipLaunchKernelGGL((k_orbit<T, CH, SYM, false, BATCH>), og, dim3(256), 0, s, odev, oone);
+        hipLaunchKernelGGL((k_orbit<T, CH, SYM, true, BATCH>), og, dim3(256), 0, s, odev, oone);
     }
     ProfScope pp("project", s);
-    hipLaunchKernelGGL((k_project<T, CH, SYM, QUAD, kLineSplit>), dim3((p->D + 63) / 64, p->Vb),
-                       dim3(64 * kLineSplit), 0, s, static_cast<const RayParam<T>*>(p->rays), static_cast<const VO*>(O),
-                       static_cast<const VO*>(OT), static_cast<T*>(sino), p->nx, p->ny, p->Vb,
-                       p->D);
-    return hipGetLastError();
+    hipLaunchKernelGGL((k_project<T, CH, SYM, QUAD, kLineSplit, BATCH>), dim3(gx, gy, n),
+                       dim3(64 * kLineSplit), 0, s, pdev, pone);
 }
 
 template <typename T, int CH, int SYM, bool QUAD>
-hipError_t bp_t(const dect_plan* p, int epi, const BpArgs<T>& a, hipStream_t s) {
-    const int dx = SYM == 4 ? p->nx / 2 : p->nx, dy = SYM == 4 ? p->ny / 2 : p->ny;
-    dim3 g((dx + 7) / 8, (dy + 7) / 8);
-    dim3 blk(64 * kViewSplit);
+hipError_t project_t(const OrbitArgs<T>* odev, const OrbitArgs<T>& oone,
+                     const ProjArgs<T>* pdev, const ProjArgs<T>& pone, int n, long pixels, int gx,
+                     int gy, hipStream_t s) {
+    if (odev)
+        project_launch<T, CH, SYM, QUAD, true>(odev, oone, pdev, pone, n, pixels, gx, gy, s);
+    else
+        project_launch<T, CH, SYM, QUAD, false>(odev, oone, pdev, pone, n, pixels, gx, gy, s);
+    return hipGetLastError();
+}
+
+template <typename T, int CH, int SYM>
+hipError_t bp_plain(const BpArgs<T>& one, hipStream_t s) {
+    hipLaunchKernelGGL((k_backproject<T, CH, SYM, false, EPI_NONE, kViewSplit, false>),
+                       dim3(one.gx, one.gy), dim3(64 * kViewSplit), 0, s, nullptr, one);
+    return hipGetLastError();
+}
+
+// The ADMM's own sinograms are two-channel quad records.
+template <typename T, int SYM, bool BATCH>
+hipError_t bp_admm_t(int epi, const BpArgs<T>* dev, const BpArgs<T>& one, int n, int gx, int gy,
+                     hipStream_t s) {
+    const dim3 g(gx, gy, n);
+    const dim3 blk(64 * kViewSplit);
     switch (epi) {
-        case EPI_NONE:
-            hipLaunchKernelGGL((k_backproject<T, CH, SYM, QUAD, EPI_NONE, kViewSplit>), g, blk, 0, s, a);
-            break;
         case EPI_RHS:
-            hipLaunchKernelGGL((k_backproject<T, 2, SYM, QUAD, EPI_RHS, kViewSplit>), g, blk, 0, s, a);
+            hipLaunchKernelGGL((k_backproject<T, 2, SYM, true, EPI_RHS, kViewSplit, BATCH>), g, blk, 0, s, dev, one);
             break;
         case EPI_Q:
-            hipLaunchKernelGGL((k_backproject<T, 2, SYM, QUAD, EPI_Q, kViewSplit>), g, blk, 0, s, a);
+            hipLaunchKernelGGL((k_backproject<T, 2, SYM, true, EPI_Q, kViewSplit, BATCH>), g, blk, 0, s, dev, one);
+            break;
+        case EPI_DUAL:
+            hipLaunchKernelGGL((k_backproject<T, 2, SYM, true, EPI_DUAL, kViewSplit, BATCH>), g, blk, 0, s, dev, one);
             break;
         default:
-            hipLaunchKernelGGL((k_backproject<T, 2, SYM, QUAD, EPI_DUAL, kViewSplit>), g, blk, 0, s, a);
+            return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <typename T, int SYM>
+hipError_t bp_admm(int epi, const BpArgs<T>* dev, const BpArgs<T>& one, int n, int gx, int gy,
+                   hipStream_t s) {
+    return dev ? bp_admm_t<T, SYM, true>(epi, dev, one, n, gx, gy, s)
+               : bp_admm_t<T, SYM, false>(epi, dev, one, n, gx, gy, s);
+}
+
+const char* bp_name(int epi) {
+    static const char* names[4] = {"backproject", "backproject_rhs", "backproject_q",
+                                   "backproject_dual"};
+    return names[epi & 3];
 }
 
 }  // namespace
 
 template <typename T>
-hipError_t launch_project(const dect_plan* p, const void* img, void* sino, int ch, hipStream_t s) {
-    void* O = p->scratch_O;
-    void* OT = p->scratch_OT;
-    if (p->sym == 4) {
-        switch (ch) {
-            case 1: return project_t<T, 1, 4, false>(p, img, O, OT, sino, s);
-            case 2: return project_t<T, 2, 4, false>(p, img, O, OT, sino, s);
-            case 4: return project_t<T, 4, 4, false>(p, img, O, OT, sino, s);
-        }
-    } else {
-        switch (ch) {
-            case 1: return project_t<T, 1, 1, false>(p, img, O, OT, sino, s);
-            case 2: return project_t<T, 2, 1, false>(p, img, O, OT, sino, s);
-            case 4: return project_t<T, 4, 1, false>(p, img, O, OT, sino, s);
-        }
-    }
-    return hipErrorInvalidValue;
-}
-
-template <typename T>
-hipError_t launch_project_pair(const dect_plan* p, const void* img, void* O, void* OT,
-                               void* sino, hipStream_t s) {
-    return p->sym == 4 ? project_t<T, 2, 4, true>(p, img, O, OT, sino, s)
-                       : project_t<T, 2, 1, true>(p, img, O, OT, sino, s);
-}
-
-template <typename T>
-hipError_t launch_backproject(const dect_plan* p, int ch, int epi, const BpArgs<T>& a0,
-                              hipStream_t s) {
-    BpArgs<T> a = a0;
+void fill_bp_plan(const dect_plan* p, BpArgs<T>& a) {
     a.rays = static_cast<const RayParam<T>*>(p->rays);
     a.views = static_cast<const ViewParam<T>*>(p->views);
     a.nx = p->nx;
@@ -499,33 +503,83 @@ hipError_t launch_backproject(const dect_plan* p, int ch, int epi, const BpArgs<
     a.Vb = p->Vb;
     a.D = p->D;
     a.margin = p->margin;
-    static const char* names[4] = {"backproject", "backproject_rhs", "backproject_q",
-                                   "backproject_dual"};
-    ProfScope ps(names[epi & 3], s);
-    const bool quad = epi != EPI_NONE;  // the ADMM's own sinograms are quad records
+    const int dx = p->sym == 4 ? p->nx / 2 : p->nx, dy = p->sym == 4 ? p->ny / 2 : p->ny;
+    a.gx = (dx + 7) / 8;
+    a.gy = (dy + 7) / 8;
+}
+
+template <typename T>
+hipError_t launch_project(const dect_plan* p, const void* img, void* sino, int ch, hipStream_t s) {
+    OrbitArgs<T> o{static_cast<const T*>(img), static_cast<T*>(p->scratch_O),
+                   static_cast<T*>(p->scratch_OT), p->nx, p->ny};
+    ProjArgs<T> q{static_cast<const RayParam<T>*>(p->rays), static_cast<const T*>(p->scratch_O),
+                  static_cast<const T*>(p->scratch_OT), static_cast<T*>(sino), p->nx, p->ny,
+                  p->Vb, p->D};
+    const int gx = (p->D + 63) / 64, gy = p->Vb;
     if (p->sym == 4) {
-        if (quad) return bp_t<T, 2, 4, true>(p, epi, a, s);
         switch (ch) {
-            case 1: return bp_t<T, 1, 4, false>(p, epi, a, s);
-            case 2: return bp_t<T, 2, 4, false>(p, epi, a, s);
-            case 4: return bp_t<T, 4, 4, false>(p, epi, a, s);
+            case 1: return project_t<T, 1, 4, false>(nullptr, o, nullptr, q, 1, p->N, gx, gy, s);
+            case 2: return project_t<T, 2, 4, false>(nullptr, o, nullptr, q, 1, p->N, gx, gy, s);
+            case 4: return project_t<T, 4, 4, false>(nullptr, o, nullptr, q, 1, p->N, gx, gy, s);
         }
     } else {
-        if (quad) return bp_t<T, 2, 1, true>(p, epi, a, s);
         switch (ch) {
-            case 1: return bp_t<T, 1, 1, false>(p, epi, a, s);
-            case 2: return bp_t<T, 2, 1, false>(p, epi, a, s);
-            case 4: return bp_t<T, 4, 1, false>(p, epi, a, s);
+            case 1: return project_t<T, 1, 1, false>(nullptr, o, nullptr, q, 1, p->N, gx, gy, s);
+            case 2: return project_t<T, 2, 1, false>(nullptr, o, nullptr, q, 1, p->N, gx, gy, s);
+            case 4: return project_t<T, 4, 1, false>(nullptr, o, nullptr, q, 1, p->N, gx, gy, s);
         }
     }
     return hipErrorInvalidValue;
 }
 
-template hipError_t launch_project<float>(const dect_plan*, const void*, void*, int, hipStream_t);
-template hipError_t launch_project<double>(const dect_plan*, const void*, void*, int, hipStream_t);
-template hipError_t launch_project_pair<float>(const dect_plan*, const void*, void*, void*, void*, hipStream_t);
-template hipError_t launch_project_pair<double>(const dect_plan*, const void*, void*, void*, void*, hipStream_t);
-template hipError_t launch_backproject<float>(const dect_plan*, int, int, const BpArgs<float>&, hipStream_t);
-template hipError_t launch_backproject<double>(const dect_plan*, int, int, const BpArgs<double>&, hipStream_t);
+template <typename T>
+hipError_t launch_project_pair(int sym, const OrbitArgs<T>* odev, const OrbitArgs<T>& oone,
+                               const ProjArgs<T>* pdev, const ProjArgs<T>& pone, int n,
+                               long pixels, int gx, int gy, hipStream_t s) {
+    return sym == 4 ? project_t<T, 2, 4, true>(odev, oone, pdev, pone, n, pixels, gx, gy, s)
+                    : project_t<T, 2, 1, true>(odev, oone, pdev, pone, n, pixels, gx, gy, s);
+}
+
+template <typename T>
+hipError_t launch_backproject(const dect_plan* p, int ch, const BpArgs<T>& a0, hipStream_t s) {
+    BpArgs<T> a = a0;
+    fill_bp_plan<T>(p, a);
+    ProfScope ps(bp_name(EPI_NONE), s);
+    if (p->sym == 4) {
+        switch (ch) {
+            case 1: return bp_plain<T, 1, 4>(a, s);
+            case 2: return bp_plain<T, 2, 4>(a, s);
+            case 4: return bp_plain<T, 4, 4>(a, s);
+        }
+    } else {
+        switch (ch) {
+            case 1: return bp_plain<T, 1, 1>(a, s);
+            case 2: return bp_plain<T, 2, 1>(a, s);
+            case 4: return bp_plain<T, 4, 1>(a, s);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_backproject_admm(int sym, int epi, const BpArgs<T>* dev, const BpArgs<T>& one,
+                                   int n, int gx, int gy, hipStream_t s) {
+    ProfScope ps(bp_name(epi), s);
+    return sym == 4 ? bp_admm<T, 4>(epi, dev, one, n, gx, gy, s)
+                    : bp_admm<T, 1>(epi, dev, one, n, gx, gy, s);
+}
+
+#define DECT_INST(T)                                                                          \
+    template void fill_bp_plan<T>(const dect_plan*, BpArgs<T>&);                              \
+    template hipError_t launch_project<T>(const dect_plan*, const void*, void*, int, hipStream_t); \
+    template hipError_t launch_project_pair<T>(int, const OrbitArgs<T>*, const OrbitArgs<T>&,     \
+                                               const ProjArgs<T>*, const ProjArgs<T>&, int, long, \
+                                               int, int, hipStream_t);                            \
+    template hipError_t launch_backproject<T>(const dect_plan*, int, const BpArgs<T>&, hipStream_t); \
+    template hipError_t launch_backproject_admm<T>(int, int, const BpArgs<T>*, const BpArgs<T>&,  \
+                                                   int, int, int, hipStream_t);
+DECT_INST(float)
+DECT_INST(double)
+#undef DECT_INST
 
 }  // namespace dect

@@ -141,11 +141,15 @@ __device__ inline void lm_solve(const T* __restrict__ spec, int kmax, int kh, in
     }
 }
 
-template <typename T, int MODE>
-__global__ __launch_bounds__(256) void k_udm(UdmArgs<T> A, const T* __restrict__ spec, int kmax,
-                                             int kh, int kl, StepBound sb) {
+template <typename T, int MODE, bool BATCH>
+__global__ __launch_bounds__(256) void k_udm(const UdmArgs<T>* __restrict__ dev, UdmArgs<T> one) {
     using V2 = vec<T, 2>;
     using V4 = vec<T, 4>;
+    const UdmArgs<T> A = pick_args<BATCH>(dev, one);
+    const T* __restrict__ spec = A.spec;
+    const int kmax = A.kmax, kh = A.kh, kl = A.kl;
+    const StepBound sb{A.kc_max, A.kp_max};
+    if ((long)blockIdx.x * blockDim.x >= A.M) return;  // beyond this slice (whole block)
     // l: internal ray index (t, da, R p, f cache); i: standard [V][D] index (m, w, a,
     // u^a, R x).
     const long l = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -263,17 +267,34 @@ __global__ __launch_bounds__(256) void k_ingest(long M, const T* __restrict__ ch
 }  // namespace
 
 template <typename T>
-hipError_t launch_udm(const dect_plan* p, int mode, const UdmArgs<T>& a, hipStream_t s) {
+void fill_udm_tables(const dect_plan* p, UdmArgs<T>& a) {
+    a.spec = static_cast<const T*>(p->spec);
+    a.kmax = p->kmax;
+    a.kh = p->kh;
+    a.kl = p->kl;
+    a.kc_max = (float)p->kc_max;
+    a.kp_max = (float)p->kp_max;
+}
+
+template <typename T>
+hipError_t launch_udm(const dect_plan* p, int mode, const UdmArgs<T>& a0, hipStream_t s) {
+    UdmArgs<T> a = a0;
+    if (p) fill_udm_tables<T>(p, a);  // else the tables are already in a
     dim3 g((unsigned)((a.M + 255) / 256));
-    const T* spec = static_cast<const T*>(p->spec);
-    const StepBound sb{(float)p->kc_max, (float)p->kp_max};
     ProfScope ps(mode == 1 ? "udm_init" : "udm", s);
     if (mode == 0)
-        hipLaunchKernelGGL((k_udm<T, 0>), g, dim3(256), 0, s, a, spec, p->kmax, p->kh, p->kl, sb);
+        hipLaunchKernelGGL((k_udm<T, 0, false>), g, dim3(256), 0, s, nullptr, a);
     else if (mode == 1)
-        hipLaunchKernelGGL((k_udm<T, 1>), g, dim3(256), 0, s, a, spec, p->kmax, p->kh, p->kl, sb);
+        hipLaunchKernelGGL((k_udm<T, 1, false>), g, dim3(256), 0, s, nullptr, a);
     else
-        hipLaunchKernelGGL((k_udm<T, 2>), g, dim3(256), 0, s, a, spec, p->kmax, p->kh, p->kl, sb);
+        hipLaunchKernelGGL((k_udm<T, 2, false>), g, dim3(256), 0, s, nullptr, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_udm_batch(const UdmArgs<T>* args, int n, int blocks, hipStream_t s) {
+    ProfScope ps("udm", s);
+    hipLaunchKernelGGL((k_udm<T, 2, true>), dim3(blocks, 1, n), dim3(256), 0, s, args, UdmArgs<T>{});
     return hipGetLastError();
 }
 
@@ -287,8 +308,12 @@ hipError_t launch_ingest(const dect_plan* p, const void* ch, const void* cl, dou
     return hipGetLastError();
 }
 
+template void fill_udm_tables<float>(const dect_plan*, UdmArgs<float>&);
+template void fill_udm_tables<double>(const dect_plan*, UdmArgs<double>&);
 template hipError_t launch_udm<float>(const dect_plan*, int, const UdmArgs<float>&, hipStream_t);
 template hipError_t launch_udm<double>(const dect_plan*, int, const UdmArgs<double>&, hipStream_t);
+template hipError_t launch_udm_batch<float>(const UdmArgs<float>*, int, int, hipStream_t);
+template hipError_t launch_udm_batch<double>(const UdmArgs<double>*, int, int, hipStream_t);
 template hipError_t launch_ingest<float>(const dect_plan*, const void*, const void*, double, double,
                                          void*, void*, void*, void*, hipStream_t);
 template hipError_t launch_ingest<double>(const dect_plan*, const void*, const void*, double,

@@ -101,12 +101,20 @@ def lib():
             "dect_admm_init": [vp, vp, vp, vp, vp, vp, ctypes.POINTER(Params), vp],
             "dect_admm_iterate": [vp, vp, vp, vp, vp, vp, ctypes.POINTER(Params), i,
                                   ctypes.POINTER(IterLog), vp],
+            "dect_state_log": [vp, vp, ctypes.c_int64, i, ctypes.POINTER(IterLog), vp],
+            "dect_batch_create": [i, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                  ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                  ctypes.POINTER(Params), i, ctypes.POINTER(vp)],
+            "dect_batch_iterate": [vp, i, vp],
+            "dect_batch_groups": [vp],
+            "dect_batch_destroy": [vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
             fn.argtypes = args
             fn.restype = ctypes.c_int
         L.dect_plan_destroy.restype = None
+        L.dect_batch_destroy.restype = None
         L.dect_state_bytes.restype = ctypes.c_size_t
         L.dect_last_error.restype = ctypes.c_char_p
         L.dect_last_error.argtypes = []
@@ -143,6 +151,11 @@ def profile_stop() -> dict:
     n = ctypes.c_int()
     _check(lib().dect_profile_stop(buf, 64, ctypes.byref(n)))
     return {buf[k].name.decode(): (buf[k].total_ms, buf[k].launches) for k in range(min(n.value, 64))}
+
+
+def _records(L, n):
+    return [dict(iter=e.iter, flags=e.flags, rho=tuple(e.rho), r=tuple(e.r_primal),
+                 s=tuple(e.s_dual), data=e.data_cost, tv=e.tv_cost) for e in L[:n]]
 
 
 def make_geometry(g: dict) -> Geometry:
@@ -315,5 +328,49 @@ class Plan:
                                        ctypes.byref(P), int(n_iters), L, _stream()))
         if not log:
             return None
-        return [dict(iter=e.iter, flags=e.flags, rho=tuple(e.rho), r=tuple(e.r_primal),
-                     s=tuple(e.s_dual), data=e.data_cost, tv=e.tv_cost) for e in L[:n_iters]]
+        return _records(L, n_iters)
+
+    def state_log(self, state: State, first: int, n: int):
+        """Log records of iterations [first, first + n) of a state (synchronises)."""
+        L = (IterLog * max(n, 1))()
+        _check(lib().dect_state_log(self.handle, state.ptr, int(first), int(n), L, _stream()))
+        return _records(L, n)
+
+
+class Batch:
+    """Slices advanced together: one launch per kernel per shape group, optionally
+    replayed from a HIP graph.  slices: sequence of (plan, meas, state); the batch
+    keeps references to them."""
+
+    def __init__(self, slices, params: AdmmParams, graph: bool = True):
+        n = len(slices)
+        arr = lambda vals: (ctypes.c_void_p * n)(*vals)
+        self._keep = list(slices)
+        plans = arr([p.handle.value for p, _, _ in slices])
+        meas = [arr([m[k].data_ptr() for _, m, _ in slices]) for k in range(4)]
+        for _, m, st in slices:
+            for t in m:
+                _ptr(t)
+        states = arr([st.buf.data_ptr() for _, _, st in slices])
+        P, self._sched = params.c_struct()
+        h = ctypes.c_void_p()
+        _check(lib().dect_batch_create(n, plans, *meas, states, ctypes.byref(P), int(graph),
+                                       ctypes.byref(h)))
+        self.handle = h
+        self.n = n
+
+    @property
+    def groups(self) -> int:
+        return lib().dect_batch_groups(self.handle)
+
+    def iterate(self, n_iters: int):
+        _check(lib().dect_batch_iterate(self.handle, int(n_iters), _stream()))
+
+    def close(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            _lib.dect_batch_destroy(h)
+            self.handle = None
+
+    def __del__(self):
+        self.close()

@@ -193,7 +193,22 @@ class Shape:
         return (np.abs(u) <= self.ax) & (np.abs(v) <= self.ay)
 
     def chord(self, origin, direction):
-        """Exact length of the intersection of each line with the shape."""
+        """Exact length of the intersection of each line with the shape.
+
+        Lines farther from the centre than the shape's circumradius miss it; the
+        exact formula runs on the others only.
+        """
+        r = max(self.ax, self.ay) if self.kind == "ellipse" else math.hypot(self.ax, self.ay)
+        ox, oy = origin[..., 0] - self.cx, origin[..., 1] - self.cy
+        dist = np.abs(ox * direction[..., 1] - oy * direction[..., 0]) / np.hypot(
+            direction[..., 0], direction[..., 1])
+        hit = dist <= r * (1.0 + 1e-9)
+        out = np.zeros(origin.shape[:-1])
+        if hit.any():
+            out[hit] = self._chord(origin[hit], direction[hit])
+        return out
+
+    def _chord(self, origin, direction):
         c, s = math.cos(self.rot), math.sin(self.rot)
         px = (origin[..., 0] - self.cx) * c + (origin[..., 1] - self.cy) * s
         py = -(origin[..., 0] - self.cx) * s + (origin[..., 1] - self.cy) * c
