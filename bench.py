@@ -53,6 +53,10 @@ def parse():
                     help="skip the 64-slice stack and the 96-slice uneven batch")
     ap.add_argument("--batch-steps", type=int, default=20,
                     help="timed iterations of the batched workloads")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrivals per s")
+    ap.add_argument("--serve-seconds", type=float, default=4.0, help="arrival window, s")
+    ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device-to-device copy (reference for "
                          "hardware byte counters)")
@@ -125,6 +129,95 @@ def batch_workload(dect, torch, dev, items, params, steps, warmup):
     out["identical_states"] = identical
     out["groups"] = len(plans)
     out["kernels_per_batch_iter_us"] = {k: round(1e3 * v[0] / 2, 2) for k, v in kt.items()}
+    return out
+
+
+def serve_workload(dect, torch, dev, items, args):
+    """Requests of the uneven mix (relative objective change 1e-4, at most 100
+    iterations, checks every 5): plain one-slice-at-a-time processing against the
+    continuous-batching server, closed and with Poisson arrivals."""
+    import numpy as np
+    from paper_1905_00934_amd import synth
+    spec = synth.default_spectra()
+    plans = {}
+    reqs = []
+    for _, _, geom, i0, ch, cl in items:
+        key = (geom["nx"], geom["ny"], geom["n_views"], geom["n_det"])
+        if key not in plans:
+            plans[key] = dect.Plan(geom, spec, torch.float32, device=dev)
+        reqs.append((plans[key], i0, ch, cl))
+    params = dect.AdmmParams()
+    tol, max_iters, step = 1e-4, 100, 5
+
+    def plain_one(plan, i0, ch, cl):
+        c = [torch.from_numpy(x).to(dev) for x in (ch, cl)]
+        meas = list(plan.ingest(c[0], c[1], i0))
+        st = plan.new_state()
+        plan.admm_init(meas, st, params)
+        it, phis = 0, []
+        while True:
+            n = min(step, max_iters - it)
+            log = plan.admm_iterate(meas, st, params, n, log=True)
+            it += n
+            phis += [e["data"] + e["tv"] for e in log]
+            rel = abs(phis[-1] - phis[-2]) / abs(phis[-1]) if len(phis) >= 2 else math.inf
+            if rel <= tol or it >= max_iters:
+                return st.x.cpu().numpy(), it
+
+    n_plain = min(len(reqs), 48)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain = [plain_one(*r) for r in reqs[:n_plain]]
+    t_plain = time.perf_counter() - t0
+    out = {"requests": n_plain, "tol": tol, "max_iters": max_iters, "check_every": step,
+           "plain": {"slices_per_s": round(n_plain / t_plain, 3),
+                     "mean_iters": round(float(np.mean([p[1] for p in plain])), 2)}}
+
+    def run(arrivals, slots):
+        srv = dect.Server(max_slots=slots, step_iters=step)
+        t0 = time.perf_counter()
+        tickets = []
+        for k, ta in enumerate(arrivals):
+            wait = ta - (time.perf_counter() - t0)
+            if wait > 0:
+                time.sleep(wait)
+            plan, i0, ch, cl = reqs[k % n_plain]
+            tickets.append(srv.submit(plan, ch, cl, i0, params=params, tol=tol,
+                                      max_iters=max_iters))
+        res = [srv.wait(t, 600000) for t in tickets]
+        span = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        if any(r is None for r in res):
+            raise RuntimeError("a served request did not finish within 600 s")
+        lat = np.array([r[1]["latency_s"] for r in res])
+        return res, {"slices_per_s": round(len(res) / span, 3),
+                     "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
+                     "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
+                     "mean_queue_s": round(float(np.mean([r[1]["queue_s"] for r in res])), 4),
+                     "mean_iters": round(float(np.mean([r[1]["iters"] for r in res])), 2),
+                     "peak_in_flight": st["peak_in_flight"], "steps": st["steps"]}
+
+    res, closed = run([0.0] * n_plain, args.serve_slots)
+    closed["identical_to_plain"] = all(
+        np.array_equal(r[0], p[0]) and r[1]["iters"] == p[1] for r, p in zip(res, plain))
+    out["served_closed"] = closed
+    rng = np.random.default_rng(2024)
+
+    def poisson(rate, seconds):
+        t = np.cumsum(rng.exponential(1.0 / rate, int(rate * seconds * 2) + 16))
+        return t[t < seconds]
+
+    _, over = run(poisson(args.serve_rate, args.serve_seconds), args.serve_slots)
+    over["offered_req_per_s"] = args.serve_rate
+    over["arrival_window_s"] = args.serve_seconds
+    out["served_poisson"] = over
+    rate = 0.7 * closed["slices_per_s"]
+    _, under = run(poisson(rate, args.serve_seconds), args.serve_slots)
+    under["offered_req_per_s"] = round(rate, 3)
+    under["arrival_window_s"] = args.serve_seconds
+    out["served_poisson_70pct"] = under
+    out["speedup_closed_vs_plain"] = round(closed["slices_per_s"] / out["plain"]["slices_per_s"], 3)
     return out
 
 
@@ -237,6 +330,8 @@ def main():
                          **batch_workload(dect, torch, dev, batch_items["uneven"], params_b,
                                           args.batch_steps, 2)},
         }
+    if batch_items and not args.no_serve:
+        out["serving"] = serve_workload(dect, torch, dev, batch_items["uneven"], args)
     if args.calibrate_copy:
         src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)

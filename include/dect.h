@@ -242,6 +242,71 @@ dect_status dect_batch_iterate(dect_batch* batch, int n_iters, void* stream);
 int dect_batch_groups(const dect_batch* batch);
 void dect_batch_destroy(dect_batch* batch);
 
+/* -------------------------------------------------------------- serving --- */
+
+/* Continuous batching of slice reconstructions (each slice its own problem,
+ * Sec. 3.3).  A server owns one worker thread and one stream on the device
+ * current at creation.  Requests wait in a FIFO queue and are admitted, in
+ * order, while a slot is free and their device footprint (state, measurements
+ * and counts: dect_serve_footprint) fits the memory budget.  An admitted request
+ * is ingested and initialised (dect_admm_init) and then advanced together with
+ * every other slot, one launch per kernel per shape group, until it stops.
+ * A slot is checked after every step_iters of its own iterations and at
+ * max_iters: it stops when |Phi_k - Phi_(k-1)| <= tol |Phi_k| (Phi = data cost
+ * + TV cost of its last two iterations), at max_iters, or on a non-finite
+ * value.  The step the server runs is the smallest distance of any slot to its
+ * next check, so every slot stops at exactly the iteration it would reach alone:
+ * its result does not depend on the other requests in flight. */
+typedef struct {
+    size_t hbm_budget_bytes; /* device memory for slots; 0: half the free memory */
+    int max_slots;           /* requests in flight at once, >= 1 */
+    int step_iters;          /* iterations between a slot's checks, >= 1 */
+} dect_server_config;
+
+typedef struct {
+    const dect_plan* plan;   /* geometry, spectra, dtype; must outlive the request */
+    const void* counts_h;    /* host [n_views*n_det], plan dtype; copied at submit */
+    const void* counts_l;
+    double i0_h, i0_l;       /* unattenuated counts */
+    dect_params params;      /* fixed or adaptive rho (no schedule) */
+    double tol;              /* relative objective change that stops the slot */
+    int max_iters;           /* outer iterations at most, >= 1 */
+    void* x_out;             /* host [ny][nx][2], plan dtype; written on completion and
+                                kept alive by the caller until poll/wait returns it */
+} dect_request;
+
+typedef struct {
+    int32_t status;     /* DECT_OK or the error that ended the request */
+    int32_t iters;      /* outer iterations run */
+    double objective;   /* Phi at the last iteration */
+    double rel_change;  /* |Phi_k - Phi_(k-1)| / |Phi_k| at the last check (inf if k < 2) */
+    int64_t queue_ns;   /* submit to admission */
+    int64_t latency_ns; /* submit to completion (x_out written) */
+} dect_result;
+
+typedef struct {
+    int64_t submitted, completed, queued, in_flight, peak_in_flight, steps;
+    size_t hbm_held;    /* device bytes held for slots (in use and cached) */
+} dect_server_stats;
+
+typedef struct dect_server dect_server;
+
+dect_status dect_server_create(const dect_server_config* cfg, dect_server** out);
+/* Device bytes one request of this plan holds while in flight. */
+size_t dect_serve_footprint(const dect_plan* plan);
+/* Queue a request; *ticket identifies it.  DECT_E_CAPACITY if its footprint
+ * exceeds the whole budget, DECT_E_ARG for bad arguments. */
+dect_status dect_serve_submit(dect_server* server, const dect_request* req, uint64_t* ticket);
+/* DECT_NOT_READY while the request is queued or running; once it has finished,
+ * DECT_OK and *out, and the ticket is released (a later poll is DECT_E_ARG). */
+dect_status dect_serve_poll(dect_server* server, uint64_t ticket, dect_result* out);
+/* As poll, but blocks up to timeout_ms (< 0: no limit) for completion. */
+dect_status dect_serve_wait(dect_server* server, uint64_t ticket, int64_t timeout_ms,
+                            dect_result* out);
+dect_status dect_server_get_stats(dect_server* server, dect_server_stats* out);
+/* Stops the worker after its current step; unfinished requests are dropped. */
+void dect_server_destroy(dect_server* server);
+
 /* --------------------------------------------------------------- timing --- */
 
 /* Per-kernel timing for benchmarks: between dect_profile_start and

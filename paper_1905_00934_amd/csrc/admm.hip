@@ -354,6 +354,8 @@ SliceJob<T> make_job(const dect_plan* p, const void* mh, const void* ml, const v
     const int n = prm->cg_iters;
 
     SliceJob<T> J{};
+    J.cg_iters = prm->cg_iters;
+    J.rho_mode = prm->rho_mode;
     J.N = p->N;
     J.M = p->M;
     J.sym = p->sym;

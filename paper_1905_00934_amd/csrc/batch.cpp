@@ -11,85 +11,149 @@
 #include "common.h"
 #include "kernels.h"
 #include "profile.h"
+#include "runner.h"
 
 namespace dect {
-namespace {
 
-template <typename T>
-struct Group {
-    std::vector<int> slices;       // indices into the batch, in launch order
-    std::vector<SliceJob<T>> jobs;
-    JobArrays<T> dev{};
-    void* mem = nullptr;           // device storage of dev
-};
+namespace {
 
 template <typename T>
 bool same_shape(const SliceJob<T>& a, const SliceJob<T>& b) {
     return a.N == b.N && a.M == b.M && a.sym == b.sym && a.bp_gx == b.bp_gx &&
            a.bp_gy == b.bp_gy && a.pj_gx == b.pj_gx && a.pj_gy == b.pj_gy &&
-           a.prj.nx == b.prj.nx && a.prj.ny == b.prj.ny;
+           a.prj.nx == b.prj.nx && a.prj.ny == b.prj.ny && a.cg_iters == b.cg_iters &&
+           a.rho_mode == b.rho_mode;
 }
 
-// Copy the argument blocks of a group to one device allocation.
+// Byte offsets of the ten argument arrays of a group of n slices.
 template <typename T>
-hipError_t upload(Group<T>& g) {
-    const size_t n = g.jobs.size();
-    size_t off = 0;
-    auto take = [&](size_t bytes) {
-        const size_t o = off;
-        off = (off + bytes + 255) & ~size_t(255);
-        return o;
-    };
-    const size_t o_orb = take(n * sizeof(OrbitArgs<T>)), o_prj = take(n * sizeof(ProjArgs<T>)),
-                 o_rhs = take(n * sizeof(BpArgs<T>)), o_q = take(n * sizeof(BpArgs<T>)),
-                 o_dual = take(n * sizeof(BpArgs<T>)), o_udm = take(n * sizeof(UdmArgs<T>)),
-                 o_vec = take(n * sizeof(VecArgs<T>)), o_tv = take(n * sizeof(TvArgs<T>)),
-                 o_resc = take(n * sizeof(RescaleArgs<T>)), o_red = take(n * sizeof(RedArgs));
-    std::vector<char> h(off, 0);
-    for (size_t k = 0; k < n; ++k) {
-        const SliceJob<T>& J = g.jobs[k];
-        std::memcpy(&h[o_orb + k * sizeof(J.orb)], &J.orb, sizeof(J.orb));
-        std::memcpy(&h[o_prj + k * sizeof(J.prj)], &J.prj, sizeof(J.prj));
-        std::memcpy(&h[o_rhs + k * sizeof(J.rhs)], &J.rhs, sizeof(J.rhs));
-        std::memcpy(&h[o_q + k * sizeof(J.q)], &J.q, sizeof(J.q));
-        std::memcpy(&h[o_dual + k * sizeof(J.dual)], &J.dual, sizeof(J.dual));
-        std::memcpy(&h[o_udm + k * sizeof(J.udm)], &J.udm, sizeof(J.udm));
-        std::memcpy(&h[o_vec + k * sizeof(J.vec)], &J.vec, sizeof(J.vec));
-        std::memcpy(&h[o_tv + k * sizeof(J.tv)], &J.tv, sizeof(J.tv));
-        std::memcpy(&h[o_resc + k * sizeof(J.resc)], &J.resc, sizeof(J.resc));
-        std::memcpy(&h[o_red + k * sizeof(J.red)], &J.red, sizeof(J.red));
+struct ArrayOffsets {
+    size_t orb, prj, rhs, q, dual, udm, vec, tv, resc, red, end;
+    ArrayOffsets(size_t base, size_t n) {
+        size_t off = base;
+        auto take = [&](size_t bytes) {
+            const size_t o = off;
+            off = (off + bytes + 255) & ~size_t(255);
+            return o;
+        };
+        orb = take(n * sizeof(OrbitArgs<T>));
+        prj = take(n * sizeof(ProjArgs<T>));
+        rhs = take(n * sizeof(BpArgs<T>));
+        q = take(n * sizeof(BpArgs<T>));
+        dual = take(n * sizeof(BpArgs<T>));
+        udm = take(n * sizeof(UdmArgs<T>));
+        vec = take(n * sizeof(VecArgs<T>));
+        tv = take(n * sizeof(TvArgs<T>));
+        resc = take(n * sizeof(RescaleArgs<T>));
+        red = take(n * sizeof(RedArgs));
+        end = off;
     }
-    hipError_t e = hipMalloc(&g.mem, off);
-    if (e != hipSuccess) return e;
-    e = hipMemcpy(g.mem, h.data(), off, hipMemcpyHostToDevice);
-    if (e != hipSuccess) return e;
-    char* b = static_cast<char*>(g.mem);
-    g.dev.orb = reinterpret_cast<OrbitArgs<T>*>(b + o_orb);
-    g.dev.prj = reinterpret_cast<ProjArgs<T>*>(b + o_prj);
-    g.dev.rhs = reinterpret_cast<BpArgs<T>*>(b + o_rhs);
-    g.dev.q = reinterpret_cast<BpArgs<T>*>(b + o_q);
-    g.dev.dual = reinterpret_cast<BpArgs<T>*>(b + o_dual);
-    g.dev.udm = reinterpret_cast<UdmArgs<T>*>(b + o_udm);
-    g.dev.vec = reinterpret_cast<VecArgs<T>*>(b + o_vec);
-    g.dev.tv = reinterpret_cast<TvArgs<T>*>(b + o_tv);
-    g.dev.resc = reinterpret_cast<RescaleArgs<T>*>(b + o_resc);
-    g.dev.red = reinterpret_cast<RedArgs*>(b + o_red);
-    return hipSuccess;
+};
+
+template <typename F>
+void put(std::vector<char>& h, size_t at, size_t k, const F& v) {
+    std::memcpy(&h[at + k * sizeof(F)], &v, sizeof(F));
 }
 
 }  // namespace
+
+template <typename T>
+Runner<T>::~Runner() {
+    if (mem_) (void)hipFree(mem_);
+}
+
+template <typename T>
+hipError_t Runner<T>::set(const std::vector<SliceJob<T>>& jobs) {
+    groups_.clear();
+    n_ = (int)jobs.size();
+    for (const SliceJob<T>& J : jobs) {
+        Group* into = nullptr;
+        for (auto& g : groups_)
+            if (same_shape(g.jobs[0], J)) into = &g;
+        if (!into) {
+            groups_.emplace_back();
+            into = &groups_.back();
+        }
+        into->jobs.push_back(J);
+    }
+    size_t total = 0;
+    std::vector<ArrayOffsets<T>> offs;
+    for (const Group& g : groups_) {
+        offs.emplace_back(total, g.jobs.size());
+        total = offs.back().end;
+    }
+    if (total == 0) return hipSuccess;
+    if (total > cap_) {
+        if (mem_) {
+            hipError_t e = hipFree(mem_);
+            mem_ = nullptr;
+            cap_ = 0;
+            if (e != hipSuccess) return e;
+        }
+        hipError_t e = hipMalloc(&mem_, total);
+        if (e != hipSuccess) return e;
+        cap_ = total;
+    }
+    std::vector<char> h(total, 0);
+    char* b = static_cast<char*>(mem_);
+    for (size_t gi = 0; gi < groups_.size(); ++gi) {
+        Group& g = groups_[gi];
+        const ArrayOffsets<T>& o = offs[gi];
+        for (size_t k = 0; k < g.jobs.size(); ++k) {
+            const SliceJob<T>& J = g.jobs[k];
+            put(h, o.orb, k, J.orb);
+            put(h, o.prj, k, J.prj);
+            put(h, o.rhs, k, J.rhs);
+            put(h, o.q, k, J.q);
+            put(h, o.dual, k, J.dual);
+            put(h, o.udm, k, J.udm);
+            put(h, o.vec, k, J.vec);
+            put(h, o.tv, k, J.tv);
+            put(h, o.resc, k, J.resc);
+            put(h, o.red, k, J.red);
+        }
+        g.dev.orb = reinterpret_cast<OrbitArgs<T>*>(b + o.orb);
+        g.dev.prj = reinterpret_cast<ProjArgs<T>*>(b + o.prj);
+        g.dev.rhs = reinterpret_cast<BpArgs<T>*>(b + o.rhs);
+        g.dev.q = reinterpret_cast<BpArgs<T>*>(b + o.q);
+        g.dev.dual = reinterpret_cast<BpArgs<T>*>(b + o.dual);
+        g.dev.udm = reinterpret_cast<UdmArgs<T>*>(b + o.udm);
+        g.dev.vec = reinterpret_cast<VecArgs<T>*>(b + o.vec);
+        g.dev.tv = reinterpret_cast<TvArgs<T>*>(b + o.tv);
+        g.dev.resc = reinterpret_cast<RescaleArgs<T>*>(b + o.resc);
+        g.dev.red = reinterpret_cast<RedArgs*>(b + o.red);
+    }
+    return hipMemcpy(mem_, h.data(), total, hipMemcpyHostToDevice);
+}
+
+template <typename T>
+hipError_t Runner<T>::enqueue(hipStream_t s) const {
+    for (const Group& g : groups_) {
+        // The launch structure comes from the group; every other parameter is in the
+        // slices' own argument blocks and device scalars.
+        dect_params prm{};
+        prm.cg_iters = g.jobs[0].cg_iters;
+        prm.rho_mode = g.jobs[0].rho_mode;
+        hipError_t e = launch_iteration<T>(g.jobs[0], &g.dev, (int)g.jobs.size(), &prm, 0, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template class Runner<float>;
+template class Runner<double>;
+
 }  // namespace dect
 
 using namespace dect;
 
 struct dect_batch {
     dect_dtype dtype;
-    int n = 0;
     int device = 0;
     dect_params prm{};
     bool use_graph = false;
-    std::vector<Group<float>> gf;
-    std::vector<Group<double>> gd;
+    Runner<float> rf;
+    Runner<double> rd;
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -98,60 +162,31 @@ struct dect_batch {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         if (cap) (void)hipStreamDestroy(cap);
-        for (auto& g : gf)
-            if (g.mem) (void)hipFree(g.mem);
-        for (auto& g : gd)
-            if (g.mem) (void)hipFree(g.mem);
-    }
-
-    template <typename T>
-    std::vector<Group<T>>& groups();
-
-    // One outer iteration of every group, enqueued on s.
-    template <typename T>
-    hipError_t enqueue(hipStream_t s) {
-        for (const Group<T>& g : groups<T>()) {
-            hipError_t e = launch_iteration<T>(g.jobs[0], &g.dev, (int)g.jobs.size(), &prm, 0, s);
-            if (e != hipSuccess) return e;
-        }
-        return hipSuccess;
     }
     hipError_t enqueue(hipStream_t s) {
-        return dtype == DECT_F32 ? enqueue<float>(s) : enqueue<double>(s);
+        return dtype == DECT_F32 ? rf.enqueue(s) : rd.enqueue(s);
     }
 };
-
-template <>
-std::vector<Group<float>>& dect_batch::groups<float>() { return gf; }
-template <>
-std::vector<Group<double>>& dect_batch::groups<double>() { return gd; }
 
 namespace {
 
 template <typename T>
-dect_status build_groups(dect_batch* b, const dect_plan* const* plans, const void* const* mh,
+dect_status build_groups(Runner<T>& r, int n, const dect_params* prm,
+                         const dect_plan* const* plans, const void* const* mh,
                          const void* const* ml, const void* const* wh, const void* const* wl,
                          void* const* states) {
-    std::vector<Group<T>>& G = b->groups<T>();
-    for (int k = 0; k < b->n; ++k) {
-        const SliceJob<T> J = make_job<T>(plans[k], mh[k], ml[k], wh[k], wl[k], states[k], &b->prm);
-        Group<T>* into = nullptr;
-        for (auto& g : G)
-            if (same_shape(g.jobs[0], J)) into = &g;
-        if (!into) {
-            G.emplace_back();
-            into = &G.back();
-        }
-        into->slices.push_back(k);
-        into->jobs.push_back(J);
-    }
-    for (auto& g : G) {
-        hipError_t e = upload<T>(g);
-        if (e != hipSuccess)
-            return fail(DECT_E_DEVICE, "batch argument upload failed: %s", hipGetErrorString(e));
-    }
+    std::vector<SliceJob<T>> jobs;
+    for (int k = 0; k < n; ++k)
+        jobs.push_back(make_job<T>(plans[k], mh[k], ml[k], wh[k], wl[k], states[k], prm));
+    hipError_t e = r.set(jobs);
+    if (e != hipSuccess)
+        return fail(DECT_E_DEVICE, "batch argument upload failed: %s", hipGetErrorString(e));
     return DECT_OK;
 }
+
+}  // namespace
+
+namespace dect {
 
 dect_status check_batch_params(const dect_params* prm) {
     if (!prm) return fail(DECT_E_ARG, "null params");
@@ -162,10 +197,12 @@ dect_status check_batch_params(const dect_params* prm) {
     if (prm->rho_mode == DECT_RHO_ADAPTIVE && (!(prm->bal_mu > 1) || !(prm->bal_tau > 1)))
         return fail(DECT_E_ARG, "residual balancing needs mu > 1 and tau > 1");
     if (!(prm->lm_mu0 > 0)) return fail(DECT_E_ARG, "lm_mu0 must be > 0");
+    if (!(prm->rho_c > 0) || !(prm->rho_p > 0) || !(prm->lambda_c >= 0) || !(prm->lambda_p >= 0))
+        return fail(DECT_E_ARG, "rho must be > 0 and lambda >= 0");
     return DECT_OK;
 }
 
-}  // namespace
+}  // namespace dect
 
 extern "C" {
 
@@ -192,14 +229,14 @@ dect_status dect_batch_create(int n, const dect_plan* const* plans, const void* 
     std::unique_ptr<dect_batch> b(new (std::nothrow) dect_batch());
     if (!b) return fail(DECT_E_NOMEM, "out of host memory");
     b->dtype = plans[0]->dtype;
-    b->n = n;
     b->prm = *params;
     b->prm.rho_schedule = nullptr;
     b->prm.rho_schedule_len = 0;
     b->use_graph = use_graph != 0;
     DECT_HIP(hipGetDevice(&b->device));
-    st = b->dtype == DECT_F32 ? build_groups<float>(b.get(), plans, m_h, m_l, w_h, w_l, states)
-                              : build_groups<double>(b.get(), plans, m_h, m_l, w_h, w_l, states);
+    st = b->dtype == DECT_F32
+             ? build_groups<float>(b->rf, n, &b->prm, plans, m_h, m_l, w_h, w_l, states)
+             : build_groups<double>(b->rd, n, &b->prm, plans, m_h, m_l, w_h, w_l, states);
     if (st) return st;
     *out = b.release();
     return DECT_OK;
@@ -239,7 +276,7 @@ dect_status dect_batch_iterate(dect_batch* b, int n_iters, void* stream) {
 
 int dect_batch_groups(const dect_batch* b) {
     if (!b) return 0;
-    return b->dtype == DECT_F32 ? (int)b->gf.size() : (int)b->gd.size();
+    return b->dtype == DECT_F32 ? b->rf.groups() : b->rd.groups();
 }
 
 void dect_batch_destroy(dect_batch* b) { delete b; }

@@ -219,6 +219,7 @@ struct SliceJob {
     RedArgs red;
     long N, M;
     int sym, bp_gx, bp_gy, pj_gx, pj_gy;
+    int cg_iters, rho_mode;  // launch structure: slices share launches only if these agree
 };
 
 // Device copies of the argument blocks of n slices of one shape, in slice order.

@@ -73,6 +73,30 @@ class Layout(ctypes.Structure):
                 ("bytes", "x", "y", "uy", "z", "uz", "a", "ua", "Rx", "scalars")]
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_slots", ctypes.c_int),
+                ("step_iters", ctypes.c_int)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("plan", ctypes.c_void_p), ("counts_h", ctypes.c_void_p),
+                ("counts_l", ctypes.c_void_p), ("i0_h", ctypes.c_double),
+                ("i0_l", ctypes.c_double), ("params", Params), ("tol", ctypes.c_double),
+                ("max_iters", ctypes.c_int), ("x_out", ctypes.c_void_p)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32),
+                ("objective", ctypes.c_double), ("rel_change", ctypes.c_double),
+                ("queue_ns", ctypes.c_int64), ("latency_ns", ctypes.c_int64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("submitted", "completed", "queued", "in_flight",
+                                              "peak_in_flight", "steps")] + [
+        ("hbm_held", ctypes.c_size_t)]
+
+
 _lib = None
 
 
@@ -108,6 +132,13 @@ def lib():
             "dect_batch_iterate": [vp, i, vp],
             "dect_batch_groups": [vp],
             "dect_batch_destroy": [vp],
+            "dect_server_create": [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)],
+            "dect_serve_footprint": [vp],
+            "dect_serve_submit": [vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)],
+            "dect_serve_poll": [vp, ctypes.c_uint64, ctypes.POINTER(Result)],
+            "dect_serve_wait": [vp, ctypes.c_uint64, ctypes.c_int64, ctypes.POINTER(Result)],
+            "dect_server_get_stats": [vp, ctypes.POINTER(ServerStats)],
+            "dect_server_destroy": [vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -115,6 +146,8 @@ def lib():
             fn.restype = ctypes.c_int
         L.dect_plan_destroy.restype = None
         L.dect_batch_destroy.restype = None
+        L.dect_server_destroy.restype = None
+        L.dect_serve_footprint.restype = ctypes.c_size_t
         L.dect_state_bytes.restype = ctypes.c_size_t
         L.dect_last_error.restype = ctypes.c_char_p
         L.dect_last_error.argtypes = []
@@ -370,6 +403,80 @@ class Batch:
         h = getattr(self, "handle", None)
         if h and _lib is not None:
             _lib.dect_batch_destroy(h)
+            self.handle = None
+
+    def __del__(self):
+        self.close()
+
+
+class Server:
+    """Continuous-batching server (worker thread and stream in the library).
+
+    submit() copies the counts and returns a ticket; wait()/poll() return
+    (x, result) once the request has finished, x being the [ny, nx, 2] basis
+    images as a host array.
+    """
+
+    def __init__(self, max_slots: int = 64, step_iters: int = 5, hbm_budget: int = 0):
+        C = ServerConfig()
+        C.hbm_budget_bytes, C.max_slots, C.step_iters = int(hbm_budget), int(max_slots), int(step_iters)
+        h = ctypes.c_void_p()
+        _check(lib().dect_server_create(ctypes.byref(C), ctypes.byref(h)))
+        self.handle = h
+        self._out = {}
+
+    @staticmethod
+    def footprint(plan: "Plan") -> int:
+        return int(lib().dect_serve_footprint(plan.handle))
+
+    def submit(self, plan: "Plan", counts_h, counts_l, i0_h, i0_l=None,
+               params: AdmmParams | None = None, tol: float = 1e-4, max_iters: int = 100) -> int:
+        import numpy as np
+        npdt = np.float32 if plan.dtype == torch.float32 else np.float64
+        ch = np.ascontiguousarray(counts_h, dtype=npdt).reshape(-1)
+        cl = np.ascontiguousarray(counts_l, dtype=npdt).reshape(-1)
+        if ch.size != plan.V * plan.D or cl.size != plan.V * plan.D:
+            raise ValueError("counts must have n_views * n_det entries")
+        x = np.empty((plan.ny, plan.nx, 2), dtype=npdt)
+        P, _ = (params or AdmmParams()).c_struct()
+        R = Request()
+        R.plan = plan.handle.value
+        R.counts_h, R.counts_l = ch.ctypes.data, cl.ctypes.data
+        R.i0_h = float(i0_h)
+        R.i0_l = float(i0_h if i0_l is None else i0_l)
+        R.params = P
+        R.tol, R.max_iters = float(tol), int(max_iters)
+        R.x_out = x.ctypes.data
+        t = ctypes.c_uint64()
+        _check(lib().dect_serve_submit(self.handle, ctypes.byref(R), ctypes.byref(t)))
+        self._out[t.value] = (x, plan)
+        return t.value
+
+    def wait(self, ticket: int, timeout_ms: int = -1):
+        """(x, result dict) once done; None if still running after timeout_ms."""
+        R = Result()
+        st = lib().dect_serve_wait(self.handle, ctypes.c_uint64(ticket), int(timeout_ms),
+                                   ctypes.byref(R))
+        if st == DECT_NOT_READY:
+            return None
+        _check(st)
+        x, _ = self._out.pop(ticket)
+        return x, dict(status=R.status, iters=R.iters, objective=R.objective,
+                       rel_change=R.rel_change, queue_s=R.queue_ns * 1e-9,
+                       latency_s=R.latency_ns * 1e-9)
+
+    def poll(self, ticket: int):
+        return self.wait(ticket, 0)
+
+    def stats(self) -> dict:
+        S = ServerStats()
+        _check(lib().dect_server_get_stats(self.handle, ctypes.byref(S)))
+        return {k: getattr(S, k) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            _lib.dect_server_destroy(h)
             self.handle = None
 
     def __del__(self):
