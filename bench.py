@@ -25,6 +25,56 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "admm_fan512_hbm_traffic.txt")
+KERNEL_SOURCES = ["tomo.hip", "udm.hip", "admm.hip", "kernels.h", "common.h"]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1905_00934_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counted_traffic() -> dict:
+    """HBM bytes per dispatch from the committed FETCH_SIZE/WRITE_SIZE summary,
+    only while the kernel sources are the ones the counters were taken on."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return {}
+    meta, table = {}, {}
+    for line in open(TRAFFIC_FILE):
+        parts = line.split()
+        if not parts or parts[0].startswith("#"):
+            continue
+        if parts[0] == "kernel":
+            # Both orbit-image kernels are timed together under one name.
+            name = "orbit" if parts[1] == "orbit_t" else parts[1]
+            table[name] = table.get(name, 0) + int(parts[-1])
+        else:
+            meta[parts[0]] = parts[1]
+    return table if meta.get("source_hash") == kernel_source_hash() else {}
+
+
+def algorithmic_bytes(N: int, M: int, cg_iters: int, elem: int = 4) -> dict:
+    """Compulsory HBM bytes per launch of each kernel of the FP32 iteration: every
+    array it must read or write once (images N pixels, sinograms M rays, two
+    channels)."""
+    extra = 2 * N if cg_iters > 1 else 0
+    return {k: v * elem for k, v in {
+        "backproject_rhs": 2 * M + 16 * N + extra,  # t; x, y, u^y, z, u^z; p (and r)
+        "backproject_q": 2 * M + 2 * N + extra,     # R p; p (and q)
+        "backproject_dual": 2 * M + 6 * N,          # da; dy, dz
+        "project": 2 * N + 2 * M,                   # p; R p
+        "orbit": 2 * (2 * N + 8 * N),               # two orbit images of p
+        "udm": 34 * M,                              # m, w, a, R x, R p, u^a, f cache in; a, u^a, R x, t, da, cache out
+        "tv_dual": 32 * N,                          # x, y, u^y, z, u^z in; y, u^y, dy, z, u^z, dz out
+        "rescale": 10 * M + 12 * N,
+        "cg_vector": 6 * N,
+    }.items()}
+
+
 def _gen(job):
     """Counts of one synthetic slice (runs in a worker process)."""
     from paper_1905_00934_amd import synth
@@ -272,24 +322,35 @@ def main():
           for b in range(2)]
 
     info = plan.info()
+    N, M = info["n_pixels"], info["n_rays"]
     # Algorithmic VALU operations of one two-channel R or R^T application: per Joseph
     # sample the position (fma), floor and fraction; per channel the difference, the
     # interpolating fma and the accumulation.
     ops_apply = 3 * info["samples"] + 3 * 2 * info["samples"]
-    per_kernel = {k: {"avg_us": 1e3 * v[0] / v[1], "launches": v[1],
-                      "share": v[0] / sum(t for t, _ in kt.values())} for k, v in kt.items()}
+    alg = algorithmic_bytes(N, M, params.cg_iters)
+    counted = counted_traffic()
+    total = sum(t for t, _ in kt.values())
+    per_kernel = {}
+    for k, (t_ms, n) in kt.items():
+        avg_s = t_ms / n / 1e3
+        e = {"avg_us": round(avg_s * 1e6, 3), "launches": n, "share": round(t_ms / total, 4)}
+        if k in alg:
+            e["hbm_alg_bytes"] = alg[k]
+            e["hbm_alg_frac"] = round(alg[k] / avg_s / 1e9 / HBM_PEAK_GBS, 4)
+        if k in counted:
+            e["hbm_counted_bytes"] = counted[k]
+            e["hbm_counted_gbs"] = round(counted[k] / avg_s / 1e9, 1)
+        per_kernel[k] = e
     dominant = max(kt, key=lambda k: kt[k][0])
-    bp = [k for k in kt if k.startswith("backproject")]
-    roof_name = dominant
-    avg_s = kt[roof_name][0] / kt[roof_name][1] / 1e3
+    avg_s = kt[dominant][0] / kt[dominant][1] / 1e3
     achieved = ops_apply / avg_s / 1e12
-    alg_bytes = 4 * (2 * info["n_pixels"] + 2 * info["n_rays"])
-    roofline = {"kernel": roof_name, "bound": "alu", "achieved": round(achieved, 3),
+    roofline = {"kernel": dominant, "bound": "alu", "achieved": round(achieved, 3),
                 "peak": round(VALU_PEAK_TOPS, 2), "unit": "TOP/s",
-                "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
+                "frac": round(achieved / VALU_PEAK_TOPS, 4),
+                "traffic": counted.get(dominant),
                 "ops_per_launch": ops_apply, "avg_launch_us": round(avg_s * 1e6, 2),
-                "hbm_alg_bytes_per_launch": alg_bytes,
-                "hbm_alg_frac": round(alg_bytes / avg_s / 1e9 / HBM_PEAK_GBS, 5)}
+                "hbm_alg_bytes_per_launch": alg.get(dominant),
+                "hbm_alg_frac": per_kernel[dominant].get("hbm_alg_frac")}
 
     out = {
         "metric": "ADMM iters/s on 512² fan-beam slice",
@@ -310,8 +371,7 @@ def main():
                    "slices": 1, "image": 512, "views": 720, "bins": 1024,
                    "lm_iters": 1, "cg_iters": 1},
         "roofline": roofline,
-        "kernels": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
-                        for kk, vv in v.items()} for k, v in per_kernel.items()},
+        "kernels": per_kernel,
         "accuracy": {"xi_c_db": round(xi[0], 3), "xi_p_db": round(xi[1], 3),
                      "iterations": args.warmup + 2 * args.steps + 1,
                      "rho": log[-1]["rho"]},
