@@ -184,81 +184,168 @@ __global__ __launch_bounds__(64 * KS) void k_project(const ProjArgs<T>* __restri
     }
 }
 
-// Candidate bins [lo, hi] of a segment for the point at detector coordinate bc
-// whose two-pixel neighbourhood spans +-db bins (linearised, margin m).
-template <typename T>
-__device__ inline void bin_range(T bc, T db, T m, int seg0, int seg1, int D, int& lo, int& hi) {
-    const T h = fabs(db) + m;
-    const T bl = fmax(bc - h, T(-1)), bh = fmin(bc + h, T(D));
-    lo = (int)ceil(bl);
-    hi = (int)floor(bh);
-    lo = lo > seg0 ? lo : seg0;
-    hi = hi < seg1 - 1 ? hi : seg1 - 1;
-}
-
 template <typename T>
 __device__ inline T fast_rcp(T x) { return T(1) / x; }
 template <>
 __device__ inline float fast_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // Sum over the base views of this wave (v = wave, wave + VS, ...) for the orbit
-// of pixel (i, j).  Pixel rot^k(p) seen from view v + k' Vb has the weight of
-// base view v at pixel rot^(k - k')(p), so for every orbit member p_m = rot^m(p)
-// the base-view weights are evaluated once and routed to acc[(m + k') mod SYM]
-// with sinogram row v + k' Vb, for all k'.  The footprint needs only ~1e-3-bin
-// accuracy (the margin covers it), hence the hardware reciprocal.
-template <typename T, int CH, int SYM, bool QUAD, int VS>
+// of pixel (i, j), reading a standard [V][D][CH] sinogram.  Pixel rot^k(p) seen
+// from view v + k' Vb has the weight of base view v at pixel rot^(k - k')(p), so
+// for every orbit member p_m = rot^m(p) the base-view weights are evaluated once
+// and routed to acc[(m + k') mod SYM] with sinogram row v + k' Vb, for all k'.
+//
+// Candidates are the bins within h = max|d beta / d pixel| + margin of the
+// member's detector coordinate beta (a ray more than one pixel step away along
+// its minor axis has no tap on the pixel); the footprint needs only ~1e-3-bin
+// accuracy, which the margin covers, hence the hardware reciprocal.  The ray's
+// type says which pixel coordinate it samples along, and the weight
+// max(0, step (1 - |phi - p|)) is the projector's linear-interpolation weight of
+// the pixel at minor coordinate p for the sample at phi, phi computed with the
+// projector's own fma on the same table entries.
+template <typename T, int CH, int SYM, int VS>
 __device__ inline void gather_orbit(const BpArgs<T>& a, int wave, int i, int j,
                                     T (&acc)[SYM][CH]) {
     const T m = (T)a.margin;
     const int D = a.D, Vb = a.Vb, n = a.nx;
     const T cx = T(0.5) * (T)(a.nx - 1), cy = T(0.5) * (T)(a.ny - 1);
+    const vec<T, CH>* __restrict__ sv = reinterpret_cast<const vec<T, CH>*>(a.sino);
     for (int v = wave; v < Vb; v += VS) {
         const ViewParam<T> w = a.views[v];
         const RayParam<T>* __restrict__ rv = a.rays + (size_t)v * D;
-        const vec<T, CH>* __restrict__ sv = reinterpret_cast<const vec<T, CH>*>(a.sino);
-        const vec<T, SYM * CH>* __restrict__ sq =
-            reinterpret_cast<const vec<T, SYM * CH>*>(a.sino) + (size_t)v * D;
 #pragma unroll
         for (int mm = 0; mm < SYM; ++mm) {
             int im, jm;
             rot(mm, n, i, j, im, jm);
             const T fi = (T)im, fj = (T)jm;
             const T ip = fi - cx, jp = fj - cy;
-            const T num = w.ni * ip + w.nj * jp;
-            const T den = w.d0 + w.di * ip + w.dj * jp;
-            const T inv = fast_rcp<T>(den);
-            const T bq = num * inv;
+            const T inv = fast_rcp<T>(w.d0 + w.di * ip + w.dj * jp);
+            const T bq = (w.ni * ip + w.nj * jp) * inv;
             const T bc = bq + w.boff;
-            // d(beta) for one pixel step along y (x-stepped rays) and along x.
+            // d(beta) for one pixel step along y and along x.
             const T dby = (w.nj - bq * w.dj) * inv;
             const T dbx = (w.ni - bq * w.di) * inv;
+            const T h = fmax(fabs(dby), fabs(dbx)) + m;
+            const int lo0 = (int)ceil(fmax(bc - h, T(-1)));
+            const int hi0 = (int)floor(fmin(bc + h, T(D)));
+            const int lo = lo0 > 0 ? lo0 : 0, hi = hi0 < D - 1 ? hi0 : D - 1;
+            for (int b = lo; b <= hi; ++b) {
+                const RayParam<T> r = rv[b];
+                const bool xs = r.pad == T(0);
+                const T phi = fma(r.slope, xs ? fi : fj, r.phi0);
+                const T wt = fmax(T(0), fma(-r.step, fabs(phi - (xs ? fj : fi)), r.step));
 #pragma unroll
-            for (int seg = 0; seg < 2; ++seg) {
-                const bool xseg = seg == 0;
-                int lo, hi;
-                if (xseg) bin_range<T>(bc, dby, m, w.xb0, w.xb1, D, lo, hi);
-                else bin_range<T>(bc, dbx, m, w.yb0, w.yb1, D, lo, hi);
-                const T fs = xseg ? fi : fj;   // sampling coordinate
-                const T fp = xseg ? fj : fi;   // interpolated coordinate of the pixel
+                for (int kp = 0; kp < SYM; ++kp) {
+                    const vec<T, CH> t = sv[(size_t)(v + kp * Vb) * D + b];
+#pragma unroll
+                    for (int c = 0; c < CH; ++c) acc[(mm + kp) % SYM][c] += wt * t.v[c];
+                }
+            }
+        }
+    }
+}
+
+// Quarter turns of a real point about the image centre, as rot() for pixels.
+template <typename T>
+__device__ inline void rotf(int k, int n, T i, T j, T& io, T& jo) {
+    const T e = (T)(n - 1);
+    switch (k & 3) {
+        case 0: io = i; jo = j; break;
+        case 1: io = e - j; jo = i; break;
+        case 2: io = e - i; jo = e - j; break;
+        default: io = j; jo = e - i; break;
+    }
+}
+
+// As gather_orbit for quad sinograms, with each view's candidate records staged in
+// LDS.  A wave covers the 64 orbits of its block: per view and orbit member their
+// candidate bins lie within a few bins of the block centre's detector coordinate,
+// so WIN records around it (ray parameters and the quad of sinogram values) are
+// loaded once per view by WIN lanes and read by every lane from LDS instead of
+// each lane loading them again.  The loads for the wave's next view are issued
+// before the current view is accumulated, so their latency is hidden.  A candidate
+// outside the window (a steep footprint near the source) is loaded directly.
+template <typename T, int CH, int SYM, int VS>
+__device__ inline void gather_orbit_staged(const BpArgs<T>& a, int wave, int lane, int i, int j,
+                                           bool inside, T (&acc)[SYM][CH]) {
+    constexpr int WIN = 16;
+    using Q = vec<T, SYM * CH>;
+    __shared__ RayParam<T> s_ray[VS][WIN * SYM];
+    __shared__ Q s_sino[VS][WIN * SYM];
+    const T m = (T)a.margin;
+    const int D = a.D, Vb = a.Vb, n = a.nx;
+    const T cx = T(0.5) * (T)(a.nx - 1), cy = T(0.5) * (T)(a.ny - 1);
+    const Q* __restrict__ sino = reinterpret_cast<const Q*>(a.sino);
+    // This lane stages bin sk of the window of orbit member sm, centred on the
+    // detector coordinate of the block centre seen as that member.
+    const int sm = lane / WIN, sk = lane % WIN;
+    const bool stager = lane < WIN * SYM;
+    T icm, jcm;
+    rotf<T>(sm, n, (T)(blockIdx.x * 8) + T(3.5), (T)(blockIdx.y * 8) + T(3.5), icm, jcm);
+    const T ipc = icm - cx, jpc = jcm - cy;
+    RayParam<T> pr{};
+    Q pq;
+    int pL = 0;
+    auto stage = [&](int v) {
+        const ViewParam<T> w = a.views[v];
+        const T bq = (w.ni * ipc + w.nj * jpc) / (w.d0 + w.di * ipc + w.dj * jpc);
+        pL = (int)floor(bq + w.boff) - (WIN / 2 - 1);
+        const int b = pL + sk;
+        if (stager && b >= 0 && b < D) {
+            pr = a.rays[(size_t)v * D + b];
+            pq = sino[(size_t)v * D + b];
+        } else {
+            pr = RayParam<T>{};
+#pragma unroll
+            for (int c = 0; c < SYM * CH; ++c) pq.v[c] = T(0);
+        }
+    };
+    if (wave < Vb) stage(wave);
+    for (int v = wave; v < Vb; v += VS) {
+        int L[SYM];
+#pragma unroll
+        for (int mm = 0; mm < SYM; ++mm) L[mm] = __builtin_amdgcn_readlane(pL, mm * WIN);
+        if (stager) {
+            s_ray[wave][lane] = pr;
+            s_sino[wave][lane] = pq;
+        }
+        // LDS operations of one wave complete in order; the barrier only keeps the
+        // compiler from moving the reads above the writes.
+        __builtin_amdgcn_wave_barrier();
+        if (v + VS < Vb) stage(v + VS);
+        if (inside) {
+            const ViewParam<T> w = a.views[v];
+            const RayParam<T>* __restrict__ rv = a.rays + (size_t)v * D;
+            const Q* __restrict__ sq = sino + (size_t)v * D;
+#pragma unroll
+            for (int mm = 0; mm < SYM; ++mm) {
+                int im, jm;
+                rot(mm, n, i, j, im, jm);
+                const T fi = (T)im, fj = (T)jm;
+                const T ip = fi - cx, jp = fj - cy;
+                const T inv = fast_rcp<T>(w.d0 + w.di * ip + w.dj * jp);
+                const T bq = (w.ni * ip + w.nj * jp) * inv;
+                const T bc = bq + w.boff;
+                const T dby = (w.nj - bq * w.dj) * inv;
+                const T dbx = (w.ni - bq * w.di) * inv;
+                const T h = fmax(fabs(dby), fabs(dbx)) + m;
+                const int lo0 = (int)ceil(fmax(bc - h, T(-1)));
+                const int hi0 = (int)floor(fmin(bc + h, T(D)));
+                const int lo = lo0 > 0 ? lo0 : 0, hi = hi0 < D - 1 ? hi0 : D - 1;
                 for (int b = lo; b <= hi; ++b) {
-                    const RayParam<T> r = rv[b];
-                    vec<T, SYM * CH> s;
-                    if constexpr (QUAD) {
-                        s = sq[b];
+                    const int idx = b - L[mm];
+                    RayParam<T> r;
+                    Q s;
+                    if ((unsigned)idx < (unsigned)WIN) {
+                        r = s_ray[wave][mm * WIN + idx];
+                        s = s_sino[wave][mm * WIN + idx];
                     } else {
-#pragma unroll
-                        for (int kp = 0; kp < SYM; ++kp) {
-                            const vec<T, CH> t = sv[(size_t)(v + kp * Vb) * D + b];
-#pragma unroll
-                            for (int c = 0; c < CH; ++c) s.v[kp * CH + c] = t.v[c];
-                        }
+                        r = rv[b];
+                        s = sq[b];
                     }
-                    const T phi = fma(r.slope, fs, r.phi0);
-                    const T fl = floor(phi);
-                    const T al = phi - fl;
-                    T wt = fl == fp ? T(1) - al : (fl == fp - T(1) ? al : T(0));
-                    wt *= r.step;
+                    const bool xs = r.pad == T(0);
+                    const T phi = fma(r.slope, xs ? fi : fj, r.phi0);
+                    const T wt = fmax(T(0), fma(-r.step, fabs(phi - (xs ? fj : fi)), r.step));
 #pragma unroll
                     for (int kp = 0; kp < SYM; ++kp)
 #pragma unroll
@@ -267,6 +354,7 @@ __device__ inline void gather_orbit(const BpArgs<T>& a, int wave, int i, int j,
                 }
             }
         }
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -370,7 +458,10 @@ __global__ __launch_bounds__(64 * VS) void k_backproject(const BpArgs<T>* __rest
     for (int k = 0; k < SYM; ++k)
 #pragma unroll
         for (int c = 0; c < CH; ++c) acc[k][c] = T(0);
-    if (inside) gather_orbit<T, CH, SYM, QUAD, VS>(a, wave, i, j, acc);
+    if constexpr (QUAD)
+        gather_orbit_staged<T, CH, SYM, VS>(a, wave, lane, i, j, inside, acc);
+    else if (inside)
+        gather_orbit<T, CH, SYM, VS>(a, wave, i, j, acc);
     if constexpr (VS > 1) {
         if (wave > 0)
 #pragma unroll

@@ -219,6 +219,23 @@ def test_admm_fp64_tiny_matches_oracle(dect):
         np.testing.assert_allclose(eg["s"], eo["s"], rtol=1e-7)
 
 
+def test_admm_fp64_symmetric_fan_matches_oracle(dect):
+    """Quarter-turn symmetric fan (the quad-record path of R and R^T) in FP64."""
+    g = GEOMS["sym_fan"]
+    k = g["nx"] * g["pixel_cm"] / 32.0
+    ph = S.tiny_phantom(5)
+    ph = S.Phantom([S.Shape(sh.kind, k * sh.cx, k * sh.cy, k * sh.ax, k * sh.ay, sh.rot,
+                            sh.xc, sh.xp) for sh in ph.shapes])
+    pr = S.make_problem("sym_fan", g, ph, 1e5, 5, with_image=False)
+    prm = O.Params(cg_iters=2, lm_iters=2)
+    ost = _admm_oracle(pr, prm, 8)
+    _, st, log = _admm_gpu(dect, pr, F64, dect.AdmmParams(cg_iters=2, lm_iters=2), 8)
+    x = host(st.x)
+    for b in range(2):
+        assert rel(x[..., b], ost.x[b]) <= 1e-8
+    assert [e["rho"] for e in log] == [tuple(e["rho"]) for e in ost.log]
+
+
 @pytest.mark.parametrize("n_iters,size", [(50, 256), (3, 512)])
 def test_admm_fp32_matches_oracle_after_fixed_iterations(dect, n_iters, size):
     """FP32 fan-beam slices against the FP64 oracle; rho follows the oracle's own
