@@ -140,6 +140,7 @@ def batch_workload(dect, torch, dev, items, params, steps, warmup):
         key = (geom["nx"], geom["ny"], geom["n_views"], geom["n_det"])
         if key not in plans:
             plans[key] = dect.Plan(geom, spec, torch.float32, device=dev)
+            plans[key].tune()
         plan = plans[key]
         c = [torch.from_numpy(x).to(dev) for x in (ch, cl)]
         meas = list(plan.ingest(c[0], c[1], i0))
@@ -178,6 +179,7 @@ def batch_workload(dect, torch, dev, items, params, steps, warmup):
                            out["plain"]["slice_iters_per_s"], 4)
     out["identical_states"] = identical
     out["groups"] = len(plans)
+    out["launch"] = {f"{k[0]}x{k[1]}/{k[2]}x{k[3]}": p.launch() for k, p in plans.items()}
     out["kernels_per_batch_iter_us"] = {k: round(1e3 * v[0] / 2, 2) for k, v in kt.items()}
     return out
 
@@ -195,6 +197,7 @@ def serve_workload(dect, torch, dev, items, args):
         key = (geom["nx"], geom["ny"], geom["n_views"], geom["n_det"])
         if key not in plans:
             plans[key] = dect.Plan(geom, spec, torch.float32, device=dev)
+            plans[key].tune()
         reqs.append((plans[key], i0, ch, cl))
     params = dect.AdmmParams()
     tol, max_iters, step = 1e-4, 100, 5
@@ -293,6 +296,7 @@ def main():
     torch.cuda.set_device(dev)
     pr = synth.slice_problem(0, with_image=True)
     plan = dect.Plan(pr.geom, pr.spec, torch.float32, device=dev)
+    tuned = plan.tune()
     counts = [torch.from_numpy(c).to(dev, torch.float32) for c in (pr.counts_high, pr.counts_low)]
     meas = list(plan.ingest(counts[0], counts[1], pr.i0))
     params = dect.AdmmParams()
@@ -371,6 +375,8 @@ def main():
                    "slices": 1, "image": 512, "views": 720, "bins": 1024,
                    "lm_iters": 1, "cg_iters": 1},
         "roofline": roofline,
+        "launch": {"bp_waves": tuned["bp_waves"], "proj_waves": tuned["proj_waves"],
+                   "tuned_by": "dect_plan_tune (timed on this device)"},
         "kernels": per_kernel,
         "accuracy": {"xi_c_db": round(xi[0], 3), "xi_p_db": round(xi[1], 3),
                      "iterations": args.warmup + 2 * args.steps + 1,

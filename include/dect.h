@@ -212,6 +212,33 @@ dect_status dect_admm_iterate(const dect_plan* plan, const void* m_h, const void
 dect_status dect_state_log(const dect_plan* plan, const void* state, int64_t first, int n,
                            dect_iter_log* log, void* stream);
 
+/* ----------------------------------------------------------- autotuning --- */
+
+/* Workgroup shapes of the ADMM's transposed projector (waves of a workgroup
+ * splitting the views) and projector (waves splitting the image lines): 2, 4 or
+ * 8 each, 4 by default.  Every shape computes the same sums; only the order in
+ * which a workgroup's partial sums are added changes.  Batches share launches
+ * only between slices whose plans have the same shapes. */
+typedef struct {
+    int bp_waves;      /* transposed projector */
+    int proj_waves;    /* projector */
+    double bp_us;      /* timed duration of the chosen shapes (0 when not timed) */
+    double proj_us;
+    int from_cache;    /* 1 if taken from the cache without timing */
+} dect_launch;
+
+#define DECT_TUNE_FORCE 1  /* time the candidates even if the cache has an entry */
+
+/* Choose the plan's workgroup shapes: from the cache file if it has an entry for
+ * this device, precision and problem shape, else by timing every candidate on a
+ * scratch state on `stream` (synchronises; allocates a temporary state) and
+ * appending the result to the cache (cache_path NULL: no cache).  The plan is
+ * updated; out (may be NULL) receives the choice. */
+dect_status dect_plan_tune(dect_plan* plan, const char* cache_path, int flags, dect_launch* out,
+                           void* stream);
+dect_status dect_plan_set_launch(dect_plan* plan, int bp_waves, int proj_waves);
+dect_status dect_plan_get_launch(const dect_plan* plan, dect_launch* out);
+
 /* ---------------------------------------------------------------- batch --- */
 
 /* Independent slices (Sec. 3.3 per slice: each detector row or table position

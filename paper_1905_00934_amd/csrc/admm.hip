@@ -359,6 +359,8 @@ SliceJob<T> make_job(const dect_plan* p, const void* mh, const void* ml, const v
     J.N = p->N;
     J.M = p->M;
     J.sym = p->sym;
+    J.bp_waves = p->bp_waves;
+    J.pj_waves = p->pj_waves;
     J.pj_gx = (p->D + 63) / 64;
     J.pj_gy = p->Vb;
     J.orb = OrbitArgs<T>{pp, pO, pOT, p->nx, p->ny};
@@ -447,15 +449,15 @@ hipError_t iteration_t(const SliceJob<T>& J, const JobArrays<T>* dev, int nsl,
     } while (0)
     const dim3 gN(nblk(J.N), 1, z), gM(nblk(J.M), 1, z);
     const VecArgs<T>* dvec = dev ? dev->vec : nullptr;
-    DECT_TRY(launch_backproject_admm<T>(J.sym, EPI_RHS, dev ? dev->rhs : nullptr, J.rhs, nsl,
-                                        J.bp_gx, J.bp_gy, s));
+    DECT_TRY(launch_backproject_admm<T>(J.sym, J.bp_waves, EPI_RHS, dev ? dev->rhs : nullptr,
+                                        J.rhs, nsl, J.bp_gx, J.bp_gy, s));
     DECT_TRY(reduce(RED_GAMMA));
     for (int c = 0; c < n; ++c) {
-        DECT_TRY(launch_project_pair<T>(J.sym, dev ? dev->orb : nullptr, J.orb,
+        DECT_TRY(launch_project_pair<T>(J.sym, J.pj_waves, dev ? dev->orb : nullptr, J.orb,
                                         dev ? dev->prj : nullptr, J.prj, nsl, J.N, J.pj_gx,
                                         J.pj_gy, s));
-        DECT_TRY(launch_backproject_admm<T>(J.sym, EPI_Q, dev ? dev->q : nullptr, J.q, nsl,
-                                            J.bp_gx, J.bp_gy, s));
+        DECT_TRY(launch_backproject_admm<T>(J.sym, J.bp_waves, EPI_Q, dev ? dev->q : nullptr, J.q,
+                                            nsl, J.bp_gx, J.bp_gy, s));
         DECT_TRY(reduce(RED_ALPHA));
         if (c < n - 1) {
             ProfScope ps("cg_vector", s);
@@ -479,8 +481,9 @@ hipError_t iteration_t(const SliceJob<T>& J, const JobArrays<T>* dev, int nsl,
     }
     DECT_TRY(hipGetLastError());
     if (adaptive)
-        DECT_TRY(launch_backproject_admm<T>(J.sym, EPI_DUAL, dev ? dev->dual : nullptr, J.dual,
-                                            nsl, J.bp_gx, J.bp_gy, s));
+        DECT_TRY(launch_backproject_admm<T>(J.sym, J.bp_waves, EPI_DUAL,
+                                            dev ? dev->dual : nullptr, J.dual, nsl, J.bp_gx,
+                                            J.bp_gy, s));
     DECT_TRY(reduce(RED_FINAL));
     if (prm->rho_mode != DECT_RHO_FIXED) {
         ProfScope ps("rescale", s);

@@ -86,6 +86,9 @@ struct dect_plan {
     // view v; 1: none) and the number of base views Vb = V / sym.
     int sym = 1, Vb = 0;
     double margin = 0.05;   // footprint margin of the transpose, in bins
+    // Workgroup shapes of the ADMM transpose (waves splitting the views) and
+    // projector (waves splitting the lines): 2, 4 or 8, set by dect_plan_tune.
+    int bp_waves = 4, pj_waves = 4;
     // device tables
     void* rays = nullptr;   // RayParam<T>[Vb * D]
     void* views = nullptr;  // ViewParam<T>[Vb]

@@ -92,18 +92,21 @@ template <typename T>
 hipError_t launch_project(const dect_plan* p, const void* img, void* sino, int ch, hipStream_t s);
 // Two-channel projection of the ADMM direction into quad-interleaved records, for
 // one slice (dev == nullptr: `one`) or n slices (dev: device arrays); the grid is
-// (gx, gy) projector blocks and `pixels` orbit-image threads per slice.
+// (gx, gy) projector blocks of `waves` (2, 4 or 8) waves splitting the lines, and
+// `pixels` orbit-image threads per slice.
 template <typename T>
-hipError_t launch_project_pair(int sym, const OrbitArgs<T>* odev, const OrbitArgs<T>& oone,
-                               const ProjArgs<T>* pdev, const ProjArgs<T>& pone, int n,
-                               long pixels, int gx, int gy, hipStream_t s);
+hipError_t launch_project_pair(int sym, int waves, const OrbitArgs<T>* odev,
+                               const OrbitArgs<T>& oone, const ProjArgs<T>* pdev,
+                               const ProjArgs<T>& pone, int n, long pixels, int gx, int gy,
+                               hipStream_t s);
 // Plain R^T of a standard-order sinogram with ch channels (one slice).
 template <typename T>
 hipError_t launch_backproject(const dect_plan* p, int ch, const BpArgs<T>& a, hipStream_t s);
-// ADMM epilogue variants of R^T on quad records, one or n slices.
+// ADMM epilogue variants of R^T on quad records, one or n slices; `waves` (2, 4
+// or 8) split the views of a workgroup.
 template <typename T>
-hipError_t launch_backproject_admm(int sym, int epi, const BpArgs<T>* dev, const BpArgs<T>& one,
-                                   int n, int gx, int gy, hipStream_t s);
+hipError_t launch_backproject_admm(int sym, int waves, int epi, const BpArgs<T>* dev,
+                                   const BpArgs<T>& one, int n, int gx, int gy, hipStream_t s);
 // Fill the plan-dependent fields of BpArgs.
 template <typename T>
 void fill_bp_plan(const dect_plan* p, BpArgs<T>& a);
@@ -219,6 +222,7 @@ struct SliceJob {
     RedArgs red;
     long N, M;
     int sym, bp_gx, bp_gy, pj_gx, pj_gy;
+    int bp_waves, pj_waves;  // workgroup shapes of the plan
     int cg_iters, rho_mode;  // launch structure: slices share launches only if these agree
 };
 

@@ -506,16 +506,12 @@ __global__ __launch_bounds__(64 * VS) void k_backproject(const BpArgs<T>* __rest
     }
 }
 
-#ifndef DECT_VIEW_SPLIT
-#define DECT_VIEW_SPLIT 4
-#endif
-#ifndef DECT_LINE_SPLIT
-#define DECT_LINE_SPLIT 4
-#endif
-constexpr int kViewSplit = DECT_VIEW_SPLIT;  // waves per transpose workgroup
-constexpr int kLineSplit = DECT_LINE_SPLIT;  // waves per projector workgroup
+// Waves per workgroup of the plain transposed projector and projector; the ADMM
+// kernels take theirs from the plan (2, 4 or 8; see dect_plan_tune).
+constexpr int kViewSplit = 4;
+constexpr int kLineSplit = 4;
 
-template <typename T, int CH, int SYM, bool QUAD, bool BATCH>
+template <typename T, int CH, int SYM, bool QUAD, bool BATCH, int KS>
 void project_launch(const OrbitArgs<T>* odev, const OrbitArgs<T>& oone, const ProjArgs<T>* pdev,
                     const ProjArgs<T>& pone, int n, long pixels, int gx, int gy, hipStream_t s) {
     const dim3 og((unsigned)((pixels + 255) / 256), 1, n);
@@ -525,18 +521,18 @@ void project_launch(const OrbitArgs<T>* odev, const OrbitArgs<T>& oone, const Pr
         hipLaunchKernelGGL((k_orbit<T, CH, SYM, true, BATCH>), og, dim3(256), 0, s, odev, oone);
     }
     ProfScope pp("project", s);
-    hipLaunchKernelGGL((k_project<T, CH, SYM, QUAD, kLineSplit, BATCH>), dim3(gx, gy, n),
-                       dim3(64 * kLineSplit), 0, s, pdev, pone);
+    hipLaunchKernelGGL((k_project<T, CH, SYM, QUAD, KS, BATCH>), dim3(gx, gy, n), dim3(64 * KS),
+                       0, s, pdev, pone);
 }
 
-template <typename T, int CH, int SYM, bool QUAD>
+template <typename T, int CH, int SYM, bool QUAD, int KS>
 hipError_t project_t(const OrbitArgs<T>* odev, const OrbitArgs<T>& oone,
                      const ProjArgs<T>* pdev, const ProjArgs<T>& pone, int n, long pixels, int gx,
                      int gy, hipStream_t s) {
     if (odev)
-        project_launch<T, CH, SYM, QUAD, true>(odev, oone, pdev, pone, n, pixels, gx, gy, s);
+        project_launch<T, CH, SYM, QUAD, true, KS>(odev, oone, pdev, pone, n, pixels, gx, gy, s);
     else
-        project_launch<T, CH, SYM, QUAD, false>(odev, oone, pdev, pone, n, pixels, gx, gy, s);
+        project_launch<T, CH, SYM, QUAD, false, KS>(odev, oone, pdev, pone, n, pixels, gx, gy, s);
     return hipGetLastError();
 }
 
@@ -548,20 +544,20 @@ hipError_t bp_plain(const BpArgs<T>& one, hipStream_t s) {
 }
 
 // The ADMM's own sinograms are two-channel quad records.
-template <typename T, int SYM, bool BATCH>
+template <typename T, int SYM, bool BATCH, int VS>
 hipError_t bp_admm_t(int epi, const BpArgs<T>* dev, const BpArgs<T>& one, int n, int gx, int gy,
                      hipStream_t s) {
     const dim3 g(gx, gy, n);
-    const dim3 blk(64 * kViewSplit);
+    const dim3 blk(64 * VS);
     switch (epi) {
         case EPI_RHS:
-            hipLaunchKernelGGL((k_backproject<T, 2, SYM, true, EPI_RHS, kViewSplit, BATCH>), g, blk, 0, s, dev, one);
+            hipLaunchKernelGGL((k_backproject<T, 2, SYM, true, EPI_RHS, VS, BATCH>), g, blk, 0, s, dev, one);
             break;
         case EPI_Q:
-            hipLaunchKernelGGL((k_backproject<T, 2, SYM, true, EPI_Q, kViewSplit, BATCH>), g, blk, 0, s, dev, one);
+            hipLaunchKernelGGL((k_backproject<T, 2, SYM, true, EPI_Q, VS, BATCH>), g, blk, 0, s, dev, one);
             break;
         case EPI_DUAL:
-            hipLaunchKernelGGL((k_backproject<T, 2, SYM, true, EPI_DUAL, kViewSplit, BATCH>), g, blk, 0, s, dev, one);
+            hipLaunchKernelGGL((k_backproject<T, 2, SYM, true, EPI_DUAL, VS, BATCH>), g, blk, 0, s, dev, one);
             break;
         default:
             return hipErrorInvalidValue;
@@ -569,11 +565,34 @@ hipError_t bp_admm_t(int epi, const BpArgs<T>* dev, const BpArgs<T>& one, int n,
     return hipGetLastError();
 }
 
+template <typename T, int SYM, bool BATCH>
+hipError_t bp_admm_w(int waves, int epi, const BpArgs<T>* dev, const BpArgs<T>& one, int n, int gx,
+                     int gy, hipStream_t s) {
+    switch (waves) {
+        case 2: return bp_admm_t<T, SYM, BATCH, 2>(epi, dev, one, n, gx, gy, s);
+        case 4: return bp_admm_t<T, SYM, BATCH, 4>(epi, dev, one, n, gx, gy, s);
+        case 8: return bp_admm_t<T, SYM, BATCH, 8>(epi, dev, one, n, gx, gy, s);
+    }
+    return hipErrorInvalidValue;
+}
+
 template <typename T, int SYM>
-hipError_t bp_admm(int epi, const BpArgs<T>* dev, const BpArgs<T>& one, int n, int gx, int gy,
-                   hipStream_t s) {
-    return dev ? bp_admm_t<T, SYM, true>(epi, dev, one, n, gx, gy, s)
-               : bp_admm_t<T, SYM, false>(epi, dev, one, n, gx, gy, s);
+hipError_t bp_admm(int waves, int epi, const BpArgs<T>* dev, const BpArgs<T>& one, int n, int gx,
+                   int gy, hipStream_t s) {
+    return dev ? bp_admm_w<T, SYM, true>(waves, epi, dev, one, n, gx, gy, s)
+               : bp_admm_w<T, SYM, false>(waves, epi, dev, one, n, gx, gy, s);
+}
+
+template <typename T, int SYM>
+hipError_t project_pair_w(int waves, const OrbitArgs<T>* odev, const OrbitArgs<T>& oone,
+                          const ProjArgs<T>* pdev, const ProjArgs<T>& pone, int n, long pixels,
+                          int gx, int gy, hipStream_t s) {
+    switch (waves) {
+        case 2: return project_t<T, 2, SYM, true, 2>(odev, oone, pdev, pone, n, pixels, gx, gy, s);
+        case 4: return project_t<T, 2, SYM, true, 4>(odev, oone, pdev, pone, n, pixels, gx, gy, s);
+        case 8: return project_t<T, 2, SYM, true, 8>(odev, oone, pdev, pone, n, pixels, gx, gy, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 const char* bp_name(int epi) {
@@ -609,26 +628,27 @@ hipError_t launch_project(const dect_plan* p, const void* img, void* sino, int c
     const int gx = (p->D + 63) / 64, gy = p->Vb;
     if (p->sym == 4) {
         switch (ch) {
-            case 1: return project_t<T, 1, 4, false>(nullptr, o, nullptr, q, 1, p->N, gx, gy, s);
-            case 2: return project_t<T, 2, 4, false>(nullptr, o, nullptr, q, 1, p->N, gx, gy, s);
-            case 4: return project_t<T, 4, 4, false>(nullptr, o, nullptr, q, 1, p->N, gx, gy, s);
+            case 1: return project_t<T, 1, 4, false, kLineSplit>(nullptr, o, nullptr, q, 1, p->N, gx, gy, s);
+            case 2: return project_t<T, 2, 4, false, kLineSplit>(nullptr, o, nullptr, q, 1, p->N, gx, gy, s);
+            case 4: return project_t<T, 4, 4, false, kLineSplit>(nullptr, o, nullptr, q, 1, p->N, gx, gy, s);
         }
     } else {
         switch (ch) {
-            case 1: return project_t<T, 1, 1, false>(nullptr, o, nullptr, q, 1, p->N, gx, gy, s);
-            case 2: return project_t<T, 2, 1, false>(nullptr, o, nullptr, q, 1, p->N, gx, gy, s);
-            case 4: return project_t<T, 4, 1, false>(nullptr, o, nullptr, q, 1, p->N, gx, gy, s);
+            case 1: return project_t<T, 1, 1, false, kLineSplit>(nullptr, o, nullptr, q, 1, p->N, gx, gy, s);
+            case 2: return project_t<T, 2, 1, false, kLineSplit>(nullptr, o, nullptr, q, 1, p->N, gx, gy, s);
+            case 4: return project_t<T, 4, 1, false, kLineSplit>(nullptr, o, nullptr, q, 1, p->N, gx, gy, s);
         }
     }
     return hipErrorInvalidValue;
 }
 
 template <typename T>
-hipError_t launch_project_pair(int sym, const OrbitArgs<T>* odev, const OrbitArgs<T>& oone,
-                               const ProjArgs<T>* pdev, const ProjArgs<T>& pone, int n,
-                               long pixels, int gx, int gy, hipStream_t s) {
-    return sym == 4 ? project_t<T, 2, 4, true>(odev, oone, pdev, pone, n, pixels, gx, gy, s)
-                    : project_t<T, 2, 1, true>(odev, oone, pdev, pone, n, pixels, gx, gy, s);
+hipError_t launch_project_pair(int sym, int waves, const OrbitArgs<T>* odev,
+                               const OrbitArgs<T>& oone, const ProjArgs<T>* pdev,
+                               const ProjArgs<T>& pone, int n, long pixels, int gx, int gy,
+                               hipStream_t s) {
+    return sym == 4 ? project_pair_w<T, 4>(waves, odev, oone, pdev, pone, n, pixels, gx, gy, s)
+                    : project_pair_w<T, 1>(waves, odev, oone, pdev, pone, n, pixels, gx, gy, s);
 }
 
 template <typename T>
@@ -653,22 +673,22 @@ hipError_t launch_backproject(const dect_plan* p, int ch, const BpArgs<T>& a0, h
 }
 
 template <typename T>
-hipError_t launch_backproject_admm(int sym, int epi, const BpArgs<T>* dev, const BpArgs<T>& one,
-                                   int n, int gx, int gy, hipStream_t s) {
+hipError_t launch_backproject_admm(int sym, int waves, int epi, const BpArgs<T>* dev,
+                                   const BpArgs<T>& one, int n, int gx, int gy, hipStream_t s) {
     ProfScope ps(bp_name(epi), s);
-    return sym == 4 ? bp_admm<T, 4>(epi, dev, one, n, gx, gy, s)
-                    : bp_admm<T, 1>(epi, dev, one, n, gx, gy, s);
+    return sym == 4 ? bp_admm<T, 4>(waves, epi, dev, one, n, gx, gy, s)
+                    : bp_admm<T, 1>(waves, epi, dev, one, n, gx, gy, s);
 }
 
 #define DECT_INST(T)                                                                          \
     template void fill_bp_plan<T>(const dect_plan*, BpArgs<T>&);                              \
     template hipError_t launch_project<T>(const dect_plan*, const void*, void*, int, hipStream_t); \
-    template hipError_t launch_project_pair<T>(int, const OrbitArgs<T>*, const OrbitArgs<T>&,     \
+    template hipError_t launch_project_pair<T>(int, int, const OrbitArgs<T>*, const OrbitArgs<T>&, \
                                                const ProjArgs<T>*, const ProjArgs<T>&, int, long, \
                                                int, int, hipStream_t);                            \
     template hipError_t launch_backproject<T>(const dect_plan*, int, const BpArgs<T>&, hipStream_t); \
-    template hipError_t launch_backproject_admm<T>(int, int, const BpArgs<T>*, const BpArgs<T>&,  \
-                                                   int, int, int, hipStream_t);
+    template hipError_t launch_backproject_admm<T>(int, int, int, const BpArgs<T>*,              \
+                                                   const BpArgs<T>&, int, int, int, hipStream_t);
 DECT_INST(float)
 DECT_INST(double)
 #undef DECT_INST

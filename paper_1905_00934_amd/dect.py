@@ -73,6 +73,12 @@ class Layout(ctypes.Structure):
                 ("bytes", "x", "y", "uy", "z", "uz", "a", "ua", "Rx", "scalars")]
 
 
+class Launch(ctypes.Structure):
+    _fields_ = [("bp_waves", ctypes.c_int), ("proj_waves", ctypes.c_int),
+                ("bp_us", ctypes.c_double), ("proj_us", ctypes.c_double),
+                ("from_cache", ctypes.c_int)]
+
+
 class ServerConfig(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_slots", ctypes.c_int),
                 ("step_iters", ctypes.c_int)]
@@ -132,6 +138,9 @@ def lib():
             "dect_batch_iterate": [vp, i, vp],
             "dect_batch_groups": [vp],
             "dect_batch_destroy": [vp],
+            "dect_plan_tune": [vp, ctypes.c_char_p, i, ctypes.POINTER(Launch), vp],
+            "dect_plan_set_launch": [vp, i, i],
+            "dect_plan_get_launch": [vp, ctypes.POINTER(Launch)],
             "dect_server_create": [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)],
             "dect_serve_footprint": [vp],
             "dect_serve_submit": [vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)],
@@ -339,6 +348,21 @@ class Plan:
                                         float(i0_h), float(i0_l), *(_ptr(o) for o in outs),
                                         _stream()))
         return tuple(outs)
+
+    def tune(self, cache: str | None = None, force: bool = False) -> dict:
+        """Choose the ADMM kernels' workgroup shapes by timing (or from the cache)."""
+        L = Launch()
+        _check(lib().dect_plan_tune(self.handle, cache.encode() if cache else None,
+                                    1 if force else 0, ctypes.byref(L), _stream()))
+        return {k: getattr(L, k) for k, _ in Launch._fields_}
+
+    def set_launch(self, bp_waves: int, proj_waves: int):
+        _check(lib().dect_plan_set_launch(self.handle, int(bp_waves), int(proj_waves)))
+
+    def launch(self) -> dict:
+        L = Launch()
+        _check(lib().dect_plan_get_launch(self.handle, ctypes.byref(L)))
+        return {"bp_waves": L.bp_waves, "proj_waves": L.proj_waves}
 
     def info(self) -> dict:
         I = PlanInfo()

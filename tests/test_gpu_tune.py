@@ -1,0 +1,134 @@
+"""Workgroup shapes of the ADMM kernels and their autotuner.
+
+Every shape computes the same sums (only the order in which a workgroup's
+partial sums are added differs), so every shape must match the FP64 oracle, and
+a batch must stay bitwise equal to single-slice runs of the same shapes.
+"""
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle as O
+from paper_1905_00934_amd import synth as S
+
+pytestmark = pytest.mark.gpu
+
+F64, F32 = torch.float64, torch.float32
+SYM_FAN = S.fan_geometry_fov(64, 120, 100, fov_cm=25.6, src_iso_cm=40.0, src_det_cm=70.0)
+RAGGED = S.geometry("fan", 37, 29, 0.4, 50, 71, 0.45, det_offset=0.3, src_iso_cm=30.0,
+                    src_det_cm=52.0, angle0=0.1)
+
+
+@pytest.fixture(scope="module")
+def dect():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1905_00934_amd import dect as D
+    D.lib()
+    return D
+
+
+def _problem(g, seed):
+    k = min(g["nx"], g["ny"]) * g["pixel_cm"] / 32.0
+    ph = S.tiny_phantom(seed)
+    ph = S.Phantom([S.Shape(sh.kind, k * sh.cx, k * sh.cy, k * sh.ax, k * sh.ay, sh.rot,
+                            sh.xc, sh.xp) for sh in ph.shapes])
+    return S.make_problem("p", g, ph, 1e5, seed, with_image=False)
+
+
+def _meas(pr, dtype):
+    mh, wh = O.ingest(pr.counts_high, pr.i0)
+    ml, wl = O.ingest(pr.counts_low, pr.i0)
+    return [torch.from_numpy(np.ascontiguousarray(m)).to("cuda", dtype) for m in (mh, ml, wh, wl)]
+
+
+@pytest.fixture(scope="module")
+def oracle_run():
+    out = {}
+    for name, g in (("sym", SYM_FAN), ("ragged", RAGGED)):
+        pr = _problem(g, 5)
+        orc = O.Oracle(pr.geom, pr.spec)
+        mh, wh = O.ingest(pr.counts_high, pr.i0)
+        ml, wl = O.ingest(pr.counts_low, pr.i0)
+        prm = O.Params(cg_iters=2, lm_iters=2)
+        st = orc.admm_init(mh, ml, wh, wl, prm)
+        st = orc.admm_iterate(st, mh, ml, wh, wl, prm, 6)
+        out[name] = (pr, st)
+    return out
+
+
+@pytest.mark.parametrize("name", ["sym", "ragged"])
+@pytest.mark.parametrize("bp,pj", [(2, 2), (4, 4), (8, 8), (2, 8), (8, 2)])
+def test_every_shape_matches_oracle_fp64(dect, oracle_run, name, bp, pj):
+    pr, ost = oracle_run[name]
+    plan = dect.Plan(pr.geom, pr.spec, F64)
+    plan.set_launch(bp, pj)
+    assert plan.launch() == {"bp_waves": bp, "proj_waves": pj}
+    meas = _meas(pr, F64)
+    params = dect.AdmmParams(cg_iters=2, lm_iters=2)
+    st = plan.new_state()
+    plan.admm_init(meas, st, params)
+    log = plan.admm_iterate(meas, st, params, 6, log=True)
+    x = st.x.cpu().numpy()
+    for b in range(2):
+        err = np.linalg.norm(x[..., b] - ost.x[b]) / np.linalg.norm(ost.x[b])
+        assert err <= 1e-8, err
+    assert [e["rho"] for e in log] == [tuple(e["rho"]) for e in ost.log]
+
+
+def test_batch_with_tuned_shapes_equals_alone(dect):
+    params = dect.AdmmParams()
+    a = dect.Plan(SYM_FAN, S.default_spectra(), F32)
+    b = dect.Plan(SYM_FAN, S.default_spectra(), F32)
+    a.set_launch(8, 2)
+    b.set_launch(2, 8)
+    slices = []
+    for plan, seed in ((a, 1), (b, 2), (a, 3)):
+        pr = _problem(SYM_FAN, seed)
+        meas = _meas(pr, F32)
+        s1, s2 = plan.new_state(), plan.new_state()
+        plan.admm_init(meas, s1, params)
+        plan.admm_init(meas, s2, params)
+        slices.append((plan, meas, s1, s2))
+    batch = dect.Batch([(p, m, s2) for p, m, _, s2 in slices], params, graph=True)
+    assert batch.groups == 2   # same geometry, different shapes: separate launches
+    batch.iterate(4)
+    for p, m, s1, _ in slices:
+        p.admm_iterate(m, s1, params, 4)
+    torch.cuda.synchronize()
+    for _, _, s1, s2 in slices:
+        assert torch.equal(s1.buf, s2.buf)
+    batch.close()
+
+
+def test_tune_times_caches_and_reuses(dect, tmp_path):
+    cache = str(tmp_path / "tune.txt")
+    p1 = dect.Plan(SYM_FAN, S.default_spectra(), F32)
+    t1 = p1.tune(cache)
+    assert t1["from_cache"] == 0
+    assert t1["bp_waves"] in (2, 4, 8) and t1["proj_waves"] in (2, 4, 8)
+    assert t1["bp_us"] > 0 and t1["proj_us"] > 0
+    assert p1.launch() == {"bp_waves": t1["bp_waves"], "proj_waves": t1["proj_waves"]}
+    assert os.path.exists(cache)
+    p2 = dect.Plan(SYM_FAN, S.default_spectra(), F32)
+    t2 = p2.tune(cache)
+    assert t2["from_cache"] == 1
+    assert (t2["bp_waves"], t2["proj_waves"]) == (t1["bp_waves"], t1["proj_waves"])
+    t3 = p2.tune(cache, force=True)
+    assert t3["from_cache"] == 0
+    # Another shape or precision has its own entry.
+    p3 = dect.Plan(SYM_FAN, S.default_spectra(), F64)
+    assert p3.tune(cache)["from_cache"] == 0
+    lines = [l for l in open(cache) if l.strip()]
+    assert len(lines) == 3
+
+
+def test_launch_shape_errors(dect):
+    p = dect.Plan(SYM_FAN, S.default_spectra(), F32)
+    for bad in ((3, 4), (4, 16), (0, 4)):
+        with pytest.raises(dect.DectError):
+            p.set_launch(*bad)
+    assert p.launch() == {"bp_waves": 4, "proj_waves": 4}
