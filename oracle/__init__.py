@@ -13,7 +13,9 @@ be read against the paper:
 * Eq. (9)    y = shrinkage(D x - u^y, lambda/rho)  (soft threshold)
 * Eq. (10)   z = max(0, x - u^z)
 * Eq. (11)   u <- u + [a; y; z] - [R; D; I] x
-* Eq. (12)   x = argmin ||[a; y; z] - [R; D; I] x + [u^a; u^y; u^z]||^2, by CG
+* Eq. (12)   x = argmin ||[a; y; z] - [R; D; I] x + [u^a; u^y; u^z]||^2, by CG, or by
+             CG preconditioned with a high-pass (ramp) filter applied by 2-D FFT
+             (Sec. 3.3: the system is shift-invariant once Sigma has moved to Eq. (13))
 * Eq. (13)   a = argmin per ray 1/2 ||f(a) - m||^2_Sigma + sum_b rho_b/2 (a_b - R x_b + u^a_b)^2,
              by Levenberg-Marquardt
 * Sec. 3.2   rho adapted from the primal and dual residuals (residual balancing)
@@ -21,7 +23,9 @@ be read against the paper:
 * Table 1    operator counts per iteration: R 2n, R^T 2(n+1), f 4m
 
 Readings where the paper is silent (each listed with its reason in the design
-notes): Sigma = diag(counts / I0); anisotropic TV with forward differences and a
+notes): the ramp preconditioner is max(|w|, 1/P) in cycles per pixel on a
+zero-padded grid of P = powers of two at least twice each image side (a pure
+ramp vanishes at w = 0); Sigma = diag(counts / I0); anisotropic TV with forward differences and a
 zero last difference; LM damping mu0 = 1e-3 reset every outer iteration, x10 / /10,
 Marquardt scaling; residual balancing with mu = 10 and tau = 2; initial state
 x = 0 and a from a rho = 0 decomposition started at the linearised solution.
@@ -97,6 +101,34 @@ def DT(y: np.ndarray) -> np.ndarray:
     return out
 
 
+def pad_shape(ny: int, nx: int) -> tuple:
+    """Padded FFT grid: the smallest powers of two at least twice each image side, so
+    that the filter acts as a linear (not circular) convolution over the image."""
+    def up(n):
+        p = 1
+        while p < 2 * n:
+            p *= 2
+        return p
+    return up(ny), up(nx)
+
+
+def ramp_filter(py: int, px: int) -> np.ndarray:
+    """Floored ramp max(|w|, 1/max(py, px)) on the py x px DFT grid, |w| in cycles per
+    pixel (the ramp filter as the CG preconditioner, Sec. 3.3)."""
+    fy = np.fft.fftfreq(py)[:, None]
+    fx = np.fft.fftfreq(px)[None, :]
+    return np.maximum(np.sqrt(fy * fy + fx * fx), 1.0 / max(py, px))
+
+
+def precondition(img: np.ndarray, filt: np.ndarray) -> np.ndarray:
+    """M r: zero-pad the image to the filter's grid, multiply its 2-D DFT by the
+    filter, transform back and keep the image's own pixels."""
+    ny, nx = img.shape
+    pad = np.zeros(filt.shape)
+    pad[:ny, :nx] = img
+    return np.real(np.fft.ifft2(np.fft.fft2(pad) * filt))[:ny, :nx]
+
+
 def shrink(v: np.ndarray, t: float) -> np.ndarray:
     """Soft threshold: the minimiser of t|y| + 1/2 (y - v)^2 (Eq. (9))."""
     return np.sign(v) * np.maximum(np.abs(v) - t, 0.0)
@@ -128,6 +160,7 @@ class Params:
     bal_mu: float = 10.0
     bal_tau: float = 2.0
     lm_mu0: float = 1e-3
+    precond: str | None = None       # None (CG) or "ramp" (PCG)
 
 
 @dataclass
@@ -265,12 +298,15 @@ class Oracle:
                      y=z2(2, ny, nx), uy=z2(2, ny, nx), z=z2(ny, nx), uz=z2(ny, nx),
                      rho=np.array(params.rho0, dtype=np.float64))
 
-    def cg(self, x, Rx, rhs_sino, rhs_img, n):
+    def cg(self, x, Rx, rhs_sino, rhs_img, n, filt=None):
         """n CG iterations on (R^T R + D^T D + I) x = R^T rhs_sino + rhs_img (Eq. (12)),
-        warm-started at x with R x = Rx known; returns (x, Rx) with Rx kept equal to R x."""
+        warm-started at x with R x = Rx known; returns (x, Rx) with Rx kept equal to R x.
+        With a filter, preconditioned CG with M = precondition(., filt)."""
+        M = (lambda v: v) if filt is None else (lambda v: precondition(v, filt))
         r = self.backproject(rhs_sino - Rx) + rhs_img - DT(D(x)) - x
-        p = r.copy()
-        gamma = float(np.dot(r.ravel(), r.ravel()))
+        zv = M(r)
+        p = zv.copy()
+        gamma = float(np.dot(r.ravel(), zv.ravel()))
         for _ in range(n):
             if gamma == 0.0:
                 break
@@ -280,14 +316,20 @@ class Oracle:
             x = x + alpha * p
             Rx = Rx + alpha * Rp
             r = r - alpha * q
-            gamma_new = float(np.dot(r.ravel(), r.ravel()))
-            p = r + (gamma_new / gamma) * p
+            zv = M(r)
+            gamma_new = float(np.dot(r.ravel(), zv.ravel()))
+            p = zv + (gamma_new / gamma) * p
             gamma = gamma_new
         return x, Rx
 
     def admm_iterate(self, st: State, mh, ml, wh, wl, params: Params, n_iters: int = 1) -> State:
         """n_iters ADMM iterations: x (Eq. 12), a (Eq. 13), y and z (Eq. 9-10), u (Eq. 11), rho."""
         st = st.copy()
+        filt = None
+        if params.precond == "ramp":
+            filt = ramp_filter(*pad_shape(*self.img_shape))
+        elif params.precond is not None:
+            raise ValueError(f"unknown preconditioner {params.precond!r}")
         for _ in range(n_iters):
             rho = st.rho.copy()
             a_prev, y_prev, z_prev = st.a.copy(), st.y.copy(), st.z.copy()
@@ -295,7 +337,7 @@ class Oracle:
             for b in range(2):
                 st.x[b], st.Rx[b] = self.cg(
                     st.x[b], st.Rx[b], st.a[b] + st.ua[b],
-                    DT(st.y[b] + st.uy[b]) + st.z[b] + st.uz[b], params.cg_iters)
+                    DT(st.y[b] + st.uy[b]) + st.z[b] + st.uz[b], params.cg_iters, filt)
             # a-update: per-ray decomposition (Eq. (13)) with v = R x - u^a.
             v = st.Rx - st.ua
             ac, ap, _ = self.udm(mh, ml, wh, wl, v[0], v[1], rho[0], rho[1], params.lm_iters,
