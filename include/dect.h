@@ -148,7 +148,20 @@ typedef struct {
     double lm_mu0;             /* LM initial damping (1e-3) */
     const double* rho_schedule;/* host, 2*rho_schedule_len doubles, for DECT_RHO_SCHEDULE */
     int rho_schedule_len;
+    int precond;               /* dect_precond: CG (0) or CG preconditioned by the ramp filter */
 } dect_params;
+
+/* Preconditioner of the x-update (Sec. 3.3: the system of Eq. (12) is shift-invariant,
+ * so CG is preconditioned by a high-pass filter applied by FFT).  RAMP: the image is
+ * zero-padded to px x py (the powers of two at least twice each side), its 2-D DFT
+ * multiplied by max(|w|, 1/max(px, py)) with |w| in cycles per pixel, transformed
+ * back and cropped.  Available when both padded sides are at most 2048. */
+typedef enum { DECT_PRECOND_NONE = 0, DECT_PRECOND_RAMP = 1 } dect_precond;
+
+/* The preconditioner applied to a two-channel image: out = M img, both device
+ * [ny][nx][2].  DECT_E_SHAPE if the plan has none.  async.  Uses plan-owned scratch,
+ * so calls with one plan must not run concurrently on different streams. */
+dect_status dect_precondition(const dect_plan* plan, const void* img, void* out, void* stream);
 
 /* Per-iteration record, filled when the caller passes a log buffer. */
 typedef struct {

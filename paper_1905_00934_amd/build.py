@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "libdect.so")
 SOURCES = ["plan.cpp", "profile.cpp", "tomo.hip", "udm.hip", "admm.hip", "batch.cpp",
-           "server.cpp", "tune.cpp"]
+           "server.cpp", "tune.cpp", "fft.hip"]
 HEADERS = ["common.h", "kernels.h", "profile.h", "runner.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -44,7 +44,7 @@ def build(verbose: bool = False, defines=(), lib_path: str = LIB) -> str:
     """
     out_dir = os.path.dirname(lib_path)
     os.makedirs(out_dir, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(9, len(SOURCES))) as ex:
         objs = list(ex.map(lambda src: _compile(src, out_dir, defines), SOURCES))
     tmp = lib_path + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]

@@ -82,7 +82,7 @@ __global__ __launch_bounds__(256) void k_rx_step(const VecArgs<T>* __restrict__ 
     reinterpret_cast<V2*>(A.Rx)[i] = a;
 }
 
-// p = r + beta p.
+// p = z + beta p (z = r for plain CG, M r for PCG).
 template <typename T, bool BATCH>
 __global__ __launch_bounds__(256) void k_p_step(const VecArgs<T>* __restrict__ dev, VecArgs<T> one) {
     using V2 = vec<T, 2>;
@@ -90,7 +90,7 @@ __global__ __launch_bounds__(256) void k_p_step(const VecArgs<T>* __restrict__ d
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= A.N) return;
     V2 a = reinterpret_cast<V2*>(A.p)[i];
-    const V2 b = reinterpret_cast<const V2*>(A.r)[i];
+    const V2 b = reinterpret_cast<const V2*>(A.zp)[i];
     a.v[0] = b.v[0] + (T)A.scal[S_BETA] * a.v[0];
     a.v[1] = b.v[1] + (T)A.scal[S_BETA + 1] * a.v[1];
     reinterpret_cast<V2*>(A.p)[i] = a;
@@ -247,7 +247,10 @@ __global__ __launch_bounds__(256) void k_reduce(const RedArgs* __restrict__ dev,
     if (!s) return;  // empty slot
     if (mode == RED_GAMMA) {
         double g[2];
-        section_sum<2>(A.tiles, A.nb_tiles, g);
+        if (A.precond)
+            section_sum<2>(A.pre, A.nb_pre, g);
+        else
+            section_sum<2>(A.tiles, A.nb_tiles, g);
         if (threadIdx.x == 0) {
             s[S_GAMMA] = g[0];
             s[S_GAMMA + 1] = g[1];
@@ -262,7 +265,10 @@ __global__ __launch_bounds__(256) void k_reduce(const RedArgs* __restrict__ dev,
             }
     } else if (mode == RED_BETA) {
         double g[2];
-        section_sum<2>(A.img, A.nb_img, g);
+        if (A.precond)
+            section_sum<2>(A.pre, A.nb_pre, g);
+        else
+            section_sum<2>(A.img, A.nb_img, g);
         if (threadIdx.x == 0)
             for (int c = 0; c < 2; ++c) {
                 s[S_BETA + c] = s[S_GAMMA + c] > 0.0 ? g[c] / s[S_GAMMA + c] : 0.0;
@@ -348,14 +354,18 @@ SliceJob<T> make_job(const dect_plan* p, const void* mh, const void* ml, const v
     T* Rp = at<T>(st, p->off_Rp);
     T* t = at<T>(st, p->off_t);
     T* da = at<T>(st, p->off_da);
+    T* zb = at<T>(st, p->off_z);
     double* part = at<double>(st, p->off_partials);
     const Partials P{part, part + (size_t)p->nb_sino * kPartialSlots,
-                     part + (size_t)(p->nb_sino + p->nb_img) * kPartialSlots};
+                     part + (size_t)(p->nb_sino + p->nb_img) * kPartialSlots,
+                     part + (size_t)(p->nb_sino + p->nb_img + p->nb_tiles) * kPartialSlots};
     const int n = prm->cg_iters;
+    const bool pre = prm->precond == DECT_PRECOND_RAMP;
 
     SliceJob<T> J{};
     J.cg_iters = prm->cg_iters;
     J.rho_mode = prm->rho_mode;
+    J.precond = pre ? 1 : 0;
     J.N = p->N;
     J.M = p->M;
     J.sym = p->sym;
@@ -374,8 +384,9 @@ SliceJob<T> make_job(const dect_plan* p, const void* mh, const void* ml, const v
     b.partials = P.tiles;
     J.rhs = b;
     J.rhs.sino = t;
-    J.rhs.out = pp;
-    J.rhs.out2 = n > 1 ? r : nullptr;
+    // CG: p0 = r0 (and r = r0 when more steps follow); PCG: r = r0, p0 = M r0 next.
+    J.rhs.out = pre ? r : pp;
+    J.rhs.out2 = (!pre && n > 1) ? r : nullptr;
     J.rhs.x = x;
     J.rhs.y = y;
     J.rhs.uy = uy;
@@ -413,10 +424,21 @@ SliceJob<T> make_job(const dect_plan* p, const void* mh, const void* ml, const v
     u.partials = P.sino;
     u.iters = prm->lm_iters;
     u.mu0 = prm->lm_mu0;
-    J.vec = VecArgs<T>{p->N, p->M, p->sym, p->Vb, p->D, x, pp, r, q, Rx, Rp, scal, P.img};
+    J.vec = VecArgs<T>{p->N, p->M, p->sym, p->Vb, p->D, x, pp, r, pre ? zb : r, q, Rx, Rp, scal,
+                       P.img};
+    if (pre) {
+        fill_precond_plan<T>(p, J.pre0);
+        J.pre0.W = at<T>(st, p->off_fftw);
+        J.pre0.r = r;
+        J.pre0.partials = P.pre;
+        J.pre1 = J.pre0;
+        J.pre0.z = pp;
+        J.pre1.z = zb;
+    }
     J.tv = TvArgs<T>{p->nx, p->ny, x, y, uy, dy, z, uz, dz, scal, P.img};
     J.resc = RescaleArgs<T>{p->M, p->N, p->sym, p->Vb, p->D, ua, t, a, Rx, uy, uz, scal};
-    J.red = RedArgs{P.tiles, p->nb_tiles, P.img, p->nb_img, P.sino, p->nb_sino, scal,
+    J.red = RedArgs{P.tiles, p->nb_tiles, P.img, p->nb_img, P.sino, p->nb_sino, P.pre, p->nb_pre,
+                    pre ? 1 : 0, scal,
                     at<double>(st, p->off_log), prm->rho_mode,
                     prm->rho_mode == DECT_RHO_ADAPTIVE ? 1 : 0, prm->bal_mu, prm->bal_tau,
                     0.0, 0.0};
@@ -451,6 +473,7 @@ hipError_t iteration_t(const SliceJob<T>& J, const JobArrays<T>* dev, int nsl,
     const VecArgs<T>* dvec = dev ? dev->vec : nullptr;
     DECT_TRY(launch_backproject_admm<T>(J.sym, J.bp_waves, EPI_RHS, dev ? dev->rhs : nullptr,
                                         J.rhs, nsl, J.bp_gx, J.bp_gy, s));
+    if (J.precond) DECT_TRY(launch_precond<T>(dev ? dev->pre0 : nullptr, J.pre0, nsl, s));
     DECT_TRY(reduce(RED_GAMMA));
     for (int c = 0; c < n; ++c) {
         DECT_TRY(launch_project_pair<T>(J.sym, J.pj_waves, dev ? dev->orb : nullptr, J.orb,
@@ -463,6 +486,7 @@ hipError_t iteration_t(const SliceJob<T>& J, const JobArrays<T>* dev, int nsl,
             ProfScope ps("cg_vector", s);
             hipLaunchKernelGGL((k_rx_step<T, BATCH>), gM, dim3(256), 0, s, dvec, J.vec);
             hipLaunchKernelGGL((k_cg_step<T, true, BATCH>), gN, dim3(256), 0, s, dvec, J.vec);
+            if (J.precond) DECT_TRY(launch_precond<T>(dev ? dev->pre1 : nullptr, J.pre1, nsl, s));
             DECT_TRY(reduce(RED_BETA));
             hipLaunchKernelGGL((k_p_step<T, BATCH>), gN, dim3(256), 0, s, dvec, J.vec);
         } else {
@@ -610,6 +634,8 @@ dect_status check_params(const dect_params* prm) {
     if (prm->rho_mode == DECT_RHO_ADAPTIVE && (!(prm->bal_mu > 1) || !(prm->bal_tau > 1)))
         return fail(DECT_E_ARG, "residual balancing needs mu > 1 and tau > 1");
     if (!(prm->lm_mu0 > 0)) return fail(DECT_E_ARG, "lm_mu0 must be > 0");
+    if (prm->precond != DECT_PRECOND_NONE && prm->precond != DECT_PRECOND_RAMP)
+        return fail(DECT_E_ARG, "bad precond %d", prm->precond);
     return DECT_OK;
 }
 
@@ -738,6 +764,8 @@ dect_status dect_admm_iterate(const dect_plan* p, const void* m_h, const void* m
         return fail(DECT_E_ARG, "state buffer must be 256-byte aligned");
     dect_status st = check_params(prm);
     if (st) return st;
+    if (prm->precond && !p->has_precond)
+        return fail(DECT_E_SHAPE, "no preconditioner for a %dx%d image", p->nx, p->ny);
     if (n_iters < 0) return fail(DECT_E_ARG, "n_iters must be >= 0");
     if (log && n_iters > kLogCap)
         return fail(DECT_E_ARG, "a log holds at most %d iterations per call", kLogCap);

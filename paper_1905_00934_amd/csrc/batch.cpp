@@ -22,13 +22,14 @@ bool same_shape(const SliceJob<T>& a, const SliceJob<T>& b) {
     return a.N == b.N && a.M == b.M && a.sym == b.sym && a.bp_gx == b.bp_gx &&
            a.bp_gy == b.bp_gy && a.pj_gx == b.pj_gx && a.pj_gy == b.pj_gy &&
            a.prj.nx == b.prj.nx && a.prj.ny == b.prj.ny && a.cg_iters == b.cg_iters &&
-           a.rho_mode == b.rho_mode && a.bp_waves == b.bp_waves && a.pj_waves == b.pj_waves;
+           a.rho_mode == b.rho_mode && a.bp_waves == b.bp_waves && a.pj_waves == b.pj_waves &&
+           a.precond == b.precond;
 }
 
 // Byte offsets of the ten argument arrays of a group of n slices.
 template <typename T>
 struct ArrayOffsets {
-    size_t orb, prj, rhs, q, dual, udm, vec, tv, resc, red, end;
+    size_t orb, prj, rhs, q, dual, udm, vec, tv, resc, red, pre0, pre1, end;
     ArrayOffsets(size_t base, size_t n) {
         size_t off = base;
         auto take = [&](size_t bytes) {
@@ -46,6 +47,8 @@ struct ArrayOffsets {
         tv = take(n * sizeof(TvArgs<T>));
         resc = take(n * sizeof(RescaleArgs<T>));
         red = take(n * sizeof(RedArgs));
+        pre0 = take(n * sizeof(PrecArgs<T>));
+        pre1 = take(n * sizeof(PrecArgs<T>));
         end = off;
     }
 };
@@ -111,6 +114,8 @@ hipError_t Runner<T>::set(const std::vector<SliceJob<T>>& jobs) {
             put(h, o.tv, k, J.tv);
             put(h, o.resc, k, J.resc);
             put(h, o.red, k, J.red);
+            put(h, o.pre0, k, J.pre0);
+            put(h, o.pre1, k, J.pre1);
         }
         g.dev.orb = reinterpret_cast<OrbitArgs<T>*>(b + o.orb);
         g.dev.prj = reinterpret_cast<ProjArgs<T>*>(b + o.prj);
@@ -122,6 +127,8 @@ hipError_t Runner<T>::set(const std::vector<SliceJob<T>>& jobs) {
         g.dev.tv = reinterpret_cast<TvArgs<T>*>(b + o.tv);
         g.dev.resc = reinterpret_cast<RescaleArgs<T>*>(b + o.resc);
         g.dev.red = reinterpret_cast<RedArgs*>(b + o.red);
+        g.dev.pre0 = reinterpret_cast<PrecArgs<T>*>(b + o.pre0);
+        g.dev.pre1 = reinterpret_cast<PrecArgs<T>*>(b + o.pre1);
     }
     return hipMemcpy(mem_, h.data(), total, hipMemcpyHostToDevice);
 }
@@ -134,6 +141,7 @@ hipError_t Runner<T>::enqueue(hipStream_t s) const {
         dect_params prm{};
         prm.cg_iters = g.jobs[0].cg_iters;
         prm.rho_mode = g.jobs[0].rho_mode;
+        prm.precond = g.jobs[0].precond;
         hipError_t e = launch_iteration<T>(g.jobs[0], &g.dev, (int)g.jobs.size(), &prm, 0, s);
         if (e != hipSuccess) return e;
     }
@@ -199,6 +207,8 @@ dect_status check_batch_params(const dect_params* prm) {
     if (!(prm->lm_mu0 > 0)) return fail(DECT_E_ARG, "lm_mu0 must be > 0");
     if (!(prm->rho_c > 0) || !(prm->rho_p > 0) || !(prm->lambda_c >= 0) || !(prm->lambda_p >= 0))
         return fail(DECT_E_ARG, "rho must be > 0 and lambda >= 0");
+    if (prm->precond != DECT_PRECOND_NONE && prm->precond != DECT_PRECOND_RAMP)
+        return fail(DECT_E_ARG, "bad precond %d", prm->precond);
     return DECT_OK;
 }
 
@@ -221,6 +231,8 @@ dect_status dect_batch_create(int n, const dect_plan* const* plans, const void* 
             return fail(DECT_E_ARG, "null entry for slice %d", k);
         if (plans[k]->dtype != plans[0]->dtype)
             return fail(DECT_E_ARG, "slice %d has another precision than slice 0", k);
+        if (params->precond && !plans[k]->has_precond)
+            return fail(DECT_E_SHAPE, "slice %d: no preconditioner for its image size", k);
         if (reinterpret_cast<uintptr_t>(states[k]) % 256)
             return fail(DECT_E_ARG, "state of slice %d is not 256-byte aligned", k);
         for (int j = 0; j < k; ++j)

@@ -99,11 +99,20 @@ struct dect_plan {
     // plan-owned scratch: orbit images of the image being projected (up to 4 channels)
     void* scratch_O = nullptr;   // T[N * 4 * sym]
     void* scratch_OT = nullptr;  // T[N * 4 * sym]
+    // preconditioner of the x-update (ramp filter on a zero-padded FFT grid of
+    // px x py = 2^lpx x 2^lpy; absent when a padded side exceeds kMaxFft)
+    bool has_precond = false;
+    int px = 0, py = 0, lpx = 0, lpy = 0;
+    void* pre_filter = nullptr;  // T[py][px]
+    void* pre_twx = nullptr;     // T[px/2][2] twiddles exp(-2 pi i k / px)
+    void* pre_twy = nullptr;     // T[py/2][2]
+    void* scratch_W = nullptr;   // T[ny][px][2] work grid of dect_precondition
+    double* scratch_part = nullptr;
     // state layout (bytes)
     dect_layout layout;
     size_t off_p, off_pO, off_pOT, off_r, off_q, off_dy, off_dz, off_Rp, off_t, off_da, off_fg,
-        off_partials, off_log;
-    int nb_sino, nb_img, nb_tiles;  // block counts of the reducing kernels
+        off_z, off_fftw, off_partials, off_log;
+    int nb_sino, nb_img, nb_tiles, nb_pre;  // block counts of the reducing kernels
 };
 
 namespace dect {
@@ -120,6 +129,7 @@ __host__ __device__ inline long std_ray(long l, int sym, int Vb, int D) {
     return ((base / D) + (long)k * Vb) * D + base % D;
 }
 
+constexpr int kMaxFft = 2048;     // longest padded side of the preconditioner's FFT
 constexpr int kLogCap = 256;      // iterations kept in the device log ring
 constexpr int kLogStride = 12;    // doubles per log entry
 constexpr int kPartialSlots = 4;  // doubles per block partial
@@ -144,6 +154,7 @@ struct Partials {
     double* sino;   // UDM: |a-Rx|^2 c, p; data cost; non-finite count
     double* img;    // TV: |y-Dx|^2+|z-x|^2 c, p; |y_c|_1, |y_p|_1
     double* tiles;  // backprojection epilogues: two sums per tile
+    double* pre;    // preconditioner: r . z per image row
 };
 
 }  // namespace dect

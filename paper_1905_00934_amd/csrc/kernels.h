@@ -149,7 +149,27 @@ hipError_t launch_udm(const dect_plan* p, int mode, const UdmArgs<T>& a, hipStre
 // Batched a-step over n slices (args: device array), grid of `blocks` x n.
 template <typename T>
 hipError_t launch_udm_batch(const UdmArgs<T>* args, int n, int blocks, hipStream_t s);
-// Image-vector CG steps: x += alpha p, r -= alpha q, p = r + beta p, R x += alpha R p.
+// Preconditioner z = M r of the x-update (ramp filter by 2-D FFT, both bases as one
+// complex image); partials: r . z per basis, one block per image row.
+template <typename T>
+struct PrecArgs {
+    int nx, ny, px, py, lpx, lpy;  // image and padded grid (px = 2^lpx, py = 2^lpy)
+    const T* filter;               // [py][px]
+    const T* twx;                  // [px/2][2]
+    const T* twy;                  // [py/2][2]
+    T* W;                          // [ny][px][2] work grid
+    const T* r;                    // [ny][nx][2]
+    T* z;                          // [ny][nx][2]
+    double* partials;
+};
+
+template <typename T>
+void fill_precond_plan(const dect_plan* p, PrecArgs<T>& a);
+template <typename T>
+hipError_t launch_precond(const PrecArgs<T>* dev, const PrecArgs<T>& one, int n, hipStream_t s);
+
+// Image-vector CG steps: x += alpha p, r -= alpha q, p = zp + beta p, R x += alpha R p
+// (zp = r for CG, the preconditioned residual for PCG).
 template <typename T>
 struct VecArgs {
     long N, M;
@@ -157,6 +177,7 @@ struct VecArgs {
     T* x;
     T* p;
     T* r;
+    const T* zp;
     const T* q;
     T* Rx;
     const T* Rp;
@@ -202,6 +223,9 @@ struct RedArgs {
     int nb_img;
     const double* sino;
     int nb_sino;
+    const double* pre;   // preconditioner partials (r . z), used for gamma with PCG
+    int nb_pre;
+    int precond;
     double* scal;
     double* log;
     int rho_mode;
@@ -220,6 +244,8 @@ struct SliceJob {
     TvArgs<T> tv;
     RescaleArgs<T> resc;
     RedArgs red;
+    PrecArgs<T> pre0, pre1;  // PCG: z0 = M r0 into p; z = M r into the z buffer
+    int precond;
     long N, M;
     int sym, bp_gx, bp_gy, pj_gx, pj_gy;
     int bp_waves, pj_waves;  // workgroup shapes of the plan
@@ -239,6 +265,8 @@ struct JobArrays {
     TvArgs<T>* tv;
     RescaleArgs<T>* resc;
     RedArgs* red;
+    PrecArgs<T>* pre0;
+    PrecArgs<T>* pre1;
 };
 
 // The argument blocks of one slice for its plan, measurements and state.

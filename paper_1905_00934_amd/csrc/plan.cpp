@@ -179,6 +179,54 @@ dect_status build_tables(dect_plan* p, const dect_spectra* spec) {
     return DECT_OK;
 }
 
+// Smallest power of two at least twice n (linear convolution over the image).
+int pad_pow2(int n, int& lg) {
+    int P = 1;
+    lg = 0;
+    while (P < 2 * n) {
+        P *= 2;
+        ++lg;
+    }
+    return P;
+}
+
+// Preconditioner of the x-update: the floored ramp max(|w|, 1/max(Py, Px)) on the
+// zero-padded DFT grid (|w| in cycles per pixel) and the DFT twiddle factors
+// exp(-2 pi i k / P), k < P / 2, of both padded sides.
+template <typename T>
+dect_status build_precond(dect_plan* p) {
+    p->px = pad_pow2(p->nx, p->lpx);
+    p->py = pad_pow2(p->ny, p->lpy);
+    if (p->px > kMaxFft || p->py > kMaxFft) return DECT_OK;  // no preconditioner for this size
+    const int px = p->px, py = p->py;
+    const double floor_w = 1.0 / (double)(px > py ? px : py);
+    std::vector<T> filt((size_t)px * py);
+    for (int ky = 0; ky < py; ++ky) {
+        const double fy = (ky < py / 2 ? ky : ky - py) / (double)py;
+        for (int kx = 0; kx < px; ++kx) {
+            const double fx = (kx < px / 2 ? kx : kx - px) / (double)px;
+            filt[(size_t)ky * px + kx] = (T)std::fmax(std::sqrt(fx * fx + fy * fy), floor_w);
+        }
+    }
+    dect_status st = upload<T>(filt.data(), filt.size() * sizeof(T), &p->pre_filter);
+    if (st) return st;
+    for (int axis = 0; axis < 2; ++axis) {
+        const int P = axis ? py : px;
+        std::vector<T> tw((size_t)P);  // (cos, -sin) pairs
+        for (int k = 0; k < P / 2; ++k) {
+            const double a = 6.283185307179586 * k / P;
+            tw[2 * k] = (T)std::cos(a);
+            tw[2 * k + 1] = (T)(-std::sin(a));
+        }
+        st = upload<T>(tw.data(), tw.size() * sizeof(T), axis ? &p->pre_twy : &p->pre_twx);
+        if (st) return st;
+    }
+    DECT_HIP(hipMalloc(&p->scratch_W, (size_t)p->ny * px * 2 * sizeof(T)));
+    DECT_HIP(hipMalloc(&p->scratch_part, (size_t)p->ny * kPartialSlots * sizeof(double)));
+    p->has_precond = true;
+    return DECT_OK;
+}
+
 void make_layout(dect_plan* p) {
     const size_t e = p->elem;
     const size_t N = (size_t)p->N, M = (size_t)p->M;
@@ -209,11 +257,14 @@ void make_layout(dect_plan* p) {
     p->off_t = take(M * 2 * e);
     p->off_da = take(M * 2 * e);
     p->off_fg = take(M * 8 * e);
+    p->off_z = take(N * 2 * e);
+    p->off_fftw = p->has_precond ? take((size_t)p->ny * p->px * 2 * e) : 0;
     p->nb_sino = (int)((M + 255) / 256);
     p->nb_img = (int)((N + 255) / 256);
     p->nb_tiles = bp_blocks(p);
-    p->off_partials =
-        take((size_t)(p->nb_sino + p->nb_img + p->nb_tiles) * kPartialSlots * sizeof(double));
+    p->nb_pre = p->ny;
+    p->off_partials = take((size_t)(p->nb_sino + p->nb_img + p->nb_tiles + p->nb_pre) *
+                           kPartialSlots * sizeof(double));
     p->off_log = take((size_t)kLogCap * kLogStride * sizeof(double));
     L.bytes = off;
 }
@@ -307,6 +358,7 @@ dect_status dect_plan_create(const dect_geometry* geom, const dect_spectra* spec
         return fail(DECT_E_DEVICE, "no HIP device");
     }
     dect_status st = dtype == DECT_F32 ? build_tables<float>(p, spec) : build_tables<double>(p, spec);
+    if (st == DECT_OK) st = dtype == DECT_F32 ? build_precond<float>(p) : build_precond<double>(p);
     if (st != DECT_OK) {
         dect_plan_destroy(p);
         return st;
@@ -323,6 +375,11 @@ void dect_plan_destroy(dect_plan* p) {
     (void)hipFree(p->spec);
     (void)hipFree(p->scratch_O);
     (void)hipFree(p->scratch_OT);
+    (void)hipFree(p->pre_filter);
+    (void)hipFree(p->pre_twx);
+    (void)hipFree(p->pre_twy);
+    (void)hipFree(p->scratch_W);
+    (void)hipFree(p->scratch_part);
     delete p;
 }
 

@@ -373,6 +373,8 @@ dect_status dect_serve_submit(dect_server* S, const dect_request* req, uint64_t*
         return fail(DECT_E_ARG, "tol must be >= 0 and max_iters >= 1");
     dect_status st = check_batch_params(&req->params);
     if (st) return st;
+    if (req->params.precond && !req->plan->has_precond)
+        return fail(DECT_E_SHAPE, "no preconditioner for this request's image size");
     const size_t need = footprint(req->plan).total;
     if (need > S->cfg.hbm_budget_bytes)
         return fail(DECT_E_CAPACITY, "request needs %zu device bytes; the budget is %zu", need,

@@ -19,6 +19,7 @@ STATUS = {-1: "DECT_E_ARG", -2: "DECT_E_SHAPE", -3: "DECT_E_NOMEM", -4: "DECT_E_
           -5: "DECT_E_NONFINITE", -6: "DECT_E_CAPACITY"}
 F32, F64 = 0, 1
 RHO_FIXED, RHO_ADAPTIVE, RHO_SCHEDULE = 0, 1, 2
+PRECOND_NONE, PRECOND_RAMP = 0, 1
 
 
 class DectError(RuntimeError):
@@ -49,7 +50,7 @@ class Params(ctypes.Structure):
                 ("rho_mode", ctypes.c_int), ("bal_mu", ctypes.c_double),
                 ("bal_tau", ctypes.c_double), ("lm_mu0", ctypes.c_double),
                 ("rho_schedule", ctypes.POINTER(ctypes.c_double)),
-                ("rho_schedule_len", ctypes.c_int)]
+                ("rho_schedule_len", ctypes.c_int), ("precond", ctypes.c_int)]
 
 
 class IterLog(ctypes.Structure):
@@ -138,6 +139,7 @@ def lib():
             "dect_batch_iterate": [vp, i, vp],
             "dect_batch_groups": [vp],
             "dect_batch_destroy": [vp],
+            "dect_precondition": [vp, vp, vp, vp],
             "dect_plan_tune": [vp, ctypes.c_char_p, i, ctypes.POINTER(Launch), vp],
             "dect_plan_set_launch": [vp, i, i],
             "dect_plan_get_launch": [vp, ctypes.POINTER(Launch)],
@@ -226,6 +228,7 @@ class AdmmParams:
     bal_tau: float = 2.0
     lm_mu0: float = 1e-3
     rho_schedule: object = None   # sequence of (rho_c, rho_p) per iteration
+    precond: int = PRECOND_NONE    # PRECOND_RAMP: CG preconditioned by the ramp filter
 
     def c_struct(self):
         P = Params()
@@ -233,6 +236,7 @@ class AdmmParams:
         P.rho_c, P.rho_p = self.rho0
         P.lm_iters, P.cg_iters, P.rho_mode = self.lm_iters, self.cg_iters, self.rho_mode
         P.bal_mu, P.bal_tau, P.lm_mu0 = self.bal_mu, self.bal_tau, self.lm_mu0
+        P.precond = int(self.precond)
         keep = None
         if self.rho_schedule is not None:
             flat = [float(v) for pair in self.rho_schedule for v in pair]
@@ -348,6 +352,13 @@ class Plan:
                                         float(i0_h), float(i0_l), *(_ptr(o) for o in outs),
                                         _stream()))
         return tuple(outs)
+
+    def precondition(self, img: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """M img for a two-channel image [ny, nx, 2] (the ramp preconditioner)."""
+        self._chk(img, (self.ny, self.nx, 2), "img")
+        out = self._t((self.ny, self.nx, 2)) if out is None else out
+        _check(lib().dect_precondition(self.handle, _ptr(img), _ptr(out), _stream()))
+        return out
 
     def tune(self, cache: str | None = None, force: bool = False) -> dict:
         """Choose the ADMM kernels' workgroup shapes by timing (or from the cache)."""
