@@ -71,7 +71,7 @@ __global__ __launch_bounds__(256) void k_pre_rows_fwd(const PrecArgs<T>* __restr
     for (int i = threadIdx.x; i < A.px; i += blockDim.x) w[i] = buf[i];
 }
 
-// C adjacent columns per block, so that every row segment read is C entries long.
+// C columns per block (C consecutive columns of the work grid).
 template <typename T, bool BATCH, int C>
 __global__ __launch_bounds__(256) void k_pre_cols(const PrecArgs<T>* __restrict__ dev,
                                                   PrecArgs<T> one) {
@@ -138,7 +138,9 @@ __global__ __launch_bounds__(256) void k_pre_rows_inv(const PrecArgs<T>* __restr
 
 template <typename T, bool BATCH>
 void precond_launch(const PrecArgs<T>* dev, const PrecArgs<T>& one, int n, hipStream_t s) {
-    constexpr int C = sizeof(T) == 4 ? 4 : 2;
+    // One column per block: more blocks and smaller LDS measured faster than
+    // batching adjacent columns for longer row segments (C = 2, 4, 8).
+    constexpr int C = 1;
     const size_t row_lds = (size_t)one.px * sizeof(cx<T>);
     const size_t col_lds = (size_t)C * one.py * sizeof(cx<T>);
     const dim3 rows((unsigned)one.ny, 1, n), cols((unsigned)((one.px + C - 1) / C), 1, n);
