@@ -59,6 +59,8 @@ def _lib():
         _LIB.orc_udm.argtypes = [i, pd, pd, pd, i, pd, pd, pd, l, pd, pd, pd, pd, pd, pd, d, d, i,
                                  d, pd, pd, pd]
         _LIB.orc_udm.restype = i
+        _LIB.orc_cdm.argtypes = [i, pd, pd, pd, i, pd, pd, pd, l, pd, pd, pd, pd, i, d, pd, pd, pd]
+        _LIB.orc_cdm.restype = i
     return _LIB
 
 
@@ -127,6 +129,19 @@ def precondition(img: np.ndarray, filt: np.ndarray) -> np.ndarray:
     pad = np.zeros(filt.shape)
     pad[:ny, :nx] = img
     return np.real(np.fft.ifft2(np.fft.fft2(pad) * filt))[:ny, :nx]
+
+
+def ramlak_kernel(P: int, delta: float) -> np.ndarray:
+    """Discrete ramp (Ram-Lak) kernel of sample spacing delta, circularly indexed over
+    P samples: h[0] = 1/(4 delta^2), h[n] = -1/(pi^2 n^2 delta^2) for odd n, 0 for
+    even n != 0 (the band-limited ramp sampled at n delta)."""
+    h = np.zeros(P)
+    n = np.arange(P)
+    n = np.where(n < P // 2, n, n - P)
+    odd = (n % 2) != 0
+    h[odd] = -1.0 / (np.pi ** 2 * n[odd].astype(float) ** 2 * delta ** 2)
+    h[0] = 1.0 / (4.0 * delta ** 2)
+    return h
 
 
 def shrink(v: np.ndarray, t: float) -> np.ndarray:
@@ -263,6 +278,72 @@ class Oracle:
         self.counts["f"] += nf
         return ac.reshape(sh), ap.reshape(sh), phi.reshape(sh)
 
+    def cdm(self, mh, ml, wh, wl, iters=20, mu0=1e-3):
+        """Constrained decomposition (CDM): per ray, 1/2 ||f(a) - m||^2_Sigma over a >= 0 by
+        projected LM from the linearised solution (projected); returns (a_c, a_p)."""
+        c0, p0 = self.linearised(mh, ml)
+        sh = np.shape(mh)
+        ac, ap = _f64(c0).ravel().copy(), _f64(p0).ravel().copy()
+        n = ac.size
+        args = [_f64(v).ravel() for v in (mh, ml, wh, wl)]
+        nf = _lib().orc_cdm(*self._spec_args(), n, *(_ptr(v) for v in args), int(iters),
+                            float(mu0), _ptr(ac), _ptr(ap), None)
+        self.counts["f"] += nf
+        return ac.reshape(sh), ap.reshape(sh)
+
+    def fbp(self, sino: np.ndarray) -> np.ndarray:
+        """Filtered backprojection of line integrals [V, D] (Kak and Slaney): parallel beam
+        x = (span/V) sum_v q_v(s), q_v = delta (p_v * h); equispaced fan beam with the
+        detector scaled to the isocentre (spacing delta), x = (span/V) sum_v U^-2 q_v(s),
+        q_v = delta (R'_v * h) / 2, R' = R D / sqrt(D^2 + s^2), U = L / D; h the Ram-Lak
+        kernel, linear interpolation in s, zero outside the detector."""
+        g = self.geom
+        V, Dn = self.sino_shape
+        ny, nx = self.img_shape
+        P = 1
+        while P < 2 * Dn:
+            P *= 2
+        fan = g["kind"] == "fan"
+        delta = g["det_cm"] * (g["src_iso_cm"] / g["src_det_cm"] if fan else 1.0)
+        u = (np.arange(Dn) - 0.5 * (Dn - 1) + g["det_offset"]) * delta
+        pre = np.asarray(sino, dtype=np.float64)
+        if fan:
+            Dsrc = g["src_iso_cm"]
+            pre = pre * (Dsrc / np.sqrt(Dsrc ** 2 + u ** 2))[None, :]
+        H = np.fft.fft(ramlak_kernel(P, delta))
+        pad = np.zeros((V, P))
+        pad[:, :Dn] = pre
+        q = delta * np.real(np.fft.ifft(np.fft.fft(pad, axis=1) * H[None, :], axis=1))[:, :Dn]
+        if fan:
+            q *= 0.5
+        xs = (np.arange(nx) - 0.5 * (nx - 1)) * g["pixel_cm"]
+        ys = (np.arange(ny) - 0.5 * (ny - 1)) * g["pixel_cm"]
+        X, Y = np.meshgrid(xs, ys)
+        img = np.zeros((ny, nx))
+        for v in range(V):
+            t = g["angle0"] + v * g["span"] / V
+            c, sn = np.cos(t), np.sin(t)
+            if fan:
+                L = g["src_iso_cm"] - (X * c + Y * sn)
+                s_iso = g["src_iso_cm"] * (-X * sn + Y * c) / L
+                w = (g["src_iso_cm"] / L) ** 2
+            else:
+                s_iso = X * c + Y * sn
+                w = 1.0
+            b = s_iso / delta + 0.5 * (Dn - 1) - g["det_offset"]
+            b0 = np.floor(b)
+            al = b - b0
+            i0 = b0.astype(np.int64)
+            v0 = np.where((i0 >= 0) & (i0 < Dn), q[v, np.clip(i0, 0, Dn - 1)], 0.0)
+            v1 = np.where((i0 + 1 >= 0) & (i0 + 1 < Dn), q[v, np.clip(i0 + 1, 0, Dn - 1)], 0.0)
+            img += w * ((1.0 - al) * v0 + al * v1)
+        return img * (g["span"] / V)
+
+    def cdm_fbp(self, mh, ml, wh, wl, iters=20):
+        """The projection-wise baseline: CDM line integrals, then FBP of each basis."""
+        ac, ap = self.cdm(mh, ml, wh, wl, iters)
+        return (ac, ap), np.stack([self.fbp(ac), self.fbp(ap)])
+
     def linearised(self, mh, ml):
         """a solving the 2x2 linearisation of f at a = 0 (rows = spectrum-mean f_KN, f_p)."""
         (hc, hp), (lc, lp) = self.mean_f
@@ -286,17 +367,33 @@ class Oracle:
                 + sum(lam[b] * np.abs(st.y[b]).sum() for b in range(2)))
 
     # -- ADMM ------------------------------------------------------------------
-    def admm_init(self, mh, ml, wh, wl, params: Params, init_iters: int = 10) -> State:
-        """x = 0 and a from a rho = 0 decomposition started at the linearised solution."""
+    def admm_init(self, mh, ml, wh, wl, params: Params, init_iters: int = 10,
+                  x0: np.ndarray | None = None) -> State:
+        """a from a rho = 0 decomposition started at the linearised solution; x = 0, or
+        x = x0 [2, ny, nx] with R x = R x0, y = D x0, z = x0 and u = 0."""
         ny, nx = self.img_shape
         V, Dn = self.sino_shape
         ac, ap = self.linearised(mh, ml)
         ac, ap, _ = self.udm(mh, ml, wh, wl, None, None, 0.0, 0.0, init_iters, ac, ap,
                              params.lm_mu0)
         z2 = lambda *s: np.zeros((2,) + s)
-        return State(x=z2(ny, nx), Rx=z2(V, Dn), a=np.stack([ac, ap]), ua=z2(V, Dn),
-                     y=z2(2, ny, nx), uy=z2(2, ny, nx), z=z2(ny, nx), uz=z2(ny, nx),
-                     rho=np.array(params.rho0, dtype=np.float64))
+        st = State(x=z2(ny, nx), Rx=z2(V, Dn), a=np.stack([ac, ap]), ua=z2(V, Dn),
+                   y=z2(2, ny, nx), uy=z2(2, ny, nx), z=z2(ny, nx), uz=z2(ny, nx),
+                   rho=np.array(params.rho0, dtype=np.float64))
+        if x0 is not None:
+            st.x = np.array(x0, dtype=np.float64)
+            st.z = st.x.copy()
+            for b in range(2):
+                st.Rx[b] = self.project(st.x[b], count=None)
+                st.y[b] = D(st.x[b])
+        return st
+
+    def cdm_fbp_start(self, mh, ml, wh, wl, cdm_iters=20) -> np.ndarray:
+        """The paper's initial image (Sec. 4): the CDM-FBP Compton image, and for the
+        photoelectric image that Compton image scaled by sum(a_p) / sum(a_c) over the
+        CDM line integrals."""
+        (ac, ap), x = self.cdm_fbp(mh, ml, wh, wl, cdm_iters)
+        return np.stack([x[0], (float(np.sum(ap)) / float(np.sum(ac))) * x[0]])
 
     def cg(self, x, Rx, rhs_sino, rhs_img, n, filt=None):
         """n CG iterations on (R^T R + D^T D + I) x = R^T rhs_sino + rhs_img (Eq. (12)),

@@ -278,3 +278,67 @@ int orc_udm(int nh, const double* lnw_h, const double* fkn_h, const double* fp_h
     }
     return 2 * (iters + 1);
 }
+
+/* Constrained decomposition (CDM, the projection-wise baseline of Sec. 2): per ray,
+ * minimise 1/2 sum_s w_s (f_s(a) - m_s)^2 over a >= 0 by Levenberg-Marquardt with an
+ * active set: a coordinate at zero whose gradient is positive is held at zero and
+ * the damped Gauss-Newton step is taken in the other coordinate alone; trial points
+ * are projected onto a >= 0 and accepted on a strict decrease, as in orc_udm.
+ * a: start point, projected first. */
+int orc_cdm(int nh, const double* lnw_h, const double* fkn_h, const double* fp_h, int nl,
+            const double* lnw_l, const double* fkn_l, const double* fp_l, long n,
+            const double* mh, const double* ml, const double* wh, const double* wl, int iters,
+            double mu0, double* ac, double* ap, double* phi_out) {
+    orc_spec sh = {nh, lnw_h, fkn_h, fp_h}, sl = {nl, lnw_l, fkn_l, fp_l};
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < n; ++i) {
+        double a_c = fmax(ac[i], 0.0), a_p = fmax(ap[i], 0.0);
+        orc_eval cur, tri;
+        udm_eval(&sh, &sl, mh[i], ml[i], wh[i], wl[i], 0.0, 0.0, 0.0, 0.0, a_c, a_p, &cur);
+        double mu = mu0;
+        for (int it = 0; it < iters; ++it) {
+            double rh = cur.fh - mh[i], rl = cur.fl - ml[i];
+            double Gc = wh[i] * rh * cur.ghc + wl[i] * rl * cur.glc;
+            double Gp = wh[i] * rh * cur.ghp + wl[i] * rl * cur.glp;
+            double Hcc = wh[i] * cur.ghc * cur.ghc + wl[i] * cur.glc * cur.glc;
+            double Hpp = wh[i] * cur.ghp * cur.ghp + wl[i] * cur.glp * cur.glp;
+            double Hcp = wh[i] * cur.ghc * cur.ghp + wl[i] * cur.glc * cur.glp;
+            double Dcc = (1.0 + mu) * Hcc, Dpp = (1.0 + mu) * Hpp;
+            const int fix_c = a_c == 0.0 && Gc > 0.0, fix_p = a_p == 0.0 && Gp > 0.0;
+            if (fix_c && fix_p) break;  /* stationary at the corner */
+            double dc, dp;
+            if (fix_c || fix_p) {
+                const double D1 = fix_c ? Dpp : Dcc;
+                if (!(D1 > 0.0) || !isfinite(D1)) {
+                    mu *= 10.0;
+                    continue;
+                }
+                dc = fix_c ? 0.0 : -Gc / D1;
+                dp = fix_p ? 0.0 : -Gp / D1;
+            } else {
+                double det = Dcc * Dpp - Hcp * Hcp;
+                if (!(det > 0.0) || !isfinite(det)) {
+                    mu *= 10.0;
+                    continue;
+                }
+                dc = -(Dpp * Gc - Hcp * Gp) / det;
+                dp = -(Dcc * Gp - Hcp * Gc) / det;
+            }
+            double tc = fmax(a_c + dc, 0.0);
+            double tp = fmax(a_p + dp, 0.0);
+            udm_eval(&sh, &sl, mh[i], ml[i], wh[i], wl[i], 0.0, 0.0, 0.0, 0.0, tc, tp, &tri);
+            if (tri.phi < cur.phi) {
+                a_c = tc;
+                a_p = tp;
+                cur = tri;
+                mu /= 10.0;
+            } else {
+                mu *= 10.0;
+            }
+        }
+        ac[i] = a_c;
+        ap[i] = a_p;
+        if (phi_out) phi_out[i] = cur.phi;
+    }
+    return 2 * (iters + 1);
+}
