@@ -163,6 +163,48 @@ typedef enum { DECT_PRECOND_NONE = 0, DECT_PRECOND_RAMP = 1 } dect_precond;
  * so calls with one plan must not run concurrently on different streams. */
 dect_status dect_precondition(const dect_plan* plan, const void* img, void* out, void* stream);
 
+/* The projection-wise baseline and the initial image (Sec. 2, the constrained
+ * decomposition CDM; Sec. 4, the start of the iterations). */
+
+/* CDM: per ray, minimise 1/2 sum_s w_s (f_s(a) - m_s)^2 over a >= 0 by lm_iters
+ * projected Levenberg-Marquardt iterations started at the linearised solution
+ * clipped to a >= 0.  A coordinate at its bound whose gradient points out of the
+ * feasible set is held there and the other one takes a 1-D damped step; every
+ * accepted point is projected onto a >= 0.  m_*, w_*: device [n_views*n_det]; a:
+ * device [n_views][n_det][2], out; cost: device [n_views*n_det] or NULL (final
+ * objective).  async. */
+dect_status dect_cdm(const dect_plan* plan, const void* m_h, const void* m_l, const void* w_h,
+                     const void* w_l, int lm_iters, void* a, void* cost, void* stream);
+
+/* Filtered backprojection of line integrals.  Parallel beam: every view row is
+ * convolved with the discrete Ram-Lak kernel of the bin spacing (times the
+ * spacing), the result linearly interpolated at each pixel's detector coordinate
+ * (zero off the detector) and summed over views times span/n_views.  Fan beam with
+ * a flat detector: the same with the detector scaled to the isocentre, each row
+ * pre-weighted by D/sqrt(D^2+u^2) and halved, and each view's contribution
+ * weighted by (D/L)^2, D = src_iso_cm and L the distance from the source to the
+ * pixel along the central ray.  sino: device [n_views][n_det][ch]; img: device
+ * [ny][nx][ch] (overwritten); ch in {1, 2}.  DECT_E_SHAPE if the row padded to a
+ * power of two at least 2 n_det exceeds 4096.  async; plan-owned scratch (calls
+ * with one plan must not overlap on different streams). */
+dect_status dect_fbp(const dect_plan* plan, const void* sino, void* img, int ch, void* stream);
+
+/* CDM-FBP and the initial image: a = CDM(m, w) with cdm_iters iterations, the FBP
+ * of both bases, and x0 = (x_c, s x_c) with x_c the Compton FBP image and s =
+ * sum(a_p) / sum(a_c) over all rays (0 if the sum of a_c is 0).  a: device
+ * [n_views][n_det][2], out; x0: device [ny][nx][2], out; fbp_out: device
+ * [ny][nx][2] for the FBP image pair, or NULL.  async; plan-owned scratch. */
+dect_status dect_cdm_fbp_start(const dect_plan* plan, const void* m_h, const void* m_l,
+                               const void* w_h, const void* w_l, int cdm_iters, void* a,
+                               void* x0, void* fbp_out, void* stream);
+
+/* As dect_admm_init, then the iterations start from the image pair x0 (device
+ * [ny][nx][2]) instead of 0: x = z = x0, R x = R x0, y = D x0 (forward
+ * differences as in Eq. (9)), u = 0.  async. */
+dect_status dect_admm_init_image(const dect_plan* plan, const void* m_h, const void* m_l,
+                                 const void* w_h, const void* w_l, const void* x0, void* state,
+                                 const dect_params* params, void* stream);
+
 /* Per-iteration record, filled when the caller passes a log buffer. */
 typedef struct {
     int32_t iter;       /* outer iteration index */

@@ -755,6 +755,19 @@ dect_status dect_admm_init(const dect_plan* p, const void* m_h, const void* m_l,
                                 : init_T<double>(p, m_h, m_l, w_h, w_l, state, prm, s);
 }
 
+dect_status dect_admm_init_image(const dect_plan* p, const void* m_h, const void* m_l,
+                                 const void* w_h, const void* w_l, const void* x0, void* state,
+                                 const dect_params* prm, void* stream) {
+    if (!x0) return fail(DECT_E_ARG, "null argument");
+    dect_status st = dect_admm_init(p, m_h, m_l, w_h, w_l, state, prm, stream);
+    if (st) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const hipError_t e = p->dtype == DECT_F32 ? launch_init_image<float>(p, x0, state, s)
+                                              : launch_init_image<double>(p, x0, state, s);
+    if (e != hipSuccess) return fail(DECT_E_DEVICE, "launch failed: %s", hipGetErrorString(e));
+    return DECT_OK;
+}
+
 dect_status dect_admm_iterate(const dect_plan* p, const void* m_h, const void* m_l,
                               const void* w_h, const void* w_l, void* state,
                               const dect_params* prm, int n_iters, dect_iter_log* log,

@@ -107,7 +107,18 @@ struct dect_plan {
     void* pre_twx = nullptr;     // T[px/2][2] twiddles exp(-2 pi i k / px)
     void* pre_twy = nullptr;     // T[py/2][2]
     void* scratch_W = nullptr;   // T[ny][px][2] work grid of dect_precondition
-    double* scratch_part = nullptr;
+    double* scratch_part = nullptr;  // block partials of the standalone calls (>= ny, >= 4)
+    // filtered backprojection (FBP rows padded to fbp_P = 2^fbp_lg; absent when
+    // fbp_P exceeds kMaxFbp)
+    bool has_fbp = false;
+    int fbp_P = 0, fbp_lg = 0;
+    double fbp_delta = 0.0;      // detector spacing at the isocentre, cm
+    double fbp_b0 = 0.0;         // bin index of detector coordinate 0
+    void* fbp_H = nullptr;       // T[P] filter spectrum (scaled)
+    void* fbp_tw = nullptr;      // T[P/2][2] twiddles
+    void* fbp_trig = nullptr;    // T[V][2] (cos, sin) of the view angles
+    void* fbp_wpre = nullptr;    // T[D] fan pre-weights (1 for parallel beams)
+    void* scratch_Q = nullptr;   // T[V][D][2] filtered rows
     // state layout (bytes)
     dect_layout layout;
     size_t off_p, off_pO, off_pOT, off_r, off_q, off_dy, off_dz, off_Rp, off_t, off_da, off_fg,
@@ -130,6 +141,7 @@ __host__ __device__ inline long std_ray(long l, int sym, int Vb, int D) {
 }
 
 constexpr int kMaxFft = 2048;     // longest padded side of the preconditioner's FFT
+constexpr int kMaxFbp = 4096;     // longest padded detector row of the FBP filter
 constexpr int kLogCap = 256;      // iterations kept in the device log ring
 constexpr int kLogStride = 12;    // doubles per log entry
 constexpr int kPartialSlots = 4;  // doubles per block partial

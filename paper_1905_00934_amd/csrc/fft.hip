@@ -16,44 +16,12 @@
 // Each transform is a radix-2 decimation-in-time FFT in LDS on bit-reversed input,
 // with the twiddles exp(-2 pi i k / P) from the plan's table.
 #include "common.h"
+#include "fftcore.h"
 #include "kernels.h"
 #include "profile.h"
 
 namespace dect {
 namespace {
-
-template <typename T>
-struct cx {
-    T re, im;
-};
-
-__device__ inline int bitrev(int i, int lg) { return (int)(__brev((unsigned)i) >> (32 - lg)); }
-
-// In-place FFTs of `count` sequences of length 2^lg stored back to back in buf,
-// each in bit-reversed order on entry and natural order on exit.  inverse: the
-// conjugate twiddles (no 1/P factor).  Every thread of the block must call it.
-template <typename T>
-__device__ void fft_lds(cx<T>* buf, int count, int lg, const T* __restrict__ tw, bool inverse) {
-    const int half = 1 << (lg - 1);
-    for (int s = 0; s < lg; ++s) {
-        __syncthreads();
-        const int m = 1 << s;
-        const int ts = lg - 1 - s;  // twiddle index = pos * P / (2m)
-        for (int t = threadIdx.x; t < count * half; t += blockDim.x) {
-            const int seq = t >> (lg - 1), b = t & (half - 1);
-            const int pos = b & (m - 1);
-            const int i0 = ((b >> s) << (s + 1)) + pos, i1 = i0 + m;
-            const T wr = tw[2 * (pos << ts)];
-            const T wi = inverse ? -tw[2 * (pos << ts) + 1] : tw[2 * (pos << ts) + 1];
-            cx<T>* x = buf + ((size_t)seq << lg);
-            const cx<T> a = x[i0], c = x[i1];
-            const T br = wr * c.re - wi * c.im, bi = wr * c.im + wi * c.re;
-            x[i0] = cx<T>{a.re + br, a.im + bi};
-            x[i1] = cx<T>{a.re - br, a.im - bi};
-        }
-    }
-    __syncthreads();
-}
 
 template <typename T, bool BATCH>
 __global__ __launch_bounds__(256) void k_pre_rows_fwd(const PrecArgs<T>* __restrict__ dev,

@@ -111,7 +111,8 @@ hipError_t launch_backproject_admm(int sym, int waves, int epi, const BpArgs<T>*
 template <typename T>
 void fill_bp_plan(const dect_plan* p, BpArgs<T>& a);
 
-// Per-ray decomposition.  mode 0: standalone call; 1: ADMM initialisation; 2: ADMM a-step.
+// Per-ray decomposition.  mode 0: standalone call; 1: ADMM initialisation; 2: ADMM a-step;
+// 3: constrained decomposition (a >= 0, no rho terms) from the projected linearised start.
 template <typename T>
 struct UdmArgs {
     const T* spec;     // spectral tables (plan)
@@ -279,6 +280,11 @@ SliceJob<T> make_job(const dect_plan* p, const void* mh, const void* ml, const v
 template <typename T>
 hipError_t launch_iteration(const SliceJob<T>& one, const JobArrays<T>* dev, int n,
                             const dect_params* prm, long it, hipStream_t s);
+
+// Start of the iterations from an image pair x0: x = z = x0, y = D x0, R x = R x0 and
+// t = a - R x0 (the state already initialised with x = 0).
+template <typename T>
+hipError_t launch_init_image(const dect_plan* p, const void* x0, void* state, hipStream_t s);
 
 template <typename T>
 hipError_t launch_ingest(const dect_plan* p, const void* ch, const void* cl, double i0h,

@@ -222,8 +222,66 @@ dect_status build_precond(dect_plan* p) {
         if (st) return st;
     }
     DECT_HIP(hipMalloc(&p->scratch_W, (size_t)p->ny * px * 2 * sizeof(T)));
-    DECT_HIP(hipMalloc(&p->scratch_part, (size_t)p->ny * kPartialSlots * sizeof(double)));
     p->has_precond = true;
+    return DECT_OK;
+}
+
+// Filtered backprojection (the CDM-FBP baseline): the discrete Ram-Lak kernel of
+// the detector spacing delta at the isocentre, h[0] = 1/(4 delta^2), h[n] =
+// -1/(pi^2 n^2 delta^2) for odd n, zero for even n, circular over P = a power of
+// two at least twice the bins; its DFT (real and even) is stored scaled by
+// delta / P (and 1/2 for a fan over a full turn), so the filtered row is the
+// inverse FFT of the product with no further factor.  Per view the (cos, sin) of
+// its angle; per bin the fan pre-weight D / sqrt(D^2 + u^2).
+template <typename T>
+dect_status build_fbp(dect_plan* p) {
+    const dect_geometry& g = p->geom;
+    p->fbp_P = pad_pow2(p->D, p->fbp_lg);
+    if (p->fbp_P > kMaxFbp) return DECT_OK;
+    const int P = p->fbp_P, D = p->D, V = p->V;
+    const bool fan = g.kind == DECT_FAN;
+    const double delta = g.det_cm * (fan ? g.src_iso_cm / g.src_det_cm : 1.0);
+    p->fbp_delta = delta;
+    p->fbp_b0 = 0.5 * (D - 1) - g.det_offset;
+    const double pi = 3.141592653589793;
+    std::vector<double> h(P / 2 + 1, 0.0);
+    h[0] = 1.0 / (4.0 * delta * delta);
+    for (int n = 1; n <= P / 2; n += 2) h[n] = -1.0 / (pi * pi * (double)n * n * delta * delta);
+    std::vector<T> H(P);
+    const double scale = delta / P * (fan ? 0.5 : 1.0);
+    for (int k = 0; k < P; ++k) {
+        // h is even: H[k] = h[0] + 2 sum_{0 < n < P/2} h[n] cos(2 pi k n / P) + h[P/2] cos(pi k).
+        double acc = h[0];
+        for (int n = 1; n < P / 2; n += 2) acc += 2.0 * h[n] * std::cos(2.0 * pi * (double)k * n / P);
+        acc += h[P / 2] * ((k & 1) ? -1.0 : 1.0);
+        H[k] = (T)(acc * scale);
+    }
+    dect_status st = upload<T>(H.data(), H.size() * sizeof(T), &p->fbp_H);
+    if (st) return st;
+    std::vector<T> tw((size_t)P);
+    for (int k = 0; k < P / 2; ++k) {
+        tw[2 * k] = (T)std::cos(2.0 * pi * k / P);
+        tw[2 * k + 1] = (T)(-std::sin(2.0 * pi * k / P));
+    }
+    st = upload<T>(tw.data(), tw.size() * sizeof(T), &p->fbp_tw);
+    if (st) return st;
+    std::vector<T> trig((size_t)2 * V);
+    for (int v = 0; v < V; ++v) {
+        const double t = g.angle0 + (double)v * g.span / V;
+        trig[2 * v] = (T)std::cos(t);
+        trig[2 * v + 1] = (T)std::sin(t);
+    }
+    st = upload<T>(trig.data(), trig.size() * sizeof(T), &p->fbp_trig);
+    if (st) return st;
+    std::vector<T> wpre((size_t)D);
+    for (int b = 0; b < D; ++b) {
+        const double u = ((double)b - 0.5 * (D - 1) + g.det_offset) * delta;
+        wpre[b] = (T)(fan ? g.src_iso_cm / std::sqrt(g.src_iso_cm * g.src_iso_cm + u * u) : 1.0);
+    }
+    st = upload<T>(wpre.data(), wpre.size() * sizeof(T), &p->fbp_wpre);
+    if (st) return st;
+    DECT_HIP(hipMalloc(&p->scratch_Q, (size_t)V * D * 2 * sizeof(T)));
+    p->has_fbp = true;
     return DECT_OK;
 }
 
@@ -359,6 +417,11 @@ dect_status dect_plan_create(const dect_geometry* geom, const dect_spectra* spec
     }
     dect_status st = dtype == DECT_F32 ? build_tables<float>(p, spec) : build_tables<double>(p, spec);
     if (st == DECT_OK) st = dtype == DECT_F32 ? build_precond<float>(p) : build_precond<double>(p);
+    if (st == DECT_OK) st = dtype == DECT_F32 ? build_fbp<float>(p) : build_fbp<double>(p);
+    if (st == DECT_OK && hipMalloc(reinterpret_cast<void**>(&p->scratch_part),
+                                   (size_t)(p->ny > 4 ? p->ny : 4) * kPartialSlots *
+                                       sizeof(double)) != hipSuccess)
+        st = fail(DECT_E_NOMEM, "device allocation failed");
     if (st != DECT_OK) {
         dect_plan_destroy(p);
         return st;
@@ -380,6 +443,11 @@ void dect_plan_destroy(dect_plan* p) {
     (void)hipFree(p->pre_twy);
     (void)hipFree(p->scratch_W);
     (void)hipFree(p->scratch_part);
+    (void)hipFree(p->fbp_H);
+    (void)hipFree(p->fbp_tw);
+    (void)hipFree(p->fbp_trig);
+    (void)hipFree(p->fbp_wpre);
+    (void)hipFree(p->scratch_Q);
     delete p;
 }
 

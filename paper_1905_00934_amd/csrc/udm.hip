@@ -98,7 +98,11 @@ __device__ inline T det2(T a, T d, T b, T c) {
 // the current point: the exponents then change by at most
 // B = kcmax |d_c| + kpmax |d_p|, so for B <= 96 nothing overflows and the largest
 // term stays above 2^-(96 + log2 K).  Larger steps take the two-pass form.
-template <typename T>
+//
+// CONSTR (the constrained decomposition, a >= 0): a coordinate at zero whose
+// gradient is positive is held at zero and the damped step is taken in the other
+// coordinate alone; trial points are projected onto a >= 0.
+template <typename T, bool CONSTR = false>
 __device__ inline void lm_solve(const T* __restrict__ spec, int kmax, int kh, int kl, T mh, T ml,
                                 T wh, T wl, T vc, T vp, T rc, T rp, int iters, T mu,
                                 StepBound sb, Point<T>& P) {
@@ -111,22 +115,45 @@ __device__ inline void lm_solve(const T* __restrict__ spec, int kmax, int kh, in
         const T App = wh * P.ghp * P.ghp + wl * P.glp * P.glp;
         const T Hcc = Acc + rc, Hpp = App + rp;
         const T Hcp = wh * P.ghc * P.ghp + wl * P.glc * P.glp;
-        // det(H + mu diag H) as a sum of nonnegative terms (no cancellation):
-        // w_h w_l (g_h x g_l)^2 + rc App + rp Acc + rc rp + mu (2 + mu) Hcc Hpp.
-        const T cr = det2<T>(P.ghc, P.glp, P.ghp, P.glc);
-        const T det = wh * wl * cr * cr + rc * App + rp * Acc + rc * rp +
-                      mu * (T(2) + mu) * Hcc * Hpp;
-        if (!(det > T(0)) || !(det < INFINITY)) {
-            mu *= T(10);
-            continue;
-        }
         const T Dcc = (T(1) + mu) * Hcc, Dpp = (T(1) + mu) * Hpp;
-        const T id = T(1) / det;
+        bool fix_c = false, fix_p = false;
+        if constexpr (CONSTR) {
+            fix_c = P.ac == T(0) && Gc > T(0);
+            fix_p = P.ap == T(0) && Gp > T(0);
+            if (fix_c && fix_p) break;  // stationary at the corner
+        }
+        T dc, dp;
+        if (fix_c || fix_p) {
+            const T d1 = fix_c ? Dpp : Dcc;
+            if (!(d1 > T(0)) || !(d1 < INFINITY)) {
+                mu *= T(10);
+                continue;
+            }
+            dc = fix_c ? T(0) : -Gc / d1;
+            dp = fix_p ? T(0) : -Gp / d1;
+        } else {
+            // det(H + mu diag H) as a sum of nonnegative terms (no cancellation):
+            // w_h w_l (g_h x g_l)^2 + rc App + rp Acc + rc rp + mu (2 + mu) Hcc Hpp.
+            const T cr = det2<T>(P.ghc, P.glp, P.ghp, P.glc);
+            const T det = wh * wl * cr * cr + rc * App + rp * Acc + rc * rp +
+                          mu * (T(2) + mu) * Hcc * Hpp;
+            if (!(det > T(0)) || !(det < INFINITY)) {
+                mu *= T(10);
+                continue;
+            }
+            const T id = T(1) / det;
+            dc = -(Dpp * Gc - Hcp * Gp) * id;
+            dp = -(Dcc * Gp - Hcp * Gc) * id;
+        }
         Point<T> Q;
-        const T dc = -(Dpp * Gc - Hcp * Gp) * id;
-        const T dp = -(Dcc * Gp - Hcp * Gc) * id;
         Q.ac = P.ac + dc;
         Q.ap = P.ap + dp;
+        if constexpr (CONSTR) {
+            Q.ac = fmax(Q.ac, T(0));
+            Q.ap = fmax(Q.ap, T(0));
+            dc = Q.ac - P.ac;
+            dp = Q.ap - P.ap;
+        }
         const T bound = (T)sb.kcmax * fabs(dc) + (T)sb.kpmax * fabs(dp);
         // A non-finite current value gives no usable shift either.
         const bool exact = !(bound <= T(96)) || !(P.fh - P.fh == T(0)) || !(P.fl - P.fl == T(0));
@@ -163,10 +190,14 @@ __global__ __launch_bounds__(256) void k_udm(const UdmArgs<T>* __restrict__ dev,
         V2 rx;
         V2 ua;
         const V2 a_prev = a2[i];
-        if constexpr (MODE == 1) {
-            // Initialisation: start at the solution of the linearisation at a = 0.
+        if constexpr (MODE == 1 || MODE == 3) {
+            // Start at the solution of the linearisation at a = 0 (CDM: projected).
             P.ac = (T)(A.lin[0] * (double)mh + A.lin[1] * (double)ml);
             P.ap = (T)(A.lin[2] * (double)mh + A.lin[3] * (double)ml);
+            if constexpr (MODE == 3) {
+                P.ac = fmax(P.ac, T(0));
+                P.ap = fmax(P.ap, T(0));
+            }
         } else {
             P.ac = a_prev.v[0];
             P.ap = a_prev.v[1];
@@ -207,12 +238,13 @@ __global__ __launch_bounds__(256) void k_udm(const UdmArgs<T>* __restrict__ dev,
         } else {
             evaluate<T>(spec, kmax, kh, kl, mh, ml, wh, wl, vc, vp, rc, rp, T(0), T(0), true, P);
         }
-        lm_solve<T>(spec, kmax, kh, kl, mh, ml, wh, wl, vc, vp, rc, rp, A.iters, (T)A.mu0, sb, P);
+        lm_solve<T, MODE == 3>(spec, kmax, kh, kl, mh, ml, wh, wl, vc, vp, rc, rp, A.iters,
+                               (T)A.mu0, sb, P);
         V2 an;
         an.v[0] = P.ac;
         an.v[1] = P.ap;
         a2[i] = an;
-        if constexpr (MODE != 0) {
+        if constexpr (MODE == 1 || MODE == 2) {
             V4 c0;
             V2 c1;
             c0.v[0] = P.fh;
@@ -224,7 +256,7 @@ __global__ __launch_bounds__(256) void k_udm(const UdmArgs<T>* __restrict__ dev,
             reinterpret_cast<V4*>(A.fg)[2 * l] = c0;
             reinterpret_cast<V2*>(A.fg)[4 * l + 2] = c1;
         }
-        if constexpr (MODE == 0) {
+        if constexpr (MODE == 0 || MODE == 3) {
             if (A.cost) A.cost[i] = P.phi;
         } else if constexpr (MODE == 1) {
             reinterpret_cast<V2*>(A.t)[l] = an;  // u^a = R x = 0
@@ -281,9 +313,11 @@ hipError_t launch_udm(const dect_plan* p, int mode, const UdmArgs<T>& a0, hipStr
     UdmArgs<T> a = a0;
     if (p) fill_udm_tables<T>(p, a);  // else the tables are already in a
     dim3 g((unsigned)((a.M + 255) / 256));
-    ProfScope ps(mode == 1 ? "udm_init" : "udm", s);
+    ProfScope ps(mode == 1 ? "udm_init" : (mode == 3 ? "cdm" : "udm"), s);
     if (mode == 0)
         hipLaunchKernelGGL((k_udm<T, 0, false>), g, dim3(256), 0, s, nullptr, a);
+    else if (mode == 3)
+        hipLaunchKernelGGL((k_udm<T, 3, false>), g, dim3(256), 0, s, nullptr, a);
     else if (mode == 1)
         hipLaunchKernelGGL((k_udm<T, 1, false>), g, dim3(256), 0, s, nullptr, a);
     else

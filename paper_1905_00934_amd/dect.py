@@ -140,6 +140,10 @@ def lib():
             "dect_batch_groups": [vp],
             "dect_batch_destroy": [vp],
             "dect_precondition": [vp, vp, vp, vp],
+            "dect_cdm": [vp, vp, vp, vp, vp, i, vp, vp, vp],
+            "dect_fbp": [vp, vp, vp, i, vp],
+            "dect_cdm_fbp_start": [vp, vp, vp, vp, vp, i, vp, vp, vp, vp],
+            "dect_admm_init_image": [vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(Params), vp],
             "dect_plan_tune": [vp, ctypes.c_char_p, i, ctypes.POINTER(Launch), vp],
             "dect_plan_set_launch": [vp, i, i],
             "dect_plan_get_launch": [vp, ctypes.POINTER(Launch)],
@@ -360,6 +364,39 @@ class Plan:
         _check(lib().dect_precondition(self.handle, _ptr(img), _ptr(out), _stream()))
         return out
 
+    def cdm(self, m_h, m_l, w_h, w_l, lm_iters=20, a=None, cost=None) -> torch.Tensor:
+        """Constrained (a >= 0) per-ray decomposition; returns a [V, D, 2]."""
+        for t, n in ((m_h, "m_h"), (m_l, "m_l"), (w_h, "w_h"), (w_l, "w_l")):
+            self._chk(t, (self.V, self.D), n)
+        a = self._t((self.V, self.D, 2)) if a is None else a
+        self._chk(a, (self.V, self.D, 2), "a")
+        if cost is not None:
+            self._chk(cost, (self.V, self.D), "cost")
+        _check(lib().dect_cdm(self.handle, _ptr(m_h), _ptr(m_l), _ptr(w_h), _ptr(w_l),
+                              int(lm_iters), _ptr(a), _ptr(cost), _stream()))
+        return a
+
+    def fbp(self, sino: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Filtered backprojection of [V, D] or [V, D, 2] line integrals."""
+        ch = 1 if sino.dim() == 2 else sino.shape[-1]
+        self._chk(sino, (self.V, self.D) if ch == 1 else (self.V, self.D, ch), "sino")
+        shape = (self.ny, self.nx) if ch == 1 else (self.ny, self.nx, ch)
+        out = self._t(shape) if out is None else out
+        self._chk(out, shape, "out")
+        _check(lib().dect_fbp(self.handle, _ptr(sino), _ptr(out), int(ch), _stream()))
+        return out
+
+    def cdm_fbp_start(self, meas, cdm_iters=20):
+        """CDM line integrals a, the FBP image pair and the initial image x0."""
+        for t, n in zip(meas, ("m_h", "m_l", "w_h", "w_l")):
+            self._chk(t, (self.V, self.D), n)
+        a = self._t((self.V, self.D, 2))
+        x0 = self._t((self.ny, self.nx, 2))
+        img = self._t((self.ny, self.nx, 2))
+        _check(lib().dect_cdm_fbp_start(self.handle, *(_ptr(m) for m in meas), int(cdm_iters),
+                                        _ptr(a), _ptr(x0), _ptr(img), _stream()))
+        return a, img, x0
+
     def tune(self, cache: str | None = None, force: bool = False) -> dict:
         """Choose the ADMM kernels' workgroup shapes by timing (or from the cache)."""
         L = Launch()
@@ -383,10 +420,16 @@ class Plan:
     def new_state(self) -> State:
         return State(self)
 
-    def admm_init(self, meas, state: State, params: AdmmParams):
+    def admm_init(self, meas, state: State, params: AdmmParams, x0: torch.Tensor | None = None):
+        """Initial state; with x0 [ny, nx, 2] the iterations start from that image."""
         P, keep = params.c_struct()
-        _check(lib().dect_admm_init(self.handle, *(_ptr(m) for m in meas), state.ptr,
-                                    ctypes.byref(P), _stream()))
+        if x0 is None:
+            _check(lib().dect_admm_init(self.handle, *(_ptr(m) for m in meas), state.ptr,
+                                        ctypes.byref(P), _stream()))
+        else:
+            self._chk(x0, (self.ny, self.nx, 2), "x0")
+            _check(lib().dect_admm_init_image(self.handle, *(_ptr(m) for m in meas), _ptr(x0),
+                                              state.ptr, ctypes.byref(P), _stream()))
 
     def admm_iterate(self, meas, state: State, params: AdmmParams, n_iters: int,
                      log: bool = False):
