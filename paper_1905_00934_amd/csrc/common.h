@@ -116,7 +116,7 @@ struct dect_plan {
     double fbp_b0 = 0.0;         // bin index of detector coordinate 0
     void* fbp_H = nullptr;       // T[P] filter spectrum (scaled)
     void* fbp_tw = nullptr;      // T[P/2][2] twiddles
-    void* fbp_trig = nullptr;    // T[V][2] (cos, sin) of the view angles
+    void* fbp_view = nullptr;    // T[V][4] (di, dj, ni, nj): bin and weight of a pixel
     void* fbp_wpre = nullptr;    // T[D] fan pre-weights (1 for parallel beams)
     void* scratch_Q = nullptr;   // T[V][D][2] filtered rows
     // state layout (bytes)
@@ -145,6 +145,7 @@ constexpr int kMaxFbp = 4096;     // longest padded detector row of the FBP filt
 constexpr int kLogCap = 256;      // iterations kept in the device log ring
 constexpr int kLogStride = 12;    // doubles per log entry
 constexpr int kPartialSlots = 4;  // doubles per block partial
+constexpr int kRaySumBlocks = 240;  // block partials of the ray sums of the start image
 
 // Device scalar block (doubles), at layout.scalars.
 enum Scalar : int {

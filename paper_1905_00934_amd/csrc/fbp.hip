@@ -53,31 +53,35 @@ __global__ __launch_bounds__(256) void k_fbp_filter(const T* __restrict__ sino, 
     for (int b = threadIdx.x; b < D; b += blockDim.x) q[b] = buf[b];
 }
 
+template <typename T>
+__device__ inline T recip(T d) {
+    if constexpr (sizeof(T) == 4)
+        return __builtin_amdgcn_rcpf(d);  // 1 ulp; the bin position is good to ~1e-4 bins
+    else
+        return T(1) / d;
+}
+
+// One thread per pixel of a 16 x 16 tile (the tile's pixels read a narrow band of
+// bins per view, which stays in L1); the views are walked in order.
 template <typename T, bool FAN>
-__global__ __launch_bounds__(256) void k_fbp_back(const T* __restrict__ Q, int nx, int ny, T pixel,
-                                                  int V, int D, T delta, T b0, T src_iso,
-                                                  const T* __restrict__ trig, T dtheta, int ch,
-                                                  T* __restrict__ img) {
-    const long pix = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (pix >= (long)nx * ny) return;
-    const int j = (int)(pix / nx), i = (int)(pix % nx);
-    const T x = ((T)i - T(0.5) * (T)(nx - 1)) * pixel;
-    const T y = ((T)j - T(0.5) * (T)(ny - 1)) * pixel;
+__global__ __launch_bounds__(256) void k_fbp_back(const T* __restrict__ Q, int nx, int ny, int V,
+                                                  int D, T b0, const T* __restrict__ view,
+                                                  T dtheta, int ch, T* __restrict__ img) {
+    const int i = blockIdx.x * 16 + (threadIdx.x & 15);
+    const int j = blockIdx.y * 16 + (threadIdx.x >> 4);
+    if (i >= nx || j >= ny) return;
+    const T ic = (T)i - T(0.5) * (T)(nx - 1), jc = (T)j - T(0.5) * (T)(ny - 1);
     const cx<T>* q = reinterpret_cast<const cx<T>*>(Q);
     T ac = T(0), ap = T(0);
+#pragma unroll 4
     for (int v = 0; v < V; ++v) {
-        const T c = trig[2 * v], s = trig[2 * v + 1];
-        T u, w;
+        const T* e = view + 4 * v;
+        T r = T(1), w = T(1);
         if constexpr (FAN) {
-            const T L = src_iso - (x * c + y * s);
-            u = src_iso * (y * c - x * s) / L;
-            const T r = src_iso / L;
+            r = recip<T>(fma(e[1], jc, fma(e[0], ic, T(1))));
             w = r * r;
-        } else {
-            u = x * c + y * s;
-            w = T(1);
         }
-        const T b = u / delta + b0;
+        const T b = fma(fma(e[3], jc, e[2] * ic), r, b0);
         const T fb = floor(b);
         const T al = b - fb;
         const int k = (int)fb;
@@ -85,9 +89,10 @@ __global__ __launch_bounds__(256) void k_fbp_back(const T* __restrict__ Q, int n
         const cx<T>* row = q + (size_t)v * D;
         if (k >= 0 && k < D) q0 = row[k];
         if (k + 1 >= 0 && k + 1 < D) q1 = row[k + 1];
-        ac += w * ((T(1) - al) * q0.re + al * q1.re);
-        ap += w * ((T(1) - al) * q0.im + al * q1.im);
+        ac = fma(w, fma(al, q1.re - q0.re, q0.re), ac);
+        ap = fma(w, fma(al, q1.im - q0.im, q0.im), ap);
     }
+    const long pix = (long)j * nx + i;
     if (ch == 2) {
         img[2 * pix] = ac * dtheta;
         img[2 * pix + 1] = ap * dtheta;
@@ -96,16 +101,27 @@ __global__ __launch_bounds__(256) void k_fbp_back(const T* __restrict__ Q, int n
     }
 }
 
-// Sums of a_c and a_p over all rays in a fixed order (one block): out[0], out[1].
+// Sums of a_c and a_p over all rays in a fixed order: kRaySumBlocks block partials
+// (grid-strided), then one block adds them into the slot after the partials.
 template <typename T>
 __global__ __launch_bounds__(256) void k_ray_sums(const T* __restrict__ a, long M,
-                                                  double* __restrict__ out) {
+                                                  double* __restrict__ part) {
     double v[2] = {0.0, 0.0};
-    for (long i = threadIdx.x; i < M; i += blockDim.x) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < M;
+         i += (long)gridDim.x * blockDim.x) {
         v[0] += (double)a[2 * i];
         v[1] += (double)a[2 * i + 1];
     }
-    block_sum_store<2>(v, out);
+    block_sum_store<2>(v, part + (size_t)blockIdx.x * kPartialSlots);
+}
+
+__global__ __launch_bounds__(256) void k_ray_sums_total(double* __restrict__ part, int nb) {
+    double v[2] = {0.0, 0.0};
+    if ((int)threadIdx.x < nb) {
+        v[0] = part[(size_t)threadIdx.x * kPartialSlots];
+        v[1] = part[(size_t)threadIdx.x * kPartialSlots + 1];
+    }
+    block_sum_store<2>(v, part + (size_t)nb * kPartialSlots);
 }
 
 // x0 = (x_c, s x_c) with s = sum a_p / sum a_c.
@@ -158,19 +174,19 @@ hipError_t fbp_t(const dect_plan* p, const void* sino, void* img, int ch, hipStr
                        static_cast<const T*>(sino), ch, p->D, p->fbp_lg,
                        static_cast<const T*>(p->fbp_H), static_cast<const T*>(p->fbp_tw),
                        static_cast<const T*>(p->fbp_wpre), static_cast<T*>(p->scratch_Q));
-    const dim3 g((unsigned)((p->N + 255) / 256));
+    const dim3 g((unsigned)((p->nx + 15) / 16), (unsigned)((p->ny + 15) / 16));
     const dect_geometry& G = p->geom;
     const T dtheta = (T)(G.span / p->V);
     if (G.kind == DECT_FAN)
         hipLaunchKernelGGL((k_fbp_back<T, true>), g, dim3(256), 0, s,
-                           static_cast<const T*>(p->scratch_Q), p->nx, p->ny, (T)G.pixel_cm, p->V,
-                           p->D, (T)p->fbp_delta, (T)p->fbp_b0, (T)G.src_iso_cm,
-                           static_cast<const T*>(p->fbp_trig), dtheta, ch, static_cast<T*>(img));
+                           static_cast<const T*>(p->scratch_Q), p->nx, p->ny, p->V, p->D,
+                           (T)p->fbp_b0, static_cast<const T*>(p->fbp_view), dtheta, ch,
+                           static_cast<T*>(img));
     else
         hipLaunchKernelGGL((k_fbp_back<T, false>), g, dim3(256), 0, s,
-                           static_cast<const T*>(p->scratch_Q), p->nx, p->ny, (T)G.pixel_cm, p->V,
-                           p->D, (T)p->fbp_delta, (T)p->fbp_b0, (T)G.src_iso_cm,
-                           static_cast<const T*>(p->fbp_trig), dtheta, ch, static_cast<T*>(img));
+                           static_cast<const T*>(p->scratch_Q), p->nx, p->ny, p->V, p->D,
+                           (T)p->fbp_b0, static_cast<const T*>(p->fbp_view), dtheta, ch,
+                           static_cast<T*>(img));
     return hipGetLastError();
 }
 
@@ -203,10 +219,15 @@ hipError_t cdm_t(const dect_plan* p, const void* mh, const void* ml, const void*
 
 template <typename T>
 hipError_t start_t(const dect_plan* p, const void* a, void* fbp, void* x0, hipStream_t s) {
-    hipLaunchKernelGGL((k_ray_sums<T>), dim3(1), dim3(256), 0, s, static_cast<const T*>(a), p->M,
-                       p->scratch_part);
+    static_assert(kRaySumBlocks <= 256, "one block adds the partials");
+    hipLaunchKernelGGL((k_ray_sums<T>), dim3(kRaySumBlocks), dim3(256), 0, s,
+                       static_cast<const T*>(a), p->M, p->scratch_part);
+    hipLaunchKernelGGL(k_ray_sums_total, dim3(1), dim3(256), 0, s, p->scratch_part,
+                       kRaySumBlocks);
     hipLaunchKernelGGL((k_start_image<T>), dim3((unsigned)((p->N + 255) / 256)), dim3(256), 0, s,
-                       static_cast<const T*>(fbp), p->N, p->scratch_part, static_cast<T*>(x0));
+                       static_cast<const T*>(fbp), p->N,
+                       p->scratch_part + (size_t)kRaySumBlocks * kPartialSlots,
+                       static_cast<T*>(x0));
     return hipGetLastError();
 }
 

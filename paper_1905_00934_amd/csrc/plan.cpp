@@ -265,13 +265,26 @@ dect_status build_fbp(dect_plan* p) {
     }
     st = upload<T>(tw.data(), tw.size() * sizeof(T), &p->fbp_tw);
     if (st) return st;
-    std::vector<T> trig((size_t)2 * V);
+    // Per view, the detector coordinate (in bins, before b0) of the point with
+    // centred pixel indices (i', j') is (ni i' + nj j') / den with den = 1 + di i' +
+    // dj j', and the fan weight (D / L)^2 is 1 / den^2 (den = L / D); parallel: den = 1.
+    std::vector<T> view((size_t)4 * V);
+    const double kb = g.pixel_cm / delta;
     for (int v = 0; v < V; ++v) {
-        const double t = g.angle0 + (double)v * g.span / V;
-        trig[2 * v] = (T)std::cos(t);
-        trig[2 * v + 1] = (T)std::sin(t);
+        const double t = g.angle0 + (double)v * g.span / V, c = std::cos(t), sn = std::sin(t);
+        T* e = &view[(size_t)4 * v];
+        if (fan) {
+            e[0] = (T)(-g.pixel_cm * c / g.src_iso_cm);
+            e[1] = (T)(-g.pixel_cm * sn / g.src_iso_cm);
+            e[2] = (T)(-kb * sn);
+            e[3] = (T)(kb * c);
+        } else {
+            e[0] = e[1] = (T)0;
+            e[2] = (T)(kb * c);
+            e[3] = (T)(kb * sn);
+        }
     }
-    st = upload<T>(trig.data(), trig.size() * sizeof(T), &p->fbp_trig);
+    st = upload<T>(view.data(), view.size() * sizeof(T), &p->fbp_view);
     if (st) return st;
     std::vector<T> wpre((size_t)D);
     for (int b = 0; b < D; ++b) {
@@ -419,7 +432,8 @@ dect_status dect_plan_create(const dect_geometry* geom, const dect_spectra* spec
     if (st == DECT_OK) st = dtype == DECT_F32 ? build_precond<float>(p) : build_precond<double>(p);
     if (st == DECT_OK) st = dtype == DECT_F32 ? build_fbp<float>(p) : build_fbp<double>(p);
     if (st == DECT_OK && hipMalloc(reinterpret_cast<void**>(&p->scratch_part),
-                                   (size_t)(p->ny > 4 ? p->ny : 4) * kPartialSlots *
+                                   (size_t)(p->ny > kRaySumBlocks ? p->ny : kRaySumBlocks + 1) *
+                                       kPartialSlots *
                                        sizeof(double)) != hipSuccess)
         st = fail(DECT_E_NOMEM, "device allocation failed");
     if (st != DECT_OK) {
@@ -445,7 +459,7 @@ void dect_plan_destroy(dect_plan* p) {
     (void)hipFree(p->scratch_part);
     (void)hipFree(p->fbp_H);
     (void)hipFree(p->fbp_tw);
-    (void)hipFree(p->fbp_trig);
+    (void)hipFree(p->fbp_view);
     (void)hipFree(p->fbp_wpre);
     (void)hipFree(p->scratch_Q);
     delete p;
