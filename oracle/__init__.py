@@ -21,6 +21,12 @@ be read against the paper:
 * Sec. 3.2   rho adapted from the primal and dual residuals (residual balancing)
 * Eq. (14)   xi(x) = 20 log10(||x - x*|| / ||x*||)
 * Table 1    operator counts per iteration: R 2n, R^T 2(n+1), f 4m
+* Sec. 2     CDM: per-ray decomposition constrained to a >= 0 (projected LM with an active
+             set), and FBP (Ram-Lak, parallel or flat-detector fan) of the line integrals
+* Sec. 4     the initial image: x_c from CDM-FBP, x_p = x_c sum(a_p) / sum(a_c)
+* Eqs. (7)-(8)  the baseline LM(m) x CG(n) splitting: x_c, then x_p, each by m LM
+             iterations whose Gauss-Newton steps are n CG steps with R and R^T;
+             Table 1: R 2m(n+1), R^T 2m(n+1), f 4m
 
 Readings where the paper is silent (each listed with its reason in the design
 notes): the ramp preconditioner is max(|w|, 1/P) in cycles per pixel on a
@@ -476,3 +482,137 @@ class Oracle:
                                phi=self.split_objective(st, mh, ml, wh, wl, params.lam)))
             st.it += 1
         return st
+
+    # -- LM(m) x CG(n): the baseline splitting of Eqs. (7)-(8) -------------------
+    def lmcg_init(self, mh, ml, wh, wl, params: Params, x0: np.ndarray | None = None):
+        """x = x0 [2, ny, nx] (or 0), y = D x, z = x, u = 0, R x, and f, grad f at R x."""
+        ny, nx = self.img_shape
+        x = np.zeros((2, ny, nx)) if x0 is None else np.array(x0, dtype=np.float64)
+        Rx = np.stack([self.project(x[b], count=None) for b in range(2)])
+        fh, fl, gh, gl = self.forward(Rx[0], Rx[1])
+        return LmcgState(x=x, Rx=Rx, y=np.stack([D(x[b]) for b in range(2)]),
+                         uy=np.zeros((2, 2, ny, nx)), z=x.copy(), uz=np.zeros((2, ny, nx)),
+                         rho=np.array(params.rho0, dtype=np.float64), fh=fh, fl=fl, gh=gh, gl=gl)
+
+    def _lm_basis(self, st: LmcgState, b: int, mh, ml, wh, wl, rho: float, params: Params):
+        """Eq. (7) (b = 0) or Eq. (8) (b = 1): m LM iterations on
+        Phi(x_b) = 1/2 ||f(R x_c, R x_p) - m||^2_Sigma + rho/2 ||[y_b; z_b] - [D; I] x_b + u_b||^2
+        with the other basis fixed.  Gauss-Newton curvature H = R^T W R + rho (D^T D + I),
+        W = sum_s w_s (df_s/da_b)^2 per ray; the damped system (H + mu kappa I) d = -grad Phi,
+        kappa = g^T H g / g^T g (the curvature along the gradient, from the first CG step),
+        is solved by n CG steps from d = 0; the step is accepted if Phi decreases
+        (mu / 10), else rejected (mu * 10); mu starts at lm_mu0 for every basis update."""
+        y, uy, z, uz = st.y[b], st.uy[b], st.z[b], st.uz[b]
+
+        def pen(x):
+            return 0.5 * rho * (float(np.sum((y - D(x) + uy) ** 2)) + float(np.sum((z - x + uz) ** 2)))
+
+        def data(fh, fl):
+            return 0.5 * float(np.sum(wh * (fh - mh) ** 2) + np.sum(wl * (fl - ml) ** 2))
+
+        mu = params.lm_mu0
+        for _ in range(params.lm_iters):
+            x = st.x[b]
+            Jh, Jl = st.gh[..., b], st.gl[..., b]
+            eh, el = st.fh - mh, st.fl - ml
+            t = wh * eh * Jh + wl * el * Jl
+            W = wh * Jh ** 2 + wl * Jl ** 2
+            phi = data(st.fh, st.fl) + pen(x)
+            g = self.backproject(t) + rho * (DT(D(x)) + x - DT(y + uy) - z - uz)
+
+            def H(v):
+                return self.backproject(W * self.project(v)) + rho * (DT(D(v)) + v)
+
+            d = np.zeros_like(x)
+            r = -g
+            p = r.copy()
+            rr = float(np.sum(r * r))
+            kappa = None
+            for _ in range(params.cg_iters):
+                Hp = H(p)
+                pp = float(np.sum(p * p))
+                if kappa is None:
+                    kappa = float(np.sum(p * Hp)) / pp if pp > 0 else 0.0
+                q = Hp + mu * kappa * p
+                pq = float(np.sum(p * q))
+                alpha = rr / pq if pq > 0 else 0.0
+                d = d + alpha * p
+                r = r - alpha * q
+                rr_new = float(np.sum(r * r))
+                p = r + (rr_new / rr if rr > 0 else 0.0) * p
+                rr = rr_new
+            xt = x + d
+            at = self.project(xt)
+            pair = (at, st.Rx[1]) if b == 0 else (st.Rx[0], at)
+            fh, fl, gh, gl = self.forward(*pair)
+            self.counts["f"] += 2  # both spectra, every ray
+            if data(fh, fl) + pen(xt) < phi:
+                st.x[b], st.Rx[b] = xt, at
+                st.fh, st.fl, st.gh, st.gl = fh, fl, gh, gl
+                mu /= 10.0
+            else:
+                mu *= 10.0
+        return st
+
+    def lmcg_iterate(self, st: LmcgState, mh, ml, wh, wl, params: Params,
+                     n_iters: int = 1) -> LmcgState:
+        """n_iters outer iterations: x_c (Eq. 7), then x_p with the new x_c (Eq. 8), y and z
+        (Eq. 9-10), u (Eq. 11 with C = [D; I]), then rho from the residuals."""
+        st = st.copy()
+        for _ in range(n_iters):
+            rho = st.rho.copy()
+            y_prev, z_prev = st.y.copy(), st.z.copy()
+            for b in range(2):
+                st = self._lm_basis(st, b, mh, ml, wh, wl, rho[b], params)
+            r_norm, s_norm = np.zeros(2), np.zeros(2)
+            for b in range(2):
+                Dx = D(st.x[b])
+                st.y[b] = shrink(Dx - st.uy[b], params.lam[b] / rho[b])
+                st.z[b] = np.maximum(0.0, st.x[b] - st.uz[b])
+                st.uy[b] += st.y[b] - Dx
+                st.uz[b] += st.z[b] - st.x[b]
+                r_norm[b] = np.sqrt(np.sum((st.y[b] - Dx) ** 2) + np.sum((st.z[b] - st.x[b]) ** 2))
+                if params.rho_mode == "adaptive":
+                    s_norm[b] = rho[b] * np.linalg.norm(DT(st.y[b] - y_prev[b]) + st.z[b] - z_prev[b])
+            new_rho = rho.copy()
+            if params.rho_mode == "adaptive":
+                for b in range(2):
+                    if r_norm[b] > params.bal_mu * s_norm[b]:
+                        new_rho[b] = rho[b] * params.bal_tau
+                    elif s_norm[b] > params.bal_mu * r_norm[b]:
+                        new_rho[b] = rho[b] / params.bal_tau
+            for b in range(2):
+                k = rho[b] / new_rho[b]
+                st.uy[b] *= k
+                st.uz[b] *= k
+            st.rho = new_rho
+            data = 0.5 * float(np.sum(wh * (st.fh - mh) ** 2) + np.sum(wl * (st.fl - ml) ** 2))
+            tv = sum(params.lam[b] * float(np.abs(st.y[b]).sum()) for b in range(2))
+            st.log.append(dict(it=st.it, rho=rho.copy(), r=r_norm.copy(), s=s_norm.copy(),
+                               data=data, tv=tv))
+            st.it += 1
+        return st
+
+
+@dataclass
+class LmcgState:
+    """State of the LM x CG scheme, per basis b: x, R x (the projection of the accepted x),
+    y, u^y, z, u^z, rho; f_h, f_l and their gradients [.., (c, p)] at R x."""
+    x: np.ndarray      # [2, ny, nx]
+    Rx: np.ndarray     # [2, V, D]
+    y: np.ndarray      # [2, 2, ny, nx]
+    uy: np.ndarray     # [2, 2, ny, nx]
+    z: np.ndarray      # [2, ny, nx]
+    uz: np.ndarray     # [2, ny, nx]
+    rho: np.ndarray    # [2]
+    fh: np.ndarray     # [V, D]
+    fl: np.ndarray     # [V, D]
+    gh: np.ndarray     # [V, D, 2]
+    gl: np.ndarray     # [V, D, 2]
+    it: int = 0
+    log: list = field(default_factory=list)
+
+    def copy(self):
+        return LmcgState(*(np.array(getattr(self, k)) for k in
+                           ("x", "Rx", "y", "uy", "z", "uz", "rho", "fh", "fl", "gh", "gl")),
+                         it=self.it, log=list(self.log))
