@@ -267,6 +267,43 @@ dect_status dect_admm_iterate(const dect_plan* plan, const void* m_h, const void
 dect_status dect_state_log(const dect_plan* plan, const void* state, int64_t first, int n,
                            dect_iter_log* log, void* stream);
 
+/* The baseline LM(m) x CG(n) splitting (Eqs. (7)-(8); Table 1 counts R 2m(n+1),
+ * R^T 2m(n+1) and f 4m per iteration).  One outer iteration: x_c by m
+ * Levenberg-Marquardt iterations on
+ *   Phi(x_c) = 1/2 ||f(R x_c, R x_p) - m||^2_Sigma + rho_c/2 ||[y_c; z_c] - [D; I] x_c + u_c||^2
+ * with x_p fixed, then x_p likewise with the new x_c.  Each LM iteration solves
+ * (R^T W R + rho (D^T D + I) + mu kappa I) d = -grad Phi by cg_iters CG steps from
+ * d = 0 (W = sum_s w_s (df_s/da)^2 per ray; kappa = g'Hg/g'g, the curvature along
+ * the gradient; mu starts at lm_mu0 for each basis, /10 on an accepted step, x10 on
+ * a rejected one: a step is accepted when Phi decreases).  f and its gradient at
+ * R x are kept per ray.  Then y, z, u as in Eqs. (9)-(11) with C = [D; I], and rho
+ * (DECT_RHO_FIXED or ADAPTIVE; the dual residual is rho ||D^T dy + dz||).
+ * The state is one caller-owned device buffer of dect_lmcg_state_bytes() bytes
+ * (256-byte aligned); images are planar per basis: x, z, u^z [2][ny][nx]; y, u^y
+ * [2][2][ny][nx] (basis, then horizontal/vertical difference); R x [2][n_views][n_det]. */
+typedef struct {
+    size_t bytes;
+    size_t x, y, uy, z, uz, Rx;
+    size_t scalars;
+} dect_lmcg_layout;
+
+size_t dect_lmcg_state_bytes(const dect_plan* plan);
+dect_status dect_lmcg_state_layout(const dect_plan* plan, dect_lmcg_layout* out);
+
+/* x = x0 (device [ny][nx][2] image pair, or NULL for 0), z = x, y = D x, u = 0,
+ * rho = (rho_c, rho_p), R x and f at R x.  lm_mu0 may be 0 (undamped Gauss-Newton);
+ * precond must be DECT_PRECOND_NONE.  async. */
+dect_status dect_lmcg_init(const dect_plan* plan, const void* m_h, const void* m_l,
+                           const void* w_h, const void* w_l, const void* x0, void* state,
+                           const dect_params* params, void* stream);
+
+/* n_iters outer iterations; log as for dect_admm_iterate (the data cost is at R x). */
+dect_status dect_lmcg_iterate(const dect_plan* plan, const void* m_h, const void* m_l,
+                              const void* w_h, const void* w_l, void* state,
+                              const dect_params* params, int n_iters, dect_iter_log* log,
+                              void* stream);
+
+
 /* ----------------------------------------------------------- autotuning --- */
 
 /* Workgroup shapes of the ADMM's transposed projector (waves of a workgroup

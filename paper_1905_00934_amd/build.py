@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "libdect.so")
 SOURCES = ["plan.cpp", "profile.cpp", "tomo.hip", "udm.hip", "admm.hip", "batch.cpp",
-           "server.cpp", "tune.cpp", "fft.hip", "fbp.hip"]
+           "server.cpp", "tune.cpp", "fft.hip", "fbp.hip", "lmcg.hip"]
 HEADERS = ["common.h", "fftcore.h", "kernels.h", "profile.h", "runner.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -281,6 +281,14 @@ template <typename T>
 hipError_t launch_iteration(const SliceJob<T>& one, const JobArrays<T>* dev, int n,
                             const dect_params* prm, long it, hipStream_t s);
 
+// f and its gradient of both spectra at (R x_c, R x_p) for the LM x CG scheme, with
+// `at` the basis' projection and `ao` the other one's; cache [6][M]; partials: data
+// cost and non-finite count per block of 256 rays.
+template <typename T>
+hipError_t launch_lm_eval(const dect_plan* p, int basis, const T* at, const T* ao, const T* mh,
+                          const T* ml, const T* wh, const T* wl, T* cache, double* partials,
+                          hipStream_t s);
+
 // Start of the iterations from an image pair x0: x = z = x0, y = D x0, R x = R x0 and
 // t = a - R x0 (the state already initialised with x = 0).
 template <typename T>

@@ -156,7 +156,7 @@ __device__ inline void lm_solve(const T* __restrict__ spec, int kmax, int kh, in
         }
         const T bound = (T)sb.kcmax * fabs(dc) + (T)sb.kpmax * fabs(dp);
         // A non-finite current value gives no usable shift either.
-        const bool exact = !(bound <= T(96)) || !(P.fh - P.fh == T(0)) || !(P.fl - P.fl == T(0));
+        const bool exact = !(bound <= T(96)) || !isfinite(P.fh) || !isfinite(P.fl);
         evaluate<T>(spec, kmax, kh, kl, mh, ml, wh, wl, vc, vp, rc, rp, -P.fh * log2e,
                     -P.fl * log2e, exact, Q);
         if (Q.phi < P.phi) {
@@ -275,12 +275,43 @@ __global__ __launch_bounds__(256) void k_udm(const UdmArgs<T>* __restrict__ dev,
             reinterpret_cast<V2*>(A.da)[l] = dn;
             const T rh = P.fh - mh, rl = P.fl - ml;
             part[2] = 0.5 * ((double)wh * (double)rh * (double)rh + (double)wl * (double)rl * (double)rl);
-            const bool finite = (P.ac - P.ac == T(0)) && (P.ap - P.ap == T(0)) &&
-                                (part[2] - part[2] == 0.0);
+            const bool finite = isfinite(P.ac) && isfinite(P.ap) && isfinite(part[2]);
             part[3] = finite ? 0.0 : 1.0;
         }
     }
     if constexpr (MODE == 2) block_sum_store<4>(part, A.partials + (size_t)blockIdx.x * kPartialSlots);
+}
+
+// f and its gradient of both spectra at (a_c, a_p) = (at, ao) (basis 0) or (ao, at)
+// (basis 1), for the LM x CG scheme: cache[k][M], k = (f_h, f_l, df_h/da_c,
+// df_h/da_p, df_l/da_c, df_l/da_p); block partials of 1/2 sum_s w_s (f_s - m_s)^2.
+template <typename T>
+__global__ __launch_bounds__(256) void k_lm_eval(const T* __restrict__ spec, int kmax, int kh,
+                                                 int kl, long M, int basis,
+                                                 const T* __restrict__ at,
+                                                 const T* __restrict__ ao, const T* __restrict__ mh,
+                                                 const T* __restrict__ ml, const T* __restrict__ wh,
+                                                 const T* __restrict__ wl, T* __restrict__ cache,
+                                                 double* __restrict__ partials) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if (i < M) {
+        Point<T> P;
+        P.ac = basis == 0 ? at[i] : ao[i];
+        P.ap = basis == 0 ? ao[i] : at[i];
+        evaluate<T>(spec, kmax, kh, kl, mh[i], ml[i], wh[i], wl[i], T(0), T(0), T(0), T(0), T(0),
+                    T(0), true, P);
+        cache[i] = P.fh;
+        cache[M + i] = P.fl;
+        cache[2 * M + i] = P.ghc;
+        cache[3 * M + i] = P.ghp;
+        cache[4 * M + i] = P.glc;
+        cache[5 * M + i] = P.glp;
+        const double eh = (double)P.fh - (double)mh[i], el = (double)P.fl - (double)ml[i];
+        v[0] = 0.5 * ((double)wh[i] * eh * eh + (double)wl[i] * el * el);
+        v[1] = (isfinite(P.fh) && isfinite(P.fl)) ? 0.0 : 1.0;
+    }
+    block_sum_store<4>(v, partials + (size_t)blockIdx.x * kPartialSlots);
 }
 
 template <typename T>
@@ -333,6 +364,17 @@ hipError_t launch_udm_batch(const UdmArgs<T>* args, int n, int blocks, hipStream
 }
 
 template <typename T>
+hipError_t launch_lm_eval(const dect_plan* p, int basis, const T* at, const T* ao, const T* mh,
+                          const T* ml, const T* wh, const T* wl, T* cache, double* partials,
+                          hipStream_t s) {
+    ProfScope ps("lm_eval", s);
+    hipLaunchKernelGGL((k_lm_eval<T>), dim3((unsigned)((p->M + 255) / 256)), dim3(256), 0, s,
+                       static_cast<const T*>(p->spec), p->kmax, p->kh, p->kl, p->M, basis, at, ao,
+                       mh, ml, wh, wl, cache, partials);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_ingest(const dect_plan* p, const void* ch, const void* cl, double i0h,
                          double i0l, void* mh, void* ml, void* wh, void* wl, hipStream_t s) {
     dim3 g((unsigned)((p->M + 255) / 256));
@@ -346,6 +388,12 @@ template void fill_udm_tables<float>(const dect_plan*, UdmArgs<float>&);
 template void fill_udm_tables<double>(const dect_plan*, UdmArgs<double>&);
 template hipError_t launch_udm<float>(const dect_plan*, int, const UdmArgs<float>&, hipStream_t);
 template hipError_t launch_udm<double>(const dect_plan*, int, const UdmArgs<double>&, hipStream_t);
+template hipError_t launch_lm_eval<float>(const dect_plan*, int, const float*, const float*,
+                                          const float*, const float*, const float*,
+                                          const float*, float*, double*, hipStream_t);
+template hipError_t launch_lm_eval<double>(const dect_plan*, int, const double*, const double*,
+                                           const double*, const double*, const double*,
+                                           const double*, double*, double*, hipStream_t);
 template hipError_t launch_udm_batch<float>(const UdmArgs<float>*, int, int, hipStream_t);
 template hipError_t launch_udm_batch<double>(const UdmArgs<double>*, int, int, hipStream_t);
 template hipError_t launch_ingest<float>(const dect_plan*, const void*, const void*, double, double,

@@ -74,6 +74,11 @@ class Layout(ctypes.Structure):
                 ("bytes", "x", "y", "uy", "z", "uz", "a", "ua", "Rx", "scalars")]
 
 
+class LmcgLayout(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_size_t) for k in
+                ("bytes", "x", "y", "uy", "z", "uz", "Rx", "scalars")]
+
+
 class Launch(ctypes.Structure):
     _fields_ = [("bp_waves", ctypes.c_int), ("proj_waves", ctypes.c_int),
                 ("bp_us", ctypes.c_double), ("proj_us", ctypes.c_double),
@@ -140,6 +145,11 @@ def lib():
             "dect_batch_groups": [vp],
             "dect_batch_destroy": [vp],
             "dect_precondition": [vp, vp, vp, vp],
+            "dect_lmcg_state_bytes": [vp],
+            "dect_lmcg_state_layout": [vp, ctypes.POINTER(LmcgLayout)],
+            "dect_lmcg_init": [vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(Params), vp],
+            "dect_lmcg_iterate": [vp, vp, vp, vp, vp, vp, ctypes.POINTER(Params), i,
+                                  ctypes.POINTER(IterLog), vp],
             "dect_cdm": [vp, vp, vp, vp, vp, i, vp, vp, vp],
             "dect_fbp": [vp, vp, vp, i, vp],
             "dect_cdm_fbp_start": [vp, vp, vp, vp, vp, i, vp, vp, vp, vp],
@@ -164,6 +174,7 @@ def lib():
         L.dect_server_destroy.restype = None
         L.dect_serve_footprint.restype = ctypes.c_size_t
         L.dect_state_bytes.restype = ctypes.c_size_t
+        L.dect_lmcg_state_bytes.restype = ctypes.c_size_t
         L.dect_last_error.restype = ctypes.c_char_p
         L.dect_last_error.argtypes = []
         _lib = L
@@ -278,6 +289,36 @@ class State:
         self.ua = view(L.ua, (V, D, 2))
         self.Rx = view(L.Rx, (V, D, 2))
         self.scalars = self.buf[L.scalars:L.scalars + 24 * 8].view(torch.float64)
+
+    @property
+    def ptr(self):
+        return ctypes.c_void_p(self.buf.data_ptr())
+
+
+class LmcgState:
+    """State of the LM x CG baseline: one device buffer; planar per-basis views."""
+
+    def __init__(self, plan: "Plan"):
+        L = LmcgLayout()
+        _check(lib().dect_lmcg_state_layout(plan.handle, ctypes.byref(L)))
+        self.layout = L
+        self.buf = torch.empty(L.bytes + 256, dtype=torch.uint8, device=plan.device)
+        off = (-self.buf.data_ptr()) % 256
+        self.buf = self.buf[off:off + L.bytes]
+        ny, nx, V, D = plan.ny, plan.nx, plan.V, plan.D
+
+        def view(o, shape):
+            n = 1
+            for s in shape:
+                n *= s
+            return self.buf[o:o + n * plan.elem].view(plan.dtype).view(*shape)
+
+        self.x = view(L.x, (2, ny, nx))
+        self.y = view(L.y, (2, 2, ny, nx))
+        self.uy = view(L.uy, (2, 2, ny, nx))
+        self.z = view(L.z, (2, ny, nx))
+        self.uz = view(L.uz, (2, ny, nx))
+        self.Rx = view(L.Rx, (2, V, D))
 
     @property
     def ptr(self):
@@ -440,6 +481,26 @@ class Plan:
         if not log:
             return None
         return _records(L, n_iters)
+
+    def new_lmcg_state(self) -> LmcgState:
+        return LmcgState(self)
+
+    def lmcg_init(self, meas, state: LmcgState, params: AdmmParams,
+                  x0: torch.Tensor | None = None):
+        """LM x CG start: x = x0 [ny, nx, 2] (or 0), z = x, y = D x, u = 0."""
+        P, keep = params.c_struct()
+        if x0 is not None:
+            self._chk(x0, (self.ny, self.nx, 2), "x0")
+        _check(lib().dect_lmcg_init(self.handle, *(_ptr(m) for m in meas), _ptr(x0), state.ptr,
+                                    ctypes.byref(P), _stream()))
+
+    def lmcg_iterate(self, meas, state: LmcgState, params: AdmmParams, n_iters: int,
+                     log: bool = False):
+        P, keep = params.c_struct()
+        L = (IterLog * max(n_iters, 1))() if log else None
+        _check(lib().dect_lmcg_iterate(self.handle, *(_ptr(m) for m in meas), state.ptr,
+                                       ctypes.byref(P), int(n_iters), L, _stream()))
+        return _records(L, n_iters) if log else None
 
     def state_log(self, state: State, first: int, n: int):
         """Log records of iterations [first, first + n) of a state (synchronises)."""
