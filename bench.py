@@ -385,6 +385,40 @@ def main():
                "pcg_from_cdm_fbp": {"xi_c_db": round(sxi[0], 3), "xi_p_db": round(sxi[1], 3),
                                     "iterations": n_same, "rho": slog[-1]["rho"]}}
 
+    # LM1xCG1: the baseline splitting of Eqs. (7)-(8) on the same slice, same rho rule,
+    # timed over the same number of iterations; operator launches counted per iteration.
+    lparams = dect.AdmmParams()
+    lst = plan.new_lmcg_state()
+    plan.lmcg_init(meas, lst, lparams)
+    plan.lmcg_iterate(meas, lst, lparams, args.warmup)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    plan.lmcg_iterate(meas, lst, lparams, args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    lms = e0.elapsed_time(e1) / args.steps
+    dect.profile_start()
+    plan.lmcg_iterate(meas, lst, lparams, args.steps)
+    lkt = dect.profile_stop()
+    llog = plan.lmcg_iterate(meas, lst, lparams, 1, log=True)
+    lx = lst.x.double().cpu().numpy()
+    lxi = [20 * math.log10(np.linalg.norm(lx[b] - pr.x_true[b]) / np.linalg.norm(pr.x_true[b]))
+           for b in range(2)]
+    per = lambda k: lkt[k][1] / args.steps if k in lkt else 0.0
+    avg = lambda k: round(1e3 * lkt[k][0] / lkt[k][1], 2) if k in lkt else None
+    lmcg = {"method": "LM1xCG1 (Eqs. (7)-(8): x_c then x_p by 1 LM iteration each, its "
+                      "Gauss-Newton system by 1 CG step with single-channel R and R^T)",
+            "value": round(1e3 / lms, 3), "unit": "iter/s", "ms_per_step": round(lms, 4),
+            "udm1_cg1_speedup": round(lms / ms_per_step, 3),
+            "operators_per_iter": {"R": per("project"), "RT": per("backproject"),
+                                   "f_per_ray": 2 * per("lm_eval")},
+            "table1": {"R": 4, "RT": 4, "f": 4},
+            "kernel_us": {"project": avg("project"), "backproject": avg("backproject"),
+                          "lm_eval": avg("lm_eval")},
+            "accuracy": {"xi_c_db": round(lxi[0], 3), "xi_p_db": round(lxi[1], 3),
+                         "iterations": args.warmup + 2 * args.steps + 1,
+                         "rho": llog[-1]["rho"]}}
+
     info = plan.info()
     N, M = info["n_pixels"], info["n_rays"]
     # Algorithmic VALU operations of one two-channel R or R^T application: per Joseph
@@ -444,6 +478,7 @@ def main():
         "wall_s": round(wall, 4),
         "pcg": pcg,
         "cdm_fbp": cdm_fbp,
+        "lmcg": lmcg,
     }
     if batch_items:
         params_b = dect.AdmmParams()
