@@ -358,6 +358,123 @@ __device__ inline void gather_orbit_staged(const BpArgs<T>& a, int wave, int lan
     }
 }
 
+// gather_orbit_staged with a 32-bin window for the quarter-turn symmetric fan: a
+// block's candidates span about 8 sqrt(2) pixels times the magnification
+// |d beta / d pixel| plus the footprint, ~14 bins at the centre of the fan and up to
+// ~35 for blocks near the source, so 16 bins left most waves loading some
+// candidates directly; with 32 that is rare.
+
+// Each lane stages WIN * SYM / 64 records.
+template <typename T, int CH, int SYM, int VS>
+__device__ inline void gather_orbit_staged_wide(const BpArgs<T>& a, int wave, int lane, int i, int j,
+                                           bool inside, T (&acc)[SYM][CH]) {
+    constexpr int WIN = 32;
+    constexpr int REC = WIN * SYM;
+    constexpr int PER = (REC + 63) / 64;
+    static_assert(WIN % 16 == 0 && (REC <= 64 || REC % 64 == 0), "window layout");
+    using Q = vec<T, SYM * CH>;
+    __shared__ RayParam<T> s_ray[VS][REC];
+    __shared__ Q s_sino[VS][REC];
+    const T m = (T)a.margin;
+    const int D = a.D, Vb = a.Vb, n = a.nx;
+    const T cx = T(0.5) * (T)(a.nx - 1), cy = T(0.5) * (T)(a.ny - 1);
+    const Q* __restrict__ sino = reinterpret_cast<const Q*>(a.sino);
+    // Record lane + 64 q of the window is bin (rec % WIN) of orbit member rec / WIN,
+    // centred on the detector coordinate of the block centre seen as that member.
+    T ipc[PER], jpc[PER];
+    int sk[PER];
+    bool stager[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int rec = lane + 64 * q;
+        stager[q] = rec < REC;
+        sk[q] = rec % WIN;
+        T icm, jcm;
+        rotf<T>(rec / WIN, n, (T)(blockIdx.x * 8) + T(3.5), (T)(blockIdx.y * 8) + T(3.5), icm, jcm);
+        ipc[q] = icm - cx;
+        jpc[q] = jcm - cy;
+    }
+    RayParam<T> pr[PER];
+    Q pq[PER];
+    int pL[PER];
+    auto stage = [&](int v) {
+        const ViewParam<T> w = a.views[v];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const T bq = (w.ni * ipc[q] + w.nj * jpc[q]) / (w.d0 + w.di * ipc[q] + w.dj * jpc[q]);
+            pL[q] = (int)floor(bq + w.boff) - (WIN / 2 - 1);
+            const int b = pL[q] + sk[q];
+            if (stager[q] && b >= 0 && b < D) {
+                pr[q] = a.rays[(size_t)v * D + b];
+                pq[q] = sino[(size_t)v * D + b];
+            } else {
+                pr[q] = RayParam<T>{};
+#pragma unroll
+                for (int c = 0; c < SYM * CH; ++c) pq[q].v[c] = T(0);
+            }
+        }
+    };
+    if (wave < Vb) stage(wave);
+    for (int v = wave; v < Vb; v += VS) {
+        int L[SYM];
+#pragma unroll
+        for (int mm = 0; mm < SYM; ++mm)
+            L[mm] = __builtin_amdgcn_readlane(pL[(mm * WIN) / 64], (mm * WIN) % 64);
+#pragma unroll
+        for (int q = 0; q < PER; ++q)
+            if (stager[q]) {
+                s_ray[wave][lane + 64 * q] = pr[q];
+                s_sino[wave][lane + 64 * q] = pq[q];
+            }
+        // LDS operations of one wave complete in order; the barrier only keeps the
+        // compiler from moving the reads above the writes.
+        __builtin_amdgcn_wave_barrier();
+        if (v + VS < Vb) stage(v + VS);
+        if (inside) {
+            const ViewParam<T> w = a.views[v];
+            const RayParam<T>* __restrict__ rv = a.rays + (size_t)v * D;
+            const Q* __restrict__ sq = sino + (size_t)v * D;
+#pragma unroll
+            for (int mm = 0; mm < SYM; ++mm) {
+                int im, jm;
+                rot(mm, n, i, j, im, jm);
+                const T fi = (T)im, fj = (T)jm;
+                const T ip = fi - cx, jp = fj - cy;
+                const T inv = fast_rcp<T>(w.d0 + w.di * ip + w.dj * jp);
+                const T bq = (w.ni * ip + w.nj * jp) * inv;
+                const T bc = bq + w.boff;
+                const T dby = (w.nj - bq * w.dj) * inv;
+                const T dbx = (w.ni - bq * w.di) * inv;
+                const T h = fmax(fabs(dby), fabs(dbx)) + m;
+                const int lo0 = (int)ceil(fmax(bc - h, T(-1)));
+                const int hi0 = (int)floor(fmin(bc + h, T(D)));
+                const int lo = lo0 > 0 ? lo0 : 0, hi = hi0 < D - 1 ? hi0 : D - 1;
+                for (int b = lo; b <= hi; ++b) {
+                    const int idx = b - L[mm];
+                    RayParam<T> r;
+                    Q s;
+                    if ((unsigned)idx < (unsigned)WIN) {
+                        r = s_ray[wave][mm * WIN + idx];
+                        s = s_sino[wave][mm * WIN + idx];
+                    } else {
+                        r = rv[b];
+                        s = sq[b];
+                    }
+                    const bool xs = r.pad == T(0);
+                    const T phi = fma(r.slope, xs ? fi : fj, r.phi0);
+                    const T wt = fmax(T(0), fma(-r.step, fabs(phi - (xs ? fj : fi)), r.step));
+#pragma unroll
+                    for (int kp = 0; kp < SYM; ++kp)
+#pragma unroll
+                        for (int c = 0; c < CH; ++c)
+                            acc[(mm + kp) % SYM][c] += wt * s.v[kp * CH + c];
+                }
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
 // Image-side terms added to R^T at pixel (i, j) for the ADMM epilogues (CH = 2).
 // Adds the per-channel partial sums of the finished values to part.
 template <typename T, int EPI>
@@ -458,7 +575,9 @@ __global__ __launch_bounds__(64 * VS) void k_backproject(const BpArgs<T>* __rest
     for (int k = 0; k < SYM; ++k)
 #pragma unroll
         for (int c = 0; c < CH; ++c) acc[k][c] = T(0);
-    if constexpr (QUAD)
+    if constexpr (QUAD && SYM == 4)
+        gather_orbit_staged_wide<T, CH, SYM, VS>(a, wave, lane, i, j, inside, acc);
+    else if constexpr (QUAD)
         gather_orbit_staged<T, CH, SYM, VS>(a, wave, lane, i, j, inside, acc);
     else if (inside)
         gather_orbit<T, CH, SYM, VS>(a, wave, i, j, acc);
