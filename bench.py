@@ -110,6 +110,9 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device-to-device copy (reference for "
                          "hardware byte counters)")
+    ap.add_argument("--launch", default=None, metavar="BP,PJ",
+                    help="fix the waves per workgroup of the transpose and the projector "
+                         "(2, 4 or 8) instead of tuning them, e.g. for counter passes")
     return ap.parse_args()
 
 
@@ -296,7 +299,14 @@ def main():
     torch.cuda.set_device(dev)
     pr = synth.slice_problem(0, with_image=True)
     plan = dect.Plan(pr.geom, pr.spec, torch.float32, device=dev)
-    tuned = plan.tune()
+    if args.launch:
+        bpw, pjw = (int(v) for v in args.launch.split(","))
+        plan.set_launch(bpw, pjw)
+        tuned = {"bp_waves": bpw, "proj_waves": pjw}
+        tuned_by = "fixed by --launch"
+    else:
+        tuned = plan.tune()
+        tuned_by = "dect_plan_tune (timed on this device)"
     counts = [torch.from_numpy(c).to(dev, torch.float32) for c in (pr.counts_high, pr.counts_low)]
     meas = list(plan.ingest(counts[0], counts[1], pr.i0))
     params = dect.AdmmParams()
@@ -470,7 +480,7 @@ def main():
                    "lm_iters": 1, "cg_iters": 1},
         "roofline": roofline,
         "launch": {"bp_waves": tuned["bp_waves"], "proj_waves": tuned["proj_waves"],
-                   "tuned_by": "dect_plan_tune (timed on this device)"},
+                   "tuned_by": tuned_by},
         "kernels": per_kernel,
         "accuracy": {"xi_c_db": round(xi[0], 3), "xi_p_db": round(xi[1], 3),
                      "iterations": args.warmup + 2 * args.steps + 1,
