@@ -107,7 +107,9 @@ dect_status dect_project(const dect_plan* plan, const void* img, void* sino, int
 /* R^T, the exact transpose of dect_project (same weights, gathered per pixel,
  * no atomics): img[j][i][c] = sum over rays of weight * sino[v][b][c].
  * sino: device [n_views][n_det][ch]; img: device [ny][nx][ch] (overwritten);
- * ch in {1, 2, 4}.  async. */
+ * ch in {1, 2, 4}.  async.  On a quarter-turn symmetric plan one or two channels
+ * are first reordered into a plan-owned scratch sinogram, so calls with one plan
+ * must not run concurrently on different streams. */
 dect_status dect_backproject(const dect_plan* plan, const void* sino, void* img, int ch,
                              void* stream);
 

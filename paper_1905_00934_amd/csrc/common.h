@@ -99,6 +99,7 @@ struct dect_plan {
     // plan-owned scratch: orbit images of the image being projected (up to 4 channels)
     void* scratch_O = nullptr;   // T[N * 4 * sym]
     void* scratch_OT = nullptr;  // T[N * 4 * sym]
+    void* scratch_sq = nullptr;  // sym == 4: T[Vb][D][4][2], a sinogram as quad records
     // preconditioner of the x-update (ramp filter on a zero-padded FFT grid of
     // px x py = 2^lpx x 2^lpy; absent when a padded side exceeds kMaxFft)
     bool has_precond = false;

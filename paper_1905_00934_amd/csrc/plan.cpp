@@ -176,6 +176,7 @@ dect_status build_tables(dect_plan* p, const dect_spectra* spec) {
     if (st) return st;
     DECT_HIP(hipMalloc(&p->scratch_O, (size_t)p->N * 4 * p->sym * sizeof(T)));
     DECT_HIP(hipMalloc(&p->scratch_OT, (size_t)p->N * 4 * p->sym * sizeof(T)));
+    if (p->sym == 4) DECT_HIP(hipMalloc(&p->scratch_sq, (size_t)p->M * 2 * sizeof(T)));
     return DECT_OK;
 }
 
@@ -452,6 +453,7 @@ void dect_plan_destroy(dect_plan* p) {
     (void)hipFree(p->spec);
     (void)hipFree(p->scratch_O);
     (void)hipFree(p->scratch_OT);
+    (void)hipFree(p->scratch_sq);
     (void)hipFree(p->pre_filter);
     (void)hipFree(p->pre_twx);
     (void)hipFree(p->pre_twy);

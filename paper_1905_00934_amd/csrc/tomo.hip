@@ -655,6 +655,46 @@ hipError_t project_t(const OrbitArgs<T>* odev, const OrbitArgs<T>& oone,
     return hipGetLastError();
 }
 
+// A standard [V][D][CH] sinogram as quad records [Vb][D][4][CH] (view v + k Vb is
+// rotation k of base view v), the layout the staged transpose reads.
+template <typename T, int CH>
+__global__ __launch_bounds__(256) void k_quad_records(const T* __restrict__ sino, int Vb, int D,
+                                                      T* __restrict__ quad) {
+    const long r = (long)blockIdx.x * blockDim.x + threadIdx.x;  // (vb, b, k)
+    if (r >= (long)Vb * D * 4) return;
+    const int k = (int)(r & 3);
+    const long vb_b = r >> 2;
+    const int vb = (int)(vb_b / D), b = (int)(vb_b % D);
+    const T* src = sino + ((size_t)(vb + k * Vb) * D + b) * CH;
+#pragma unroll
+    for (int c = 0; c < CH; ++c) quad[r * CH + c] = src[c];
+}
+
+// R^T of one or two channels on a quarter-turn symmetric plan: the sinogram is
+// reordered into quad records in the plan's scratch and gathered by the staged
+// transpose with `waves` waves per workgroup.
+template <typename T, int CH, int VS>
+hipError_t bp_quad_plain(const BpArgs<T>& one, T* quad, hipStream_t s) {
+    const long recs = (long)one.Vb * one.D * 4;
+    hipLaunchKernelGGL((k_quad_records<T, CH>), dim3((unsigned)((recs + 255) / 256)), dim3(256),
+                       0, s, one.sino, one.Vb, one.D, quad);
+    BpArgs<T> a = one;
+    a.sino = quad;
+    hipLaunchKernelGGL((k_backproject<T, CH, 4, true, EPI_NONE, VS, false>), dim3(a.gx, a.gy),
+                       dim3(64 * VS), 0, s, nullptr, a);
+    return hipGetLastError();
+}
+
+template <typename T, int CH>
+hipError_t bp_quad_plain_w(int waves, const BpArgs<T>& one, T* quad, hipStream_t s) {
+    switch (waves) {
+        case 2: return bp_quad_plain<T, CH, 2>(one, quad, s);
+        case 4: return bp_quad_plain<T, CH, 4>(one, quad, s);
+        case 8: return bp_quad_plain<T, CH, 8>(one, quad, s);
+    }
+    return hipErrorInvalidValue;
+}
+
 template <typename T, int CH, int SYM>
 hipError_t bp_plain(const BpArgs<T>& one, hipStream_t s) {
     hipLaunchKernelGGL((k_backproject<T, CH, SYM, false, EPI_NONE, kViewSplit, false>),
@@ -776,9 +816,10 @@ hipError_t launch_backproject(const dect_plan* p, int ch, const BpArgs<T>& a0, h
     fill_bp_plan<T>(p, a);
     ProfScope ps(bp_name(EPI_NONE), s);
     if (p->sym == 4) {
+        T* quad = static_cast<T*>(p->scratch_sq);
         switch (ch) {
-            case 1: return bp_plain<T, 1, 4>(a, s);
-            case 2: return bp_plain<T, 2, 4>(a, s);
+            case 1: return bp_quad_plain_w<T, 1>(p->bp_waves, a, quad, s);
+            case 2: return bp_quad_plain_w<T, 2>(p->bp_waves, a, quad, s);
             case 4: return bp_plain<T, 4, 4>(a, s);
         }
     } else {
