@@ -51,6 +51,14 @@ struct alignas(sizeof(T) * 4) RayParam {
     T phi0, slope, step, pad;
 };
 
+// A ray as the transpose weighs it: the signed minor-axis distance from the sample
+// to the pixel (i, j) is d = phi0 + ci i + cj j (x-stepped: ci = slope, cj = -1;
+// y-stepped: ci = -1, cj = slope), and the weight is step max(0, 1 - |d|).
+template <typename T>
+struct alignas(sizeof(T) * 4) BpRay {
+    T phi0, ci, cj, step;
+};
+
 // Per-view data for the pixel-driven transpose.  The detector coordinate (in
 // bins) of the ray through the point with centred pixel coordinates (i', j') is
 //   beta = (ni i' + nj j') / (d0 + di i' + dj j') + boff
@@ -92,6 +100,7 @@ struct dect_plan {
     // device tables
     void* rays = nullptr;   // RayParam<T>[Vb * D]
     void* views = nullptr;  // ViewParam<T>[Vb]
+    void* bp_rays = nullptr;  // BpRay<T>[Vb * D]: the transpose's form of the rays
     void* spec = nullptr;   // T[6 * Kmax]: lw_h, kc_h, kp_h, lw_l, kc_l, kp_l
     int kh = 0, kl = 0, kmax = 0;
     double kc_max = 0.0, kp_max = 0.0;  // largest f_KN, f_p times log2(e) over used bins

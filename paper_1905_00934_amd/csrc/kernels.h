@@ -55,6 +55,7 @@ struct ProjArgs {
 template <typename T>
 struct BpArgs {
     const RayParam<T>* rays;
+    const BpRay<T>* brays;
     const ViewParam<T>* views;
     int nx, ny, V, Vb, D;
     int gx, gy;   // this slice's grid of 8x8 orbit blocks

@@ -139,6 +139,14 @@ dect_status build_tables(dect_plan* p, const dect_spectra* spec) {
     }
     dect_status st = upload<T>(rays.data(), rays.size() * sizeof(rays[0]), &p->rays);
     if (st) return st;
+    std::vector<BpRay<T>> brays(rays.size());
+    for (size_t k = 0; k < rays.size(); ++k) {
+        const RayParam<T>& r = rays[k];
+        const bool xs = r.pad == T(0);
+        brays[k] = BpRay<T>{r.phi0, xs ? r.slope : T(-1), xs ? T(-1) : r.slope, r.step};
+    }
+    st = upload<T>(brays.data(), brays.size() * sizeof(brays[0]), &p->bp_rays);
+    if (st) return st;
     st = upload<T>(views.data(), views.size() * sizeof(views[0]), &p->views);
     if (st) return st;
 
@@ -450,6 +458,7 @@ void dect_plan_destroy(dect_plan* p) {
     if (!p) return;
     (void)hipFree(p->rays);
     (void)hipFree(p->views);
+    (void)hipFree(p->bp_rays);
     (void)hipFree(p->spec);
     (void)hipFree(p->scratch_O);
     (void)hipFree(p->scratch_OT);

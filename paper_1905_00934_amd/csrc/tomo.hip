@@ -373,7 +373,7 @@ __device__ inline void gather_orbit_staged_wide(const BpArgs<T>& a, int wave, in
     constexpr int PER = (REC + 63) / 64;
     static_assert(WIN % 16 == 0 && (REC <= 64 || REC % 64 == 0), "window layout");
     using Q = vec<T, SYM * CH>;
-    __shared__ RayParam<T> s_ray[VS][REC];
+    __shared__ BpRay<T> s_ray[VS][REC];
     __shared__ Q s_sino[VS][REC];
     const T m = (T)a.margin;
     const int D = a.D, Vb = a.Vb, n = a.nx;
@@ -394,7 +394,7 @@ __device__ inline void gather_orbit_staged_wide(const BpArgs<T>& a, int wave, in
         ipc[q] = icm - cx;
         jpc[q] = jcm - cy;
     }
-    RayParam<T> pr[PER];
+    BpRay<T> pr[PER];
     Q pq[PER];
     int pL[PER];
     auto stage = [&](int v) {
@@ -405,10 +405,10 @@ __device__ inline void gather_orbit_staged_wide(const BpArgs<T>& a, int wave, in
             pL[q] = (int)floor(bq + w.boff) - (WIN / 2 - 1);
             const int b = pL[q] + sk[q];
             if (stager[q] && b >= 0 && b < D) {
-                pr[q] = a.rays[(size_t)v * D + b];
+                pr[q] = a.brays[(size_t)v * D + b];
                 pq[q] = sino[(size_t)v * D + b];
             } else {
-                pr[q] = RayParam<T>{};
+                pr[q] = BpRay<T>{};
 #pragma unroll
                 for (int c = 0; c < SYM * CH; ++c) pq[q].v[c] = T(0);
             }
@@ -432,7 +432,7 @@ __device__ inline void gather_orbit_staged_wide(const BpArgs<T>& a, int wave, in
         if (v + VS < Vb) stage(v + VS);
         if (inside) {
             const ViewParam<T> w = a.views[v];
-            const RayParam<T>* __restrict__ rv = a.rays + (size_t)v * D;
+            const BpRay<T>* __restrict__ rv = a.brays + (size_t)v * D;
             const Q* __restrict__ sq = sino + (size_t)v * D;
 #pragma unroll
             for (int mm = 0; mm < SYM; ++mm) {
@@ -451,7 +451,7 @@ __device__ inline void gather_orbit_staged_wide(const BpArgs<T>& a, int wave, in
                 const int lo = lo0 > 0 ? lo0 : 0, hi = hi0 < D - 1 ? hi0 : D - 1;
                 for (int b = lo; b <= hi; ++b) {
                     const int idx = b - L[mm];
-                    RayParam<T> r;
+                    BpRay<T> r;
                     Q s;
                     if ((unsigned)idx < (unsigned)WIN) {
                         r = s_ray[wave][mm * WIN + idx];
@@ -460,9 +460,8 @@ __device__ inline void gather_orbit_staged_wide(const BpArgs<T>& a, int wave, in
                         r = rv[b];
                         s = sq[b];
                     }
-                    const bool xs = r.pad == T(0);
-                    const T phi = fma(r.slope, xs ? fi : fj, r.phi0);
-                    const T wt = fmax(T(0), fma(-r.step, fabs(phi - (xs ? fj : fi)), r.step));
+                    const T d = fma(r.ci, fi, fma(r.cj, fj, r.phi0));
+                    const T wt = fmax(T(0), fma(-r.step, fabs(d), r.step));
 #pragma unroll
                     for (int kp = 0; kp < SYM; ++kp)
 #pragma unroll
@@ -765,6 +764,7 @@ const char* bp_name(int epi) {
 template <typename T>
 void fill_bp_plan(const dect_plan* p, BpArgs<T>& a) {
     a.rays = static_cast<const RayParam<T>*>(p->rays);
+    a.brays = static_cast<const BpRay<T>*>(p->bp_rays);
     a.views = static_cast<const ViewParam<T>*>(p->views);
     a.nx = p->nx;
     a.ny = p->ny;
