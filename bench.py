@@ -75,6 +75,49 @@ def algorithmic_bytes(N: int, M: int, cg_iters: int, elem: int = 4) -> dict:
     }.items()}
 
 
+def table1_workload(dect, torch, plan, meas, steps: int = 3) -> list:
+    """Operator applications per outer iteration of both schemes for several (m, n),
+    counted from the launches the library records, beside Table 1's formulas, and the
+    time per iteration on the same slice.  A two-channel launch applies R (or R^T) to
+    both bases, so it counts as two; the dual residual's R^T is listed separately
+    (Table 1 does not count it)."""
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    rows = []
+    for m, n in ((1, 1), (1, 2), (2, 1), (3, 4)):
+        prm = dect.AdmmParams(lm_iters=m, cg_iters=n)
+        for scheme in ("UDM-CG", "LMxCG"):
+            if scheme == "UDM-CG":
+                st = plan.new_state()
+                plan.admm_init(meas, st, prm)
+                run = lambda k: plan.admm_iterate(meas, st, prm, k)
+            else:
+                st = plan.new_lmcg_state()
+                plan.lmcg_init(meas, st, prm)
+                run = lambda k: plan.lmcg_iterate(meas, st, prm, k)
+            run(1)
+            torch.cuda.synchronize()
+            e0.record()
+            run(steps)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            dect.profile_start()
+            run(steps)
+            kt = dect.profile_stop()
+            cnt = lambda k: kt[k][1] / steps if k in kt else 0.0
+            if scheme == "UDM-CG":
+                got = {"R": 2 * cnt("project"),
+                       "RT": 2 * (cnt("backproject_rhs") + cnt("backproject_q")),
+                       "RT_dual": 2 * cnt("backproject_dual")}
+                want = {"R": 2 * n, "RT": 2 * (n + 1)}
+            else:
+                got = {"R": cnt("project"), "RT": cnt("backproject"), "RT_dual": 0.0}
+                want = {"R": 2 * m * (n + 1), "RT": 2 * m * (n + 1)}
+            rows.append({"scheme": scheme, "m": m, "n": n, "measured": got, "table1": want,
+                         "ms_per_iter": round(ms, 4)})
+    return rows
+
+
 def _gen(job):
     """Counts of one synthetic slice (runs in a worker process)."""
     from paper_1905_00934_amd import synth
@@ -429,6 +472,8 @@ def main():
                          "iterations": args.warmup + 2 * args.steps + 1,
                          "rho": llog[-1]["rho"]}}
 
+    table1 = table1_workload(dect, torch, plan, meas)
+
     info = plan.info()
     N, M = info["n_pixels"], info["n_rays"]
     # Algorithmic VALU operations of one two-channel R or R^T application: per Joseph
@@ -489,6 +534,7 @@ def main():
         "pcg": pcg,
         "cdm_fbp": cdm_fbp,
         "lmcg": lmcg,
+        "table1": table1,
     }
     if batch_items:
         params_b = dect.AdmmParams()
