@@ -371,8 +371,8 @@ SliceJob<T> make_job(const dect_plan* p, const void* mh, const void* ml, const v
     J.sym = p->sym;
     J.bp_waves = p->bp_waves;
     J.pj_waves = p->pj_waves;
-    J.pj_gx = (p->D + 63) / 64;
-    J.pj_gy = p->Vb;
+    J.pj_gx = proj_grid_x(p->D);
+    J.pj_gy = proj_grid_y(p->Vb);
     J.orb = OrbitArgs<T>{pp, pO, pOT, p->nx, p->ny};
     J.prj = ProjArgs<T>{static_cast<const RayParam<T>*>(p->rays), pO, pOT, Rp, p->nx, p->ny,
                         p->Vb, p->D};

@@ -89,6 +89,19 @@ __device__ inline void block_sum_store(double (&v)[K], double* out) {
         for (int k = 0; k < K; ++k) out[k] = (sh[0][k] + sh[1][k]) + (sh[2][k] + sh[3][k]);
 }
 
+// Projector workgroups: 64 / kProjViews consecutive bins of kProjViews consecutive
+// base views (lane = bin * kProjViews + view), so the lanes of a wave read nearby
+// image rows at every step.
+#ifndef DECT_PJ_VIEWS
+#define DECT_PJ_VIEWS 8
+#endif
+constexpr int kProjViews = DECT_PJ_VIEWS;
+static_assert(kProjViews == 1 || kProjViews == 2 || kProjViews == 4 || kProjViews == 8 ||
+                  kProjViews == 16 || kProjViews == 32,
+              "projector views per wave");
+inline int proj_grid_x(int D) { return (D + 64 / kProjViews - 1) / (64 / kProjViews); }
+inline int proj_grid_y(int Vb) { return (Vb + kProjViews - 1) / kProjViews; }
+
 template <typename T>
 hipError_t launch_project(const dect_plan* p, const void* img, void* sino, int ch, hipStream_t s);
 // Two-channel projection of the ADMM direction into quad-interleaved records, for

@@ -74,9 +74,10 @@ __global__ __launch_bounds__(256) void k_orbit(const OrbitArgs<T>* __restrict__ 
 
 // R for base rays: QUAD = true writes [Vb][D][SYM][CH] records, false writes the
 // standard [V][D][CH] layout (view v + k*Vb for rotation k).  A workgroup owns
-// 64 consecutive bins of one base view; its KS waves step through KS disjoint
-// ranges of image lines (so the lanes of a wave read one image line together)
-// and wave 0 adds the KS partial sums in order.
+// 64 / kProjViews consecutive bins of kProjViews consecutive base views (one ray
+// per lane); its KS waves step through KS disjoint ranges of image lines (so the
+// lanes of a wave read one image line together) and wave 0 adds the KS partial
+// sums in order.
 template <typename T, int CH, int SYM, bool QUAD, int KS, bool BATCH>
 __global__ __launch_bounds__(64 * KS) void k_project(const ProjArgs<T>* __restrict__ dev,
                                                      ProjArgs<T> one) {
@@ -84,17 +85,18 @@ __global__ __launch_bounds__(64 * KS) void k_project(const ProjArgs<T>* __restri
     __shared__ T red[KS > 1 ? KS - 1 : 1][64][W];
     const ProjArgs<T> A = pick_args<BATCH>(dev, one);
     const int nx = A.nx, ny = A.ny, Vb = A.Vb, D = A.D;
-    if ((int)blockIdx.x * 64 >= D || (int)blockIdx.y >= Vb) return;  // beyond this slice
+    constexpr int BV = kProjViews, BB = 64 / kProjViews;
+    if ((int)blockIdx.x * BB >= D || (int)blockIdx.y * BV >= Vb) return;  // beyond this slice
     const RayParam<T>* __restrict__ rays = A.rays;
     const vec<T, W>* __restrict__ O = reinterpret_cast<const vec<T, W>*>(A.O);
     const vec<T, W>* __restrict__ OT = reinterpret_cast<const vec<T, W>*>(A.OT);
     T* __restrict__ sino = A.sino;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int v = blockIdx.y;
-    const int b = blockIdx.x * 64 + lane;
-    const bool valid = b < D;
-    RayParam<T> r = rays[(size_t)v * D + (valid ? b : D - 1)];
+    const int v = blockIdx.y * BV + lane % BV;
+    const int b = blockIdx.x * BB + lane / BV;
+    const bool valid = b < D && v < Vb;
+    RayParam<T> r = rays[(size_t)(v < Vb ? v : Vb - 1) * D + (b < D ? b : D - 1)];
     const bool xs = r.pad == T(0);
     const int n_steps = xs ? nx : ny;   // samples along the ray
     const int n_lines = xs ? ny : nx;   // interpolation axis
@@ -784,7 +786,7 @@ hipError_t launch_project(const dect_plan* p, const void* img, void* sino, int c
     ProjArgs<T> q{static_cast<const RayParam<T>*>(p->rays), static_cast<const T*>(p->scratch_O),
                   static_cast<const T*>(p->scratch_OT), static_cast<T*>(sino), p->nx, p->ny,
                   p->Vb, p->D};
-    const int gx = (p->D + 63) / 64, gy = p->Vb;
+    const int gx = proj_grid_x(p->D), gy = proj_grid_y(p->Vb);
     if (p->sym == 4) {
         switch (ch) {
             case 1: return project_t<T, 1, 4, false, kLineSplit>(nullptr, o, nullptr, q, 1, p->N, gx, gy, s);
