@@ -403,7 +403,10 @@ __device__ inline void gather_orbit_staged_wide(const BpArgs<T>& a, int wave, in
         const ViewParam<T> w = a.views[v];
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
-            const T bq = (w.ni * ipc[q] + w.nj * jpc[q]) / (w.d0 + w.di * ipc[q] + w.dj * jpc[q]);
+            // Only the window's placement depends on this value (candidates outside
+            // it are loaded directly), so the hardware reciprocal is accurate enough.
+            const T bq = (w.ni * ipc[q] + w.nj * jpc[q]) *
+                         fast_rcp<T>(w.d0 + w.di * ipc[q] + w.dj * jpc[q]);
             pL[q] = (int)floor(bq + w.boff) - (WIN / 2 - 1);
             const int b = pL[q] + sk[q];
             if (stager[q] && b >= 0 && b < D) {
