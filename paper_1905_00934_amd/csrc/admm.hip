@@ -13,6 +13,7 @@
 #include <cstring>
 
 #include "common.h"
+#include "epilogue.h"
 #include "kernels.h"
 #include "profile.h"
 
@@ -53,6 +54,10 @@ __global__ __launch_bounds__(256) void k_cg_step(const VecArgs<T>* __restrict__ 
 #pragma unroll
         for (int c = 0; c < 2; ++c) xv.v[c] += al[c] * pv.v[c];
         reinterpret_cast<V2*>(A.x)[i] = xv;
+        // R x moves by alpha R p, so the tracked R^T (a - R x) by -alpha R^T R p.
+        const V2 rr = reinterpret_cast<const V2*>(A.rtrp)[i];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) A.h[2 * i + c] -= A.scal[S_ALPHA + c] * (double)rr.v[c];
         if constexpr (FULL) {
             V2 rv = reinterpret_cast<V2*>(A.r)[i];
             const V2 qv = reinterpret_cast<const V2*>(A.q)[i];
@@ -193,22 +198,28 @@ __global__ __launch_bounds__(256) void k_rescale(const RescaleArgs<T>* __restric
     T* __restrict__ uz = A.uz;
     if ((long)blockIdx.x * blockDim.x >= (M > N ? M : N)) return;
     const double k0 = A.scal[S_KAPPA], k1 = A.scal[S_KAPPA + 1];
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    // u^a <- kappa (u^a + a - R x) gives R^T u^a <- kappa (R^T u^a + R^T (a - R x)).
+    if (i < N) {
+        A.u[2 * i] = k0 * (A.u[2 * i] + A.h[2 * i]);
+        A.u[2 * i + 1] = k1 * (A.u[2 * i + 1] + A.h[2 * i + 1]);
+    }
     if (k0 == 1.0 && k1 == 1.0) return;
     const T kc[2] = {(T)k0, (T)k1};
-    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < M) {
         const long si = std_ray(i, sym, Vb, D);
         V2 u = reinterpret_cast<V2*>(ua)[si];
-        const V2 av = reinterpret_cast<const V2*>(a)[si];
-        const V2 rv = reinterpret_cast<const V2*>(Rx)[si];
-        V2 tv;
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            u.v[c] *= kc[c];
-            tv.v[c] = av.v[c] + u.v[c] - rv.v[c];
-        }
+        for (int c = 0; c < 2; ++c) u.v[c] *= kc[c];
         reinterpret_cast<V2*>(ua)[si] = u;
-        reinterpret_cast<V2*>(t)[i] = tv;
+        if (t) {  // the sinogram right-hand side, when it is kept
+            const V2 av = reinterpret_cast<const V2*>(a)[si];
+            const V2 rv = reinterpret_cast<const V2*>(Rx)[si];
+            V2 tv;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) tv.v[c] = av.v[c] + u.v[c] - rv.v[c];
+            reinterpret_cast<V2*>(t)[i] = tv;
+        }
     }
     if (i < N) {
         V4 u4 = reinterpret_cast<V4*>(uy)[i];
@@ -250,7 +261,7 @@ __global__ __launch_bounds__(256) void k_reduce(const RedArgs* __restrict__ dev,
         if (A.precond)
             section_sum<2>(A.pre, A.nb_pre, g);
         else
-            section_sum<2>(A.tiles, A.nb_tiles, g);
+            section_sum<2>(A.img, A.nb_img, g);
         if (threadIdx.x == 0) {
             s[S_GAMMA] = g[0];
             s[S_GAMMA + 1] = g[1];
@@ -322,6 +333,30 @@ __global__ __launch_bounds__(256) void k_reduce(const RedArgs* __restrict__ dev,
     }
 }
 
+// Initial CG residual of Eq. (12): r0 = R^T t + D^T (y + u^y - D x) + (z + u^z - x)
+// with R^T t = h + u (the tracked R^T (a - R x) and R^T u^a), per pixel; block
+// partials of |r0|^2 per 256 pixels.
+template <typename T, bool BATCH>
+__global__ __launch_bounds__(256) void k_rhs(const BpArgs<T>* __restrict__ dev, BpArgs<T> one) {
+    const BpArgs<T> a = pick_args<BATCH>(dev, one);
+    const long N = (long)a.nx * a.ny;
+    if ((long)blockIdx.x * blockDim.x >= N) return;  // beyond this slice (whole block)
+    const long pix = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    double part[2] = {0.0, 0.0};
+    if (pix < N) {
+        T res[2] = {(T)(a.h[2 * pix] + a.u[2 * pix]), (T)(a.h[2 * pix + 1] + a.u[2 * pix + 1])};
+        epilogue<T, EPI_RHS>(a, (int)(pix % a.nx), (int)(pix / a.nx), res, part);
+    }
+    block_sum_store<2>(part, a.part_img + (size_t)blockIdx.x * kPartialSlots);
+}
+
+// The tracked right-hand side at the start: h = R^T t with t = a + u^a - R x (u^a = 0
+// then, so h = R^T (a - R x)), u = 0.
+__global__ __launch_bounds__(256) void k_zero_f64(double* __restrict__ p, long n) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
 template <typename T>
 T* at(void* base, size_t off) {
     return reinterpret_cast<T*>(static_cast<char*>(base) + off);
@@ -355,6 +390,9 @@ SliceJob<T> make_job(const dect_plan* p, const void* mh, const void* ml, const v
     T* t = at<T>(st, p->off_t);
     T* da = at<T>(st, p->off_da);
     T* zb = at<T>(st, p->off_z);
+    double* hh = at<double>(st, p->off_h);
+    double* uu = at<double>(st, p->off_u);
+    T* rtrp = at<T>(st, p->off_rtrp);
     double* part = at<double>(st, p->off_partials);
     const Partials P{part, part + (size_t)p->nb_sino * kPartialSlots,
                      part + (size_t)(p->nb_sino + p->nb_img) * kPartialSlots,
@@ -402,6 +440,13 @@ SliceJob<T> make_job(const dect_plan* p, const void* mh, const void* ml, const v
     J.dual.sino = da;
     J.dual.y = dy;
     J.dual.z = dz;
+    // The tracked right-hand side: the RHS kernel reads h + u, the q transpose stores
+    // R^T R p, the dual transpose adds R^T da to h.
+    J.rhs.h = hh;
+    J.rhs.u = uu;
+    J.rhs.part_img = P.img;
+    J.q.raw = rtrp;
+    J.dual.h = hh;
     // a-update (Eq. (13)) fused with R x += alpha R p, u^a and the next t.
     UdmArgs<T>& u = J.udm;
     fill_udm_tables<T>(p, u);
@@ -417,7 +462,7 @@ SliceJob<T> make_job(const dect_plan* p, const void* mh, const void* ml, const v
     u.ua = ua;
     u.Rx = Rx;
     u.Rp = Rp;
-    u.t = t;
+    u.t = nullptr;  // R^T t is tracked in h + u
     u.da = da;
     u.fg = at<T>(st, p->off_fg);
     u.scal = scal;
@@ -425,7 +470,7 @@ SliceJob<T> make_job(const dect_plan* p, const void* mh, const void* ml, const v
     u.iters = prm->lm_iters;
     u.mu0 = prm->lm_mu0;
     J.vec = VecArgs<T>{p->N, p->M, p->sym, p->Vb, p->D, x, pp, r, pre ? zb : r, q, Rx, Rp, scal,
-                       P.img};
+                       P.img, hh, rtrp};
     if (pre) {
         fill_precond_plan<T>(p, J.pre0);
         J.pre0.W = at<T>(st, p->off_fftw);
@@ -436,7 +481,9 @@ SliceJob<T> make_job(const dect_plan* p, const void* mh, const void* ml, const v
         J.pre1.z = zb;
     }
     J.tv = TvArgs<T>{p->nx, p->ny, x, y, uy, dy, z, uz, dz, scal, P.img};
-    J.resc = RescaleArgs<T>{p->M, p->N, p->sym, p->Vb, p->D, ua, t, a, Rx, uy, uz, scal};
+    // The iterations keep R^T t tracked in h + u, not t itself (t is set at the start).
+    J.resc = RescaleArgs<T>{p->M, p->N, p->sym, p->Vb, p->D, ua, nullptr, a, Rx, uy, uz, scal,
+                            hh, uu};
     J.red = RedArgs{P.tiles, p->nb_tiles, P.img, p->nb_img, P.sino, p->nb_sino, P.pre, p->nb_pre,
                     pre ? 1 : 0, scal,
                     at<double>(st, p->off_log), prm->rho_mode,
@@ -451,7 +498,6 @@ template <typename T, bool BATCH>
 hipError_t iteration_t(const SliceJob<T>& J, const JobArrays<T>* dev, int nsl,
                        const dect_params* prm, long it, hipStream_t s) {
     const int n = prm->cg_iters;
-    const bool adaptive = prm->rho_mode == DECT_RHO_ADAPTIVE;
     const unsigned z = (unsigned)nsl;
     auto reduce = [&](int mode) -> hipError_t {
         RedArgs A = J.red;
@@ -471,8 +517,13 @@ hipError_t iteration_t(const SliceJob<T>& J, const JobArrays<T>* dev, int nsl,
     } while (0)
     const dim3 gN(nblk(J.N), 1, z), gM(nblk(J.M), 1, z);
     const VecArgs<T>* dvec = dev ? dev->vec : nullptr;
-    DECT_TRY(launch_backproject_admm<T>(J.sym, J.bp_waves, EPI_RHS, dev ? dev->rhs : nullptr,
-                                        J.rhs, nsl, J.bp_gx, J.bp_gy, s));
+    {
+        // R^T t of the right-hand side is tracked (h + u), so no transpose is needed.
+        ProfScope ps("rhs", s);
+        hipLaunchKernelGGL((k_rhs<T, BATCH>), gN, dim3(256), 0, s, dev ? dev->rhs : nullptr,
+                           J.rhs);
+        DECT_TRY(hipGetLastError());
+    }
     if (J.precond) DECT_TRY(launch_precond<T>(dev ? dev->pre0 : nullptr, J.pre0, nsl, s));
     DECT_TRY(reduce(RED_GAMMA));
     for (int c = 0; c < n; ++c) {
@@ -504,12 +555,11 @@ hipError_t iteration_t(const SliceJob<T>& J, const JobArrays<T>* dev, int nsl,
         hipLaunchKernelGGL((k_tv_dual<T, BATCH>), gN, dim3(256), 0, s, dev ? dev->tv : nullptr, J.tv);
     }
     DECT_TRY(hipGetLastError());
-    if (adaptive)
-        DECT_TRY(launch_backproject_admm<T>(J.sym, J.bp_waves, EPI_DUAL,
-                                            dev ? dev->dual : nullptr, J.dual, nsl, J.bp_gx,
-                                            J.bp_gy, s));
+    // R^T da: the dual residual (adaptive rho) and the tracked h in every mode.
+    DECT_TRY(launch_backproject_admm<T>(J.sym, J.bp_waves, EPI_DUAL, dev ? dev->dual : nullptr,
+                                        J.dual, nsl, J.bp_gx, J.bp_gy, s));
     DECT_TRY(reduce(RED_FINAL));
-    if (prm->rho_mode != DECT_RHO_FIXED) {
+    {
         ProfScope ps("rescale", s);
         hipLaunchKernelGGL((k_rescale<T, BATCH>), dim3(nblk(J.M > J.N ? J.M : J.N), 1, z), dim3(256), 0,
                            s, dev ? dev->resc : nullptr, J.resc);
@@ -528,11 +578,26 @@ hipError_t launch_iteration(const SliceJob<T>& J, const JobArrays<T>* dev, int n
                : iteration_t<T, false>(J, dev, nsl, prm, it, s);
 }
 
+template <typename T>
+hipError_t launch_track_init(const dect_plan* p, void* st, hipStream_t s) {
+    double* hh = at<double>(st, p->off_h);
+    hipLaunchKernelGGL(k_zero_f64, dim3(nblk(2 * p->N)), dim3(256), 0, s, hh, 2 * p->N);
+    BpArgs<T> b{};
+    fill_bp_plan<T>(p, b);
+    b.sino = at<T>(st, p->off_t);
+    b.y = at<T>(st, p->off_dy);  // zero at the start
+    b.z = at<T>(st, p->off_dz);  // zero at the start
+    b.h = hh;
+    b.partials = at<double>(st, p->off_partials) + (size_t)(p->nb_sino + p->nb_img) * kPartialSlots;
+    return launch_backproject_admm<T>(p->sym, p->bp_waves, EPI_DUAL, nullptr, b, 1, b.gx, b.gy, s);
+}
+
 #define DECT_INST(T)                                                                            \
     template SliceJob<T> make_job<T>(const dect_plan*, const void*, const void*, const void*,    \
                                      const void*, void*, const dect_params*);                    \
     template hipError_t launch_iteration<T>(const SliceJob<T>&, const JobArrays<T>*, int,        \
-                                            const dect_params*, long, hipStream_t);
+                                            const dect_params*, long, hipStream_t);              \
+    template hipError_t launch_track_init<T>(const dect_plan*, void*, hipStream_t);
 DECT_INST(float)
 DECT_INST(double)
 #undef DECT_INST
@@ -619,6 +684,7 @@ dect_status init_T(const dect_plan* p, const void* mh, const void* ml, const voi
     u.lin[2] = -lc / det;
     u.lin[3] = hc / det;
     hipError_t e = launch_udm<T>(p, 1, u, s);
+    if (e == hipSuccess) e = launch_track_init<T>(p, st, s);
     if (e != hipSuccess) return fail(DECT_E_DEVICE, "launch failed: %s", hipGetErrorString(e));
     return DECT_OK;
 }

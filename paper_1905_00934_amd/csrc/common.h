@@ -133,6 +133,9 @@ struct dect_plan {
     dect_layout layout;
     size_t off_p, off_pO, off_pOT, off_r, off_q, off_dy, off_dz, off_Rp, off_t, off_da, off_fg,
         off_z, off_fftw, off_partials, off_log;
+    // Tracked right-hand-side images (double [N][2]): H = R^T (a - R x), U = R^T u^a,
+    // and the last CG step's R^T R p ([N][2] of the plan's type).
+    size_t off_h, off_u, off_rtrp;
     int nb_sino, nb_img, nb_tiles, nb_pre;  // block counts of the reducing kernels
 };
 

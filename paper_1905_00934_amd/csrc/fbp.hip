@@ -249,7 +249,9 @@ hipError_t launch_init_image(const dect_plan* p, const void* x0, void* state, hi
     hipLaunchKernelGGL((k_init_t<T>), dim3((unsigned)((p->M + 255) / 256)), dim3(256), 0, s,
                        reinterpret_cast<const T*>(st + L.a), Rx, p->M, p->sym, p->Vb, p->D,
                        reinterpret_cast<T*>(st + p->off_t));
-    return hipGetLastError();
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_track_init<T>(p, state, s);
 }
 
 template hipError_t launch_init_image<float>(const dect_plan*, const void*, void*, hipStream_t);

@@ -10,9 +10,11 @@ enum Epilogue : int { EPI_NONE = 0, EPI_RHS = 1, EPI_Q = 2, EPI_DUAL = 3 };
 // Arguments of the transposed projector and its image-side epilogues.
 //  EPI_NONE: out = R^T sino (ch channels)
 //  EPI_RHS : out (and out2 if set) = R^T sino + D^T (y + uy - D x) + (z + uz - x);
-//            partials = per-channel |out|^2
-//  EPI_Q   : out (if set) = R^T sino + D^T D x + x, with x = p; partials = p . out
-//  EPI_DUAL: y = dy, z = dz; partials = |R^T sino + D^T dy + dz|^2
+//            partials = per-channel |out|^2 (the right-hand-side kernel applies the same
+//            image terms to the tracked R^T t = h + u instead of a transpose)
+//  EPI_Q   : out (if set) = R^T sino + D^T D x + x, with x = p; partials = p . out;
+//            raw (if set) = R^T sino
+//  EPI_DUAL: y = dy, z = dz; partials = |R^T sino + D^T dy + dz|^2; h (if set) += R^T sino
 // Every kernel takes its per-slice arguments either by value (BATCH = false: one
 // slice) or as a device array indexed by blockIdx.z (BATCH = true: several
 // slices of one shape in one launch).  The array is read word by word through
@@ -69,6 +71,13 @@ struct BpArgs {
     const T* z;
     const T* uz;
     double* partials;
+    // Tracked right-hand side: h = R^T (a - R x), u = R^T u^a (double [N][2]);
+    // raw: the plain R^T of the gathered sinogram ([N][2]) before any image term;
+    // part_img: per-256-pixel partials of the right-hand-side kernel.
+    double* h;
+    double* u;
+    T* raw;
+    double* part_img;
 };
 
 // Deterministic sum of K doubles over a 256-thread block (fixed shuffle and LDS
@@ -145,7 +154,7 @@ struct UdmArgs {
     T* ua;         // [M][2]
     T* Rx;         // [M][2], updated with alpha * Rp
     const T* Rp;   // [M][2]
-    T* t;          // [M][2] next right-hand side a + u^a - R x
+    T* t;          // [M][2] next right-hand side a + u^a - R x, or nullptr (not kept)
     T* da;         // [M][2] a - a_prev
     T* fg;         // [M][8] f_h, f_l, grad f_h, grad f_l at the current a (internal order)
     const double* scal;  // device scalars (rho, alpha)
@@ -198,6 +207,8 @@ struct VecArgs {
     const T* Rp;
     const double* scal;
     double* partials;   // image partials
+    double* h;          // tracked R^T (a - R x): minus alpha R^T R p per CG step
+    const T* rtrp;      // R^T R p of the current CG step
 };
 
 // Shrinkage, nonnegativity and the y, z duals (Eq. (9)-(11)).
@@ -227,6 +238,8 @@ struct RescaleArgs {
     T* uy;
     T* uz;
     const double* scal;
+    double* h;  // R^T (a - R x) of the new iterate
+    double* u;  // R^T u^a: u <- kappa (u + h)
 };
 
 // Fixed-order reductions of block partials and the scalar updates (one block per
@@ -303,8 +316,13 @@ hipError_t launch_lm_eval(const dect_plan* p, int basis, const T* at, const T* a
                           const T* ml, const T* wh, const T* wl, T* cache, double* partials,
                           hipStream_t s);
 
-// Start of the iterations from an image pair x0: x = z = x0, y = D x0, R x = R x0 and
-// t = a - R x0 (the state already initialised with x = 0).
+// The tracked right-hand side of a state whose t (= a + u^a - R x, internal ray order)
+// and zero u^a, dy, dz were just set: h = R^T t, by one transpose.
+template <typename T>
+hipError_t launch_track_init(const dect_plan* p, void* state, hipStream_t s);
+
+// Start of the iterations from an image pair x0: x = z = x0, y = D x0, R x = R x0,
+// t = a - R x0 and h = R^T t (the state already initialised with x = 0).
 template <typename T>
 hipError_t launch_init_image(const dect_plan* p, const void* x0, void* state, hipStream_t s);
 

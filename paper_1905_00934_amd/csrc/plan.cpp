@@ -338,6 +338,9 @@ void make_layout(dect_plan* p) {
     p->off_da = take(M * 2 * e);
     p->off_fg = take(M * 8 * e);
     p->off_z = take(N * 2 * e);
+    p->off_h = take(N * 2 * sizeof(double));
+    p->off_u = take(N * 2 * sizeof(double));
+    p->off_rtrp = take(N * 2 * e);
     p->off_fftw = p->has_precond ? take((size_t)p->ny * p->px * 2 * e) : 0;
     p->nb_sino = (int)((M + 255) / 256);
     p->nb_img = (int)((N + 255) / 256);

@@ -23,6 +23,7 @@
 // up to summation order.  The views are split over the waves of a workgroup and
 // the wave sums are added in a fixed order through LDS.
 #include "common.h"
+#include "epilogue.h"
 #include "kernels.h"
 #include "profile.h"
 
@@ -479,85 +480,6 @@ __device__ inline void gather_orbit_staged_wide(const BpArgs<T>& a, int wave, in
     }
 }
 
-// Image-side terms added to R^T at pixel (i, j) for the ADMM epilogues (CH = 2).
-// Adds the per-channel partial sums of the finished values to part.
-template <typename T, int EPI>
-__device__ inline void epilogue(const BpArgs<T>& a, int i, int j, T (&res)[2], double (&part)[2]) {
-    using V2 = vec<T, 2>;
-    using V4 = vec<T, 4>;
-    const int nx = a.nx, ny = a.ny;
-    const size_t pix = (size_t)j * nx + i;
-    const V2* x2 = reinterpret_cast<const V2*>(a.x);
-    if constexpr (EPI == EPI_RHS) {
-        // r0 = R^T t + D^T (y + u^y - D x) + (z + u^z - x), Eq. (12).
-        const V4* y4 = reinterpret_cast<const V4*>(a.y);
-        const V4* u4 = reinterpret_cast<const V4*>(a.uy);
-        const V2 xc = x2[pix];
-        const V2 z = reinterpret_cast<const V2*>(a.z)[pix];
-        const V2 uz = reinterpret_cast<const V2*>(a.uz)[pix];
-        const V4 yc = y4[pix], uc = u4[pix];
-#pragma unroll
-        for (int c = 0; c < 2; ++c) res[c] += z.v[c] + uz.v[c] - xc.v[c];
-        if (i < nx - 1) {
-            const V2 xr = x2[pix + 1];
-#pragma unroll
-            for (int c = 0; c < 2; ++c) res[c] -= yc.v[c] + uc.v[c] - (xr.v[c] - xc.v[c]);
-        }
-        if (i > 0) {
-            const V2 xl = x2[pix - 1];
-            const V4 yl = y4[pix - 1], ul = u4[pix - 1];
-#pragma unroll
-            for (int c = 0; c < 2; ++c) res[c] += yl.v[c] + ul.v[c] - (xc.v[c] - xl.v[c]);
-        }
-        if (j < ny - 1) {
-            const V2 xd = x2[pix + nx];
-#pragma unroll
-            for (int c = 0; c < 2; ++c) res[c] -= yc.v[2 + c] + uc.v[2 + c] - (xd.v[c] - xc.v[c]);
-        }
-        if (j > 0) {
-            const V2 xu = x2[pix - nx];
-            const V4 yu = y4[pix - nx], uu = u4[pix - nx];
-#pragma unroll
-            for (int c = 0; c < 2; ++c) res[c] += yu.v[2 + c] + uu.v[2 + c] - (xc.v[c] - xu.v[c]);
-        }
-        V2 o;
-        o.v[0] = res[0];
-        o.v[1] = res[1];
-        reinterpret_cast<V2*>(a.out)[pix] = o;
-        if (a.out2) reinterpret_cast<V2*>(a.out2)[pix] = o;
-        part[0] += (double)res[0] * (double)res[0];
-        part[1] += (double)res[1] * (double)res[1];
-    } else if constexpr (EPI == EPI_Q) {
-        // q = R^T R p + D^T D p + p; a.x holds p.
-        const V2 pc = x2[pix];
-#pragma unroll
-        for (int c = 0; c < 2; ++c) res[c] += pc.v[c];
-        if (i < nx - 1) { const V2 q = x2[pix + 1]; for (int c = 0; c < 2; ++c) res[c] += pc.v[c] - q.v[c]; }
-        if (i > 0) { const V2 q = x2[pix - 1]; for (int c = 0; c < 2; ++c) res[c] += pc.v[c] - q.v[c]; }
-        if (j < ny - 1) { const V2 q = x2[pix + nx]; for (int c = 0; c < 2; ++c) res[c] += pc.v[c] - q.v[c]; }
-        if (j > 0) { const V2 q = x2[pix - nx]; for (int c = 0; c < 2; ++c) res[c] += pc.v[c] - q.v[c]; }
-        if (a.out) {
-            V2 o;
-            o.v[0] = res[0];
-            o.v[1] = res[1];
-            reinterpret_cast<V2*>(a.out)[pix] = o;
-        }
-        part[0] += (double)pc.v[0] * (double)res[0];
-        part[1] += (double)pc.v[1] * (double)res[1];
-    } else {  // EPI_DUAL: s = R^T da + D^T dy + dz
-        const V4* d4 = reinterpret_cast<const V4*>(a.y);
-        const V4 dc = d4[pix];
-        const V2 dz = reinterpret_cast<const V2*>(a.z)[pix];
-#pragma unroll
-        for (int c = 0; c < 2; ++c) res[c] += dz.v[c];
-        if (i < nx - 1) for (int c = 0; c < 2; ++c) res[c] -= dc.v[c];
-        if (i > 0) { const V4 dl = d4[pix - 1]; for (int c = 0; c < 2; ++c) res[c] += dl.v[c]; }
-        if (j < ny - 1) for (int c = 0; c < 2; ++c) res[c] -= dc.v[2 + c];
-        if (j > 0) { const V4 du = d4[pix - nx]; for (int c = 0; c < 2; ++c) res[c] += du.v[2 + c]; }
-        part[0] += (double)res[0] * (double)res[0];
-        part[1] += (double)res[1] * (double)res[1];
-    }
-}
 
 // R^T (+ epilogue).  A workgroup owns an 8x8 block of pixel orbits (the block
 // lies in the first quadrant when SYM = 4) and has VS waves, each summing a

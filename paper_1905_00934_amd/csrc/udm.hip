@@ -271,7 +271,7 @@ __global__ __launch_bounds__(256) void k_udm(const UdmArgs<T>* __restrict__ dev,
             }
             reinterpret_cast<V2*>(A.ua)[i] = un;
             reinterpret_cast<V2*>(A.Rx)[i] = rx;
-            reinterpret_cast<V2*>(A.t)[l] = tn;
+            if (A.t) reinterpret_cast<V2*>(A.t)[l] = tn;
             reinterpret_cast<V2*>(A.da)[l] = dn;
             const T rh = P.fh - mh, rl = P.fl - ml;
             part[2] = 0.5 * ((double)wh * (double)rh * (double)rh + (double)wl * (double)rl * (double)rl);
