@@ -9,9 +9,9 @@ enum Epilogue : int { EPI_NONE = 0, EPI_RHS = 1, EPI_Q = 2, EPI_DUAL = 3 };
 
 // Arguments of the transposed projector and its image-side epilogues.
 //  EPI_NONE: out = R^T sino (ch channels)
-//  EPI_RHS : out (and out2 if set) = R^T sino + D^T (y + uy - D x) + (z + uz - x);
-//            partials = per-channel |out|^2 (the right-hand-side kernel applies the same
-//            image terms to the tracked R^T t = h + u instead of a transpose)
+//  EPI_RHS : out (and out2 if set) = R^T t + D^T (y + uy - D x) + (z + uz - x);
+//            partials = per-channel |out|^2.  Only the right-hand-side kernel uses it,
+//            with the tracked R^T t = h + u in place of a transpose.
 //  EPI_Q   : out (if set) = R^T sino + D^T D x + x, with x = p; partials = p . out;
 //            raw (if set) = R^T sino
 //  EPI_DUAL: y = dy, z = dz; partials = |R^T sino + D^T dy + dz|^2; h (if set) += R^T sino
@@ -108,8 +108,30 @@ constexpr int kProjViews = DECT_PJ_VIEWS;
 static_assert(kProjViews == 1 || kProjViews == 2 || kProjViews == 4 || kProjViews == 8 ||
                   kProjViews == 16 || kProjViews == 32,
               "projector views per wave");
-inline int proj_grid_x(int D) { return (D + 64 / kProjViews - 1) / (64 / kProjViews); }
-inline int proj_grid_y(int Vb) { return (Vb + kProjViews - 1) / kProjViews; }
+__host__ __device__ inline int proj_grid_x(int D) { return (D + 64 / kProjViews - 1) / (64 / kProjViews); }
+__host__ __device__ inline int proj_grid_y(int Vb) { return (Vb + kProjViews - 1) / kProjViews; }
+
+// Projector workgroup order.  The dispatcher hands consecutive workgroup ids to the
+// kXcds XCDs in turn, each with its own L2.  The gx bin groups form chunks of
+// kProjChunk; XCD x takes chunks x, x + kXcds, ... and runs every view group of a
+// chunk before the next one.  The rays in flight on one XCD then pass through a few
+// narrow annuli of the image, whose part of the orbit images its L2 can hold, and
+// each XCD still gets bins from across the whole detector, so the XCDs' shares of
+// ray length balance.  Measured at 512^2 / 720 x 1024: chunks of 1, 2, 4, 8 and 16
+// bin groups take 146, 149, 153, 160 and 244 us against 163 us in the plain
+// bins-then-views order; 16 leaves one chunk per XCD and unequal ray lengths.
+#ifndef DECT_PJ_CHUNK
+#define DECT_PJ_CHUNK 1
+#endif
+constexpr int kXcds = 8;
+constexpr int kProjChunk = DECT_PJ_CHUNK;
+static_assert(kProjChunk >= 1, "projector chunk");
+// Workgroups of one slice's projector launch (a multiple of kXcds; ids whose chunk
+// lies past the last bin group exit at once).
+inline unsigned proj_blocks(int gx, int gy) {
+    const int chunks = (gx + kProjChunk - 1) / kProjChunk;
+    return (unsigned)(kXcds * ((chunks + kXcds - 1) / kXcds) * kProjChunk * gy);
+}
 
 template <typename T>
 hipError_t launch_project(const dect_plan* p, const void* img, void* sino, int ch, hipStream_t s);

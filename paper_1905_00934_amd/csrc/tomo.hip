@@ -76,9 +76,9 @@ __global__ __launch_bounds__(256) void k_orbit(const OrbitArgs<T>* __restrict__ 
 // R for base rays: QUAD = true writes [Vb][D][SYM][CH] records, false writes the
 // standard [V][D][CH] layout (view v + k*Vb for rotation k).  A workgroup owns
 // 64 / kProjViews consecutive bins of kProjViews consecutive base views (one ray
-// per lane); its KS waves step through KS disjoint ranges of image lines (so the
-// lanes of a wave read one image line together) and wave 0 adds the KS partial
-// sums in order.
+// per lane), in the XCD-aware order of proj_blocks; its KS waves step through KS
+// disjoint ranges of image lines (so the lanes of a wave read one image line
+// together) and wave 0 adds the KS partial sums in order.
 template <typename T, int CH, int SYM, bool QUAD, int KS, bool BATCH>
 __global__ __launch_bounds__(64 * KS) void k_project(const ProjArgs<T>* __restrict__ dev,
                                                      ProjArgs<T> one) {
@@ -87,15 +87,19 @@ __global__ __launch_bounds__(64 * KS) void k_project(const ProjArgs<T>* __restri
     const ProjArgs<T> A = pick_args<BATCH>(dev, one);
     const int nx = A.nx, ny = A.ny, Vb = A.Vb, D = A.D;
     constexpr int BV = kProjViews, BB = 64 / kProjViews;
-    if ((int)blockIdx.x * BB >= D || (int)blockIdx.y * BV >= Vb) return;  // beyond this slice
+    const int gy = proj_grid_y(Vb);
+    const int xcd = blockIdx.x % kXcds, nth = blockIdx.x / kXcds;
+    const int chunk = xcd + kXcds * (nth / (kProjChunk * gy)), within = nth % (kProjChunk * gy);
+    const int bg = chunk * kProjChunk + within / gy, vg = within % gy;
+    if (bg >= proj_grid_x(D)) return;  // past the last bin group of this slice
     const RayParam<T>* __restrict__ rays = A.rays;
     const vec<T, W>* __restrict__ O = reinterpret_cast<const vec<T, W>*>(A.O);
     const vec<T, W>* __restrict__ OT = reinterpret_cast<const vec<T, W>*>(A.OT);
     T* __restrict__ sino = A.sino;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int v = blockIdx.y * BV + lane % BV;
-    const int b = blockIdx.x * BB + lane / BV;
+    const int v = vg * BV + lane % BV;
+    const int b = bg * BB + lane / BV;
     const bool valid = b < D && v < Vb;
     RayParam<T> r = rays[(size_t)(v < Vb ? v : Vb - 1) * D + (b < D ? b : D - 1)];
     const bool xs = r.pad == T(0);
@@ -376,6 +380,8 @@ __device__ inline void gather_orbit_staged_wide(const BpArgs<T>& a, int wave, in
     constexpr int PER = (REC + 63) / 64;
     static_assert(WIN % 16 == 0 && (REC <= 64 || REC % 64 == 0), "window layout");
     using Q = vec<T, SYM * CH>;
+    // A staged candidate: the ray record and the quad of sinogram values side by side,
+    // so one address steps through the window.
     __shared__ BpRay<T> s_ray[VS][REC];
     __shared__ Q s_sino[VS][REC];
     const T m = (T)a.margin;
@@ -455,17 +461,7 @@ __device__ inline void gather_orbit_staged_wide(const BpArgs<T>& a, int wave, in
                 const int lo0 = (int)ceil(fmax(bc - h, T(-1)));
                 const int hi0 = (int)floor(fmin(bc + h, T(D)));
                 const int lo = lo0 > 0 ? lo0 : 0, hi = hi0 < D - 1 ? hi0 : D - 1;
-                for (int b = lo; b <= hi; ++b) {
-                    const int idx = b - L[mm];
-                    BpRay<T> r;
-                    Q s;
-                    if ((unsigned)idx < (unsigned)WIN) {
-                        r = s_ray[wave][mm * WIN + idx];
-                        s = s_sino[wave][mm * WIN + idx];
-                    } else {
-                        r = rv[b];
-                        s = sq[b];
-                    }
+                auto add = [&](const BpRay<T>& r, const Q& s) {
                     const T d = fma(r.ci, fi, fma(r.cj, fj, r.phi0));
                     const T wt = fmax(T(0), fma(-r.step, fabs(d), r.step));
 #pragma unroll
@@ -473,7 +469,16 @@ __device__ inline void gather_orbit_staged_wide(const BpArgs<T>& a, int wave, in
 #pragma unroll
                         for (int c = 0; c < CH; ++c)
                             acc[(mm + kp) % SYM][c] += wt * s.v[kp * CH + c];
-                }
+                };
+                // Candidates in the window come from LDS; the rest (a steep footprint
+                // near the source, rare) are loaded directly, after them.
+                const int ilo = max(lo - L[mm], 0), ihi = min(hi - L[mm], WIN - 1);
+                const BpRay<T>* sr = &s_ray[wave][mm * WIN];
+                const Q* ss = &s_sino[wave][mm * WIN];
+                for (int k = ilo; k <= ihi; ++k) add(sr[k], ss[k]);
+                const int below = min(hi, L[mm] - 1), above = max(lo, L[mm] + WIN);
+                for (int b = lo; b <= below; ++b) add(rv[b], sq[b]);
+                for (int b = above; b <= hi; ++b) add(rv[b], sq[b]);
             }
         }
         __builtin_amdgcn_wave_barrier();
@@ -566,7 +571,7 @@ void project_launch(const OrbitArgs<T>* odev, const OrbitArgs<T>& oone, const Pr
         hipLaunchKernelGGL((k_orbit<T, CH, SYM, true, BATCH>), og, dim3(256), 0, s, odev, oone);
     }
     ProfScope pp("project", s);
-    hipLaunchKernelGGL((k_project<T, CH, SYM, QUAD, KS, BATCH>), dim3(gx, gy, n), dim3(64 * KS),
+    hipLaunchKernelGGL((k_project<T, CH, SYM, QUAD, KS, BATCH>), dim3(proj_blocks(gx, gy), 1, n), dim3(64 * KS),
                        0, s, pdev, pone);
 }
 
@@ -635,9 +640,6 @@ hipError_t bp_admm_t(int epi, const BpArgs<T>* dev, const BpArgs<T>& one, int n,
     const dim3 g(gx, gy, n);
     const dim3 blk(64 * VS);
     switch (epi) {
-        case EPI_RHS:
-            hipLaunchKernelGGL((k_backproject<T, 2, SYM, true, EPI_RHS, VS, BATCH>), g, blk, 0, s, dev, one);
-            break;
         case EPI_Q:
             hipLaunchKernelGGL((k_backproject<T, 2, SYM, true, EPI_Q, VS, BATCH>), g, blk, 0, s, dev, one);
             break;
