@@ -380,10 +380,14 @@ __device__ inline void gather_orbit_staged_wide(const BpArgs<T>& a, int wave, in
     constexpr int PER = (REC + 63) / 64;
     static_assert(WIN % 16 == 0 && (REC <= 64 || REC % 64 == 0), "window layout");
     using Q = vec<T, SYM * CH>;
-    // A staged candidate: the ray record and the quad of sinogram values side by side,
-    // so one address steps through the window.
-    __shared__ BpRay<T> s_ray[VS][REC];
-    __shared__ Q s_sino[VS][REC];
+    // A staged candidate: its ray record and its quad of sinogram values side by
+    // side (48 bytes for two FP32 channels), so that one address steps through the
+    // window.
+    struct alignas(sizeof(T) * 4) Staged {
+        BpRay<T> r;
+        T s[SYM * CH];
+    };
+    __shared__ Staged s_win[VS][REC];
     const T m = (T)a.margin;
     const int D = a.D, Vb = a.Vb, n = a.nx;
     const T cx = T(0.5) * (T)(a.nx - 1), cy = T(0.5) * (T)(a.ny - 1);
@@ -435,8 +439,9 @@ __device__ inline void gather_orbit_staged_wide(const BpArgs<T>& a, int wave, in
 #pragma unroll
         for (int q = 0; q < PER; ++q)
             if (stager[q]) {
-                s_ray[wave][lane + 64 * q] = pr[q];
-                s_sino[wave][lane + 64 * q] = pq[q];
+                s_win[wave][lane + 64 * q].r = pr[q];
+#pragma unroll
+                for (int c = 0; c < SYM * CH; ++c) s_win[wave][lane + 64 * q].s[c] = pq[q].v[c];
             }
         // LDS operations of one wave complete in order; the barrier only keeps the
         // compiler from moving the reads above the writes.
@@ -452,33 +457,32 @@ __device__ inline void gather_orbit_staged_wide(const BpArgs<T>& a, int wave, in
                 rot(mm, n, i, j, im, jm);
                 const T fi = (T)im, fj = (T)jm;
                 const T ip = fi - cx, jp = fj - cy;
+                // The denominator is positive for every image pixel (the plan keeps a
+                // fan's source outside the image), so |d beta / d i| and
+                // |d beta / d j| share the factor inv.
                 const T inv = fast_rcp<T>(w.d0 + w.di * ip + w.dj * jp);
                 const T bq = (w.ni * ip + w.nj * jp) * inv;
                 const T bc = bq + w.boff;
-                const T dby = (w.nj - bq * w.dj) * inv;
-                const T dbx = (w.ni - bq * w.di) * inv;
-                const T h = fmax(fabs(dby), fabs(dbx)) + m;
-                const int lo0 = (int)ceil(fmax(bc - h, T(-1)));
-                const int hi0 = (int)floor(fmin(bc + h, T(D)));
-                const int lo = lo0 > 0 ? lo0 : 0, hi = hi0 < D - 1 ? hi0 : D - 1;
-                auto add = [&](const BpRay<T>& r, const Q& s) {
+                const T h = fma(fmax(fabs(w.nj - bq * w.dj), fabs(w.ni - bq * w.di)), inv, m);
+                const int lo = (int)ceil(fmax(bc - h, T(0)));
+                const int hi = (int)floor(fmin(bc + h, T(D - 1)));
+                auto add = [&](const BpRay<T>& r, const T* s) {
                     const T d = fma(r.ci, fi, fma(r.cj, fj, r.phi0));
                     const T wt = fmax(T(0), fma(-r.step, fabs(d), r.step));
 #pragma unroll
                     for (int kp = 0; kp < SYM; ++kp)
 #pragma unroll
                         for (int c = 0; c < CH; ++c)
-                            acc[(mm + kp) % SYM][c] += wt * s.v[kp * CH + c];
+                            acc[(mm + kp) % SYM][c] += wt * s[kp * CH + c];
                 };
                 // Candidates in the window come from LDS; the rest (a steep footprint
                 // near the source, rare) are loaded directly, after them.
                 const int ilo = max(lo - L[mm], 0), ihi = min(hi - L[mm], WIN - 1);
-                const BpRay<T>* sr = &s_ray[wave][mm * WIN];
-                const Q* ss = &s_sino[wave][mm * WIN];
-                for (int k = ilo; k <= ihi; ++k) add(sr[k], ss[k]);
+                const Staged* sw = &s_win[wave][mm * WIN];
+                for (const Staged *c = sw + ilo, *e = sw + ihi; c <= e; ++c) add(c->r, c->s);
                 const int below = min(hi, L[mm] - 1), above = max(lo, L[mm] + WIN);
-                for (int b = lo; b <= below; ++b) add(rv[b], sq[b]);
-                for (int b = above; b <= hi; ++b) add(rv[b], sq[b]);
+                for (int b = lo; b <= below; ++b) add(rv[b], sq[b].v);
+                for (int b = above; b <= hi; ++b) add(rv[b], sq[b].v);
             }
         }
         __builtin_amdgcn_wave_barrier();
