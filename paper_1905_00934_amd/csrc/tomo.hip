@@ -462,10 +462,7 @@ __device__ inline void gather_orbit_staged_wide(const BpArgs<T>& a, int wave, in
                 // |d beta / d j| share the factor inv.
                 const T inv = fast_rcp<T>(w.d0 + w.di * ip + w.dj * jp);
                 const T bq = (w.ni * ip + w.nj * jp) * inv;
-                const T bc = bq + w.boff;
                 const T h = fma(fmax(fabs(w.nj - bq * w.dj), fabs(w.ni - bq * w.di)), inv, m);
-                const int lo = (int)ceil(fmax(bc - h, T(0)));
-                const int hi = (int)floor(fmin(bc + h, T(D - 1)));
                 auto add = [&](const BpRay<T>& r, const T* s) {
                     const T d = fma(r.ci, fi, fma(r.cj, fj, r.phi0));
                     const T wt = fmax(T(0), fma(-r.step, fabs(d), r.step));
@@ -475,14 +472,23 @@ __device__ inline void gather_orbit_staged_wide(const BpArgs<T>& a, int wave, in
                         for (int c = 0; c < CH; ++c)
                             acc[(mm + kp) % SYM][c] += wt * s[kp * CH + c];
                 };
-                // Candidates in the window come from LDS; the rest (a steep footprint
-                // near the source, rare) are loaded directly, after them.
-                const int ilo = max(lo - L[mm], 0), ihi = min(hi - L[mm], WIN - 1);
+                // Candidates in the window come from LDS, in window coordinates (bins
+                // of the window past the detector's ends hold zero records and add
+                // nothing).  The rest (a steep footprint near the source, rare) are
+                // loaded directly, after them, when some lane of the wave has any.
+                const T x = bq + (w.boff - (T)L[mm]);
+                const int ilo = (int)ceil(fmax(x - h, T(0)));
+                const int ihi = (int)floor(fmin(x + h, T(WIN - 1)));
                 const Staged* sw = &s_win[wave][mm * WIN];
                 for (const Staged *c = sw + ilo, *e = sw + ihi; c <= e; ++c) add(c->r, c->s);
-                const int below = min(hi, L[mm] - 1), above = max(lo, L[mm] + WIN);
-                for (int b = lo; b <= below; ++b) add(rv[b], sq[b].v);
-                for (int b = above; b <= hi; ++b) add(rv[b], sq[b].v);
+                if (__any(x - h < T(0) || x + h > T(WIN - 1))) {
+                    const T bc = bq + w.boff;
+                    const int lo = (int)ceil(fmax(bc - h, T(0)));
+                    const int hi = (int)floor(fmin(bc + h, T(D - 1)));
+                    const int below = min(hi, L[mm] - 1), above = max(lo, L[mm] + WIN);
+                    for (int b = lo; b <= below; ++b) add(rv[b], sq[b].v);
+                    for (int b = above; b <= hi; ++b) add(rv[b], sq[b].v);
+                }
             }
         }
         __builtin_amdgcn_wave_barrier();
