@@ -233,22 +233,6 @@ __global__ __launch_bounds__(256) void k_rescale(const RescaleArgs<T>* __restric
     }
 }
 
-// Fixed-order sum of K slots over nb block partials; the result reaches all threads.
-template <int K>
-__device__ inline void section_sum(const double* base, int nb, double (&out)[K]) {
-    __shared__ double res[K];
-    double v[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = 0.0;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x)
-#pragma unroll
-        for (int k = 0; k < K; ++k) v[k] += base[(size_t)b * kPartialSlots + k];
-    block_sum_store<K>(v, res);
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < K; ++k) out[k] = res[k];
-    __syncthreads();
-}
 
 template <bool BATCH>
 __global__ __launch_bounds__(256) void k_reduce(const RedArgs* __restrict__ dev, RedArgs one,
@@ -259,16 +243,16 @@ __global__ __launch_bounds__(256) void k_reduce(const RedArgs* __restrict__ dev,
     if (mode == RED_GAMMA) {
         double g[2];
         if (A.precond)
-            section_sum<2>(A.pre, A.nb_pre, g);
+            partial_sum<2>(A.pre, A.nb_pre, g);
         else
-            section_sum<2>(A.img, A.nb_img, g);
+            partial_sum<2>(A.img, A.nb_img, g);
         if (threadIdx.x == 0) {
             s[S_GAMMA] = g[0];
             s[S_GAMMA + 1] = g[1];
         }
     } else if (mode == RED_ALPHA) {
         double pq[2];
-        section_sum<2>(A.tiles, A.nb_tiles, pq);
+        partial_sum<2>(A.tiles, A.nb_tiles, pq);
         if (threadIdx.x == 0)
             for (int c = 0; c < 2; ++c) {
                 s[S_PQ + c] = pq[c];
@@ -277,9 +261,9 @@ __global__ __launch_bounds__(256) void k_reduce(const RedArgs* __restrict__ dev,
     } else if (mode == RED_BETA) {
         double g[2];
         if (A.precond)
-            section_sum<2>(A.pre, A.nb_pre, g);
+            partial_sum<2>(A.pre, A.nb_pre, g);
         else
-            section_sum<2>(A.img, A.nb_img, g);
+            partial_sum<2>(A.img, A.nb_img, g);
         if (threadIdx.x == 0)
             for (int c = 0; c < 2; ++c) {
                 s[S_BETA + c] = s[S_GAMMA + c] > 0.0 ? g[c] / s[S_GAMMA + c] : 0.0;
@@ -287,9 +271,9 @@ __global__ __launch_bounds__(256) void k_reduce(const RedArgs* __restrict__ dev,
             }
     } else {
         double sn[4], im[4], du[2] = {0.0, 0.0};
-        section_sum<4>(A.sino, A.nb_sino, sn);
-        section_sum<4>(A.img, A.nb_img, im);
-        if (A.dual) section_sum<2>(A.tiles, A.nb_tiles, du);
+        partial_sum<4>(A.sino, A.nb_sino, sn);
+        partial_sum<4>(A.img, A.nb_img, im);
+        if (A.dual) partial_sum<2>(A.tiles, A.nb_tiles, du);
         if (threadIdx.x == 0) {
             const double rho[2] = {s[S_RHO], s[S_RHO + 1]};
             double r[2], sd[2], nr[2];

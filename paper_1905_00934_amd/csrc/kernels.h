@@ -98,6 +98,40 @@ __device__ inline void block_sum_store(double (&v)[K], double* out) {
         for (int k = 0; k < K; ++k) out[k] = (sh[0][k] + sh[1][k]) + (sh[2][k] + sh[3][k]);
 }
 
+// Fixed-order sum of K slots over nb block partials (kPartialSlots doubles each) by
+// a 256-thread block; the result reaches all threads.  Thread t adds partials t,
+// t + 256, ... in that order; the loads of 8 of them are issued before they are
+// added, so the thread waits on memory once per 8 partials.
+template <int K>
+__device__ inline void partial_sum(const double* __restrict__ base, int nb, double (&out)[K]) {
+    __shared__ double res[K];
+    constexpr int U = 8;
+    const int nt = blockDim.x;
+    double v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = 0.0;
+    int b = threadIdx.x;
+    for (; b + (U - 1) * nt < nb; b += U * nt) {
+        double t[U][K];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int k = 0; k < K; ++k) t[u][k] = base[(size_t)(b + u * nt) * kPartialSlots + k];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int k = 0; k < K; ++k) v[k] += t[u][k];
+    }
+    for (; b < nb; b += nt)
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] += base[(size_t)b * kPartialSlots + k];
+    block_sum_store<K>(v, res);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) out[k] = res[k];
+    __syncthreads();
+}
+
 // Projector workgroups: 64 / kProjViews consecutive bins of kProjViews consecutive
 // base views (lane = bin * kProjViews + view), so the lanes of a wave read nearby
 // image rows at every step.

@@ -392,22 +392,6 @@ __global__ __launch_bounds__(256) void k_lm_rescale(long N, const double* __rest
     }
 }
 
-// Fixed-order sum of K slots over nb block partials; the result reaches all threads.
-template <int K>
-__device__ inline void lm_sum(const double* base, int nb, double (&out)[K]) {
-    __shared__ double res[K];
-    double v[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = 0.0;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x)
-#pragma unroll
-        for (int k = 0; k < K; ++k) v[k] += base[(size_t)b * kPartialSlots + k];
-    block_sum_store<K>(v, res);
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < K; ++k) out[k] = res[k];
-    __syncthreads();
-}
 
 struct RedLm {
     double* sc;
@@ -424,8 +408,8 @@ __global__ __launch_bounds__(256) void k_lm_reduce(RedLm A, int mode, int reset_
     double* s = A.sc;
     if (mode == LR_GRAD) {
         double dn[4], im[4];
-        lm_sum<4>(A.sino, A.nb_s, dn);
-        lm_sum<4>(A.img, A.nb_i, im);
+        partial_sum<4>(A.sino, A.nb_s, dn);
+        partial_sum<4>(A.img, A.nb_i, im);
         if (threadIdx.x == 0) {
             s[L_DATA] = dn[0];
             s[L_PHI] = dn[0] + im[1];
@@ -435,7 +419,7 @@ __global__ __launch_bounds__(256) void k_lm_reduce(RedLm A, int mode, int reset_
         }
     } else if (mode == LR_Q) {
         double im[4];
-        lm_sum<4>(A.img, A.nb_i, im);
+        partial_sum<4>(A.img, A.nb_i, im);
         if (threadIdx.x == 0) {
             const double php = im[0], pp = im[1];
             if (s[L_FIRST] != 0.0) {
@@ -447,15 +431,15 @@ __global__ __launch_bounds__(256) void k_lm_reduce(RedLm A, int mode, int reset_
         }
     } else if (mode == LR_UPD) {
         double im[4];
-        lm_sum<4>(A.img, A.nb_i, im);
+        partial_sum<4>(A.img, A.nb_i, im);
         if (threadIdx.x == 0) {
             s[L_BETA] = s[L_RR] > 0.0 ? im[0] / s[L_RR] : 0.0;
             s[L_RR] = im[0];
         }
     } else if (mode == LR_TRIAL) {
         double dn[4], im[4];
-        lm_sum<4>(A.sino, A.nb_s, dn);
-        lm_sum<4>(A.img, A.nb_i, im);
+        partial_sum<4>(A.sino, A.nb_s, dn);
+        partial_sum<4>(A.img, A.nb_i, im);
         if (threadIdx.x == 0) {
             const double phit = dn[0] + im[0];
             const bool acc = phit < s[L_PHI];
@@ -470,8 +454,8 @@ __global__ __launch_bounds__(256) void k_lm_reduce(RedLm A, int mode, int reset_
         }
     } else {
         double im[4], du[4];
-        lm_sum<4>(A.img, A.nb_i, im);
-        lm_sum<4>(A.dual, A.nb_i, du);
+        partial_sum<4>(A.img, A.nb_i, im);
+        partial_sum<4>(A.dual, A.nb_i, du);
         if (threadIdx.x == 0) {
             const double rho[2] = {s[L_RHO], s[L_RHO + 1]};
             double r[2], sd[2], nr[2];
