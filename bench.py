@@ -49,9 +49,7 @@ def counted_traffic() -> dict:
         if not parts or parts[0].startswith("#"):
             continue
         if parts[0] == "kernel":
-            # Both orbit-image kernels are timed together under one name.
-            name = "orbit" if parts[1] == "orbit_t" else parts[1]
-            table[name] = table.get(name, 0) + int(parts[-1])
+            table[parts[1]] = int(parts[-1])
         else:
             meta[parts[0]] = parts[1]
     return table if meta.get("source_hash") == kernel_source_hash() else {}
@@ -68,7 +66,7 @@ def algorithmic_bytes(N: int, M: int, cg_iters: int, elem: int = 4) -> dict:
         "backproject_q": 2 * M + 4 * N + extra,     # R p; p; R^T R p (and q)
         "backproject_dual": 2 * M + 14 * N,         # da; dy, dz; h in and out
         "project": 2 * N + 2 * M,                   # p; R p
-        "orbit": 2 * (2 * N + 8 * N),               # two orbit images of p
+        "orbit": 2 * N + 16 * N,                    # p; its orbit image and the transpose
         "udm": 32 * M,                              # m, w, a, R x, R p, u^a, f cache in; a, u^a, R x, da, cache out
         "tv_dual": 32 * N,                          # x, y, u^y, z, u^z in; y, u^y, dy, z, u^z, dz out
         "rescale": 4 * M + 24 * N,                  # u, h in, u out; when rho changes u^a, u^y, u^z in and out

@@ -21,7 +21,7 @@ namespace dect {
 
 namespace {
 
-enum RedMode : int { RED_GAMMA = 0, RED_ALPHA = 1, RED_BETA = 2, RED_FINAL = 3 };
+enum RedMode : int { RED_ALPHA = 1, RED_BETA = 2, RED_FINAL = 3 };
 
 __global__ __launch_bounds__(256) void k_zero(uint32_t* p, size_t n) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -240,23 +240,20 @@ __global__ __launch_bounds__(256) void k_reduce(const RedArgs* __restrict__ dev,
     const RedArgs A = pick_args<BATCH>(dev, one);
     double* s = A.scal;
     if (!s) return;  // empty slot
-    if (mode == RED_GAMMA) {
-        double g[2];
+    if (mode == RED_ALPHA) {
+        // gamma = r . z of the current residual: its block partials are still in place
+        // (no kernel between the one that wrote them and this reduction writes there).
+        double g[2], pq[2];
         if (A.precond)
             partial_sum<2>(A.pre, A.nb_pre, g);
         else
             partial_sum<2>(A.img, A.nb_img, g);
-        if (threadIdx.x == 0) {
-            s[S_GAMMA] = g[0];
-            s[S_GAMMA + 1] = g[1];
-        }
-    } else if (mode == RED_ALPHA) {
-        double pq[2];
         partial_sum<2>(A.tiles, A.nb_tiles, pq);
         if (threadIdx.x == 0)
             for (int c = 0; c < 2; ++c) {
+                s[S_GAMMA + c] = g[c];
                 s[S_PQ + c] = pq[c];
-                s[S_ALPHA + c] = (pq[c] > 0.0 && s[S_GAMMA + c] > 0.0) ? s[S_GAMMA + c] / pq[c] : 0.0;
+                s[S_ALPHA + c] = (pq[c] > 0.0 && g[c] > 0.0) ? g[c] / pq[c] : 0.0;
             }
     } else if (mode == RED_BETA) {
         double g[2];
@@ -509,7 +506,6 @@ hipError_t iteration_t(const SliceJob<T>& J, const JobArrays<T>* dev, int nsl,
         DECT_TRY(hipGetLastError());
     }
     if (J.precond) DECT_TRY(launch_precond<T>(dev ? dev->pre0 : nullptr, J.pre0, nsl, s));
-    DECT_TRY(reduce(RED_GAMMA));
     for (int c = 0; c < n; ++c) {
         DECT_TRY(launch_project_pair<T>(J.sym, J.pj_waves, dev ? dev->orb : nullptr, J.orb,
                                         dev ? dev->prj : nullptr, J.prj, nsl, J.N, J.pj_gx,

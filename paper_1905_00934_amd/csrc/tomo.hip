@@ -47,20 +47,10 @@ __device__ inline void rot(int k, int n, int i, int j, int& io, int& jo) {
     }
 }
 
-// Orbit image (TR = false: O[j][i]; TR = true: its transpose OT[i][j]) with
-// component k*CH + c = channel c of X at rot^k(i, j).  SYM = 1 gives X or X^T.
-template <typename T, int CH, int SYM, bool TR, bool BATCH>
-__global__ __launch_bounds__(256) void k_orbit(const OrbitArgs<T>* __restrict__ dev,
-                                               OrbitArgs<T> one) {
-    const OrbitArgs<T> A = pick_args<BATCH>(dev, one);
-    const int nx = A.nx, ny = A.ny;
-    const vec<T, CH>* __restrict__ X = reinterpret_cast<const vec<T, CH>*>(A.X);
-    vec<T, CH * SYM>* __restrict__ out = reinterpret_cast<vec<T, CH * SYM>*>(TR ? A.OT : A.O);
-    const int lines = TR ? nx : ny, len = TR ? ny : nx;
-    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (long)lines * len) return;
-    const int line = (int)(idx / len), pos = (int)(idx % len);
-    const int i = TR ? line : pos, j = TR ? pos : line;
+// Orbit record of pixel (i, j): component k*CH + c = channel c of X at rot^k(i, j).
+template <typename T, int CH, int SYM>
+__device__ inline vec<T, CH * SYM> orbit_record(const vec<T, CH>* __restrict__ X, int nx, int i,
+                                                int j) {
     vec<T, CH * SYM> o;
 #pragma unroll
     for (int k = 0; k < SYM; ++k) {
@@ -70,7 +60,23 @@ __global__ __launch_bounds__(256) void k_orbit(const OrbitArgs<T>* __restrict__ 
 #pragma unroll
         for (int c = 0; c < CH; ++c) o.v[k * CH + c] = x.v[c];
     }
-    out[idx] = o;
+    return o;
+}
+
+// Orbit image O[j][i] and its transpose OT[i][j] in one pass: thread idx writes
+// record idx of both.  SYM = 1 gives X and X^T.
+template <typename T, int CH, int SYM, bool BATCH>
+__global__ __launch_bounds__(256) void k_orbit(const OrbitArgs<T>* __restrict__ dev,
+                                               OrbitArgs<T> one) {
+    const OrbitArgs<T> A = pick_args<BATCH>(dev, one);
+    const int nx = A.nx, ny = A.ny;
+    const vec<T, CH>* __restrict__ X = reinterpret_cast<const vec<T, CH>*>(A.X);
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)nx * ny) return;
+    reinterpret_cast<vec<T, CH * SYM>*>(A.O)[idx] =
+        orbit_record<T, CH, SYM>(X, nx, (int)(idx % nx), (int)(idx / nx));
+    reinterpret_cast<vec<T, CH * SYM>*>(A.OT)[idx] =
+        orbit_record<T, CH, SYM>(X, nx, (int)(idx / ny), (int)(idx % ny));
 }
 
 // R for base rays: QUAD = true writes [Vb][D][SYM][CH] records, false writes the
@@ -574,11 +580,10 @@ constexpr int kLineSplit = 4;
 template <typename T, int CH, int SYM, bool QUAD, bool BATCH, int KS>
 void project_launch(const OrbitArgs<T>* odev, const OrbitArgs<T>& oone, const ProjArgs<T>* pdev,
                     const ProjArgs<T>& pone, int n, long pixels, int gx, int gy, hipStream_t s) {
-    const dim3 og((unsigned)((pixels + 255) / 256), 1, n);
     {
         ProfScope pt("orbit", s);
-        hipLaunchKernelGGL((k_orbit<T, CH, SYM, false, BATCH>), og, dim3(256), 0, s, odev, oone);
-        hipLaunchKernelGGL((k_orbit<T, CH, SYM, true, BATCH>), og, dim3(256), 0, s, odev, oone);
+        hipLaunchKernelGGL((k_orbit<T, CH, SYM, BATCH>), dim3((unsigned)((pixels + 255) / 256), 1, n),
+                           dim3(256), 0, s, odev, oone);
     }
     ProfScope pp("project", s);
     hipLaunchKernelGGL((k_project<T, CH, SYM, QUAD, KS, BATCH>), dim3(proj_blocks(gx, gy), 1, n), dim3(64 * KS),
