@@ -457,17 +457,23 @@ __device__ inline void gather_orbit_staged_wide(const BpArgs<T>& a, int wave, in
             const ViewParam<T> w = a.views[v];
             const BpRay<T>* __restrict__ rv = a.brays + (size_t)v * D;
             const Q* __restrict__ sq = sino + (size_t)v * D;
+            // Orbit member mm of the centred pixel (ip, jp) is (ip, jp), (-jp, ip),
+            // (-ip, -jp), (jp, -ip), so its projective denominator and numerator are
+            // signed combinations of four products shared by the members.
+            const T ip0 = (T)i - cx, jp0 = (T)j - cy;
+            const T pa = w.di * ip0 + w.dj * jp0, pb = w.dj * ip0 - w.di * jp0;
+            const T na = w.ni * ip0 + w.nj * jp0, nb = w.nj * ip0 - w.ni * jp0;
 #pragma unroll
             for (int mm = 0; mm < SYM; ++mm) {
                 int im, jm;
                 rot(mm, n, i, j, im, jm);
                 const T fi = (T)im, fj = (T)jm;
-                const T ip = fi - cx, jp = fj - cy;
+                const T dq = (mm & 1) ? pb : pa, nq = (mm & 1) ? nb : na;
                 // The denominator is positive for every image pixel (the plan keeps a
                 // fan's source outside the image), so |d beta / d i| and
                 // |d beta / d j| share the factor inv.
-                const T inv = fast_rcp<T>(w.d0 + w.di * ip + w.dj * jp);
-                const T bq = (w.ni * ip + w.nj * jp) * inv;
+                const T inv = fast_rcp<T>(mm & 2 ? w.d0 - dq : w.d0 + dq);
+                const T bq = (mm & 2 ? -nq : nq) * inv;
                 const T h = fma(fmax(fabs(w.nj - bq * w.dj), fabs(w.ni - bq * w.di)), inv, m);
                 auto add = [&](const BpRay<T>& r, const T* s) {
                     const T d = fma(r.ci, fi, fma(r.cj, fj, r.phi0));
