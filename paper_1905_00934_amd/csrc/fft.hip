@@ -39,6 +39,13 @@ __global__ __launch_bounds__(256) void k_pre_rows_fwd(const PrecArgs<T>* __restr
     for (int i = threadIdx.x; i < A.px; i += blockDim.x) w[i] = buf[i];
 }
 
+// Column groups per XCD: workgroups reach the kXcds XCDs in turn, and XCD x takes
+// the x-th contiguous range of column groups, so the columns that share a cache
+// line of the work grid are read through the same L2.
+inline unsigned pre_col_blocks(int groups) {
+    return (unsigned)(kXcds * ((groups + kXcds - 1) / kXcds));
+}
+
 // C columns per block (C consecutive columns of the work grid).
 template <typename T, bool BATCH, int C>
 __global__ __launch_bounds__(256) void k_pre_cols(const PrecArgs<T>* __restrict__ dev,
@@ -46,8 +53,10 @@ __global__ __launch_bounds__(256) void k_pre_cols(const PrecArgs<T>* __restrict_
     extern __shared__ char smem[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem);
     const PrecArgs<T> A = pick_args<BATCH>(dev, one);
-    const int c0 = blockIdx.x * C;
-    if (c0 >= A.px) return;  // beyond this slice (whole block)
+    const int groups = (A.px + C - 1) / C, per = (groups + kXcds - 1) / kXcds;
+    const int g = (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
+    const int c0 = g * C;
+    if (g >= groups) return;  // beyond this slice (whole block)
     const int py = A.py, lg = A.lpy;
     cx<T>* W = reinterpret_cast<cx<T>*>(A.W);
     for (int t = threadIdx.x; t < C * py; t += blockDim.x) {
@@ -111,7 +120,7 @@ void precond_launch(const PrecArgs<T>* dev, const PrecArgs<T>& one, int n, hipSt
     constexpr int C = 1;
     const size_t row_lds = (size_t)one.px * sizeof(cx<T>);
     const size_t col_lds = (size_t)C * one.py * sizeof(cx<T>);
-    const dim3 rows((unsigned)one.ny, 1, n), cols((unsigned)((one.px + C - 1) / C), 1, n);
+    const dim3 rows((unsigned)one.ny, 1, n), cols(pre_col_blocks((one.px + C - 1) / C), 1, n);
     hipLaunchKernelGGL((k_pre_rows_fwd<T, BATCH>), rows, dim3(256), row_lds, s, dev, one);
     hipLaunchKernelGGL((k_pre_cols<T, BATCH, C>), cols, dim3(256), col_lds, s, dev, one);
     hipLaunchKernelGGL((k_pre_rows_inv<T, BATCH>), rows, dim3(256), row_lds, s, dev, one);
