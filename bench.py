@@ -67,8 +67,9 @@ def algorithmic_bytes(N: int, M: int, cg_iters: int, elem: int = 4) -> dict:
         "backproject_dual": 2 * M + 14 * N,         # da; dy, dz; h in and out
         "project": 2 * N + 2 * M,                   # p; R p
         "orbit": 2 * N + 16 * N,                    # p; its orbit image and the transpose
-        "udm": 32 * M,                              # m, w, a, R x, R p, u^a, f cache in; a, u^a, R x, da, cache out
-        "tv_dual": 32 * N,                          # x, y, u^y, z, u^z in; y, u^y, dy, z, u^z, dz out
+        # a-update: m, w, a, R x, R p, u^a, f cache in; a, u^a, R x, da, cache out; with
+        # the TV/z/dual blocks: x, y, u^y, z, u^z in; y, u^y, dy, z, u^z, dz out
+        "udm": 32 * M + 32 * N,
         "rescale": 4 * M + 24 * N,                  # u, h in, u out; when rho changes u^a, u^y, u^z in and out
         "cg_vector": 16 * N,                        # x in and out, p, R^T R p, h in and out
     }.items()}

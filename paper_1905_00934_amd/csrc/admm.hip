@@ -101,86 +101,6 @@ __global__ __launch_bounds__(256) void k_p_step(const VecArgs<T>* __restrict__ d
     reinterpret_cast<V2*>(A.p)[i] = a;
 }
 
-template <typename T>
-__device__ inline T soft(T v, T t) {
-    const T m = fabs(v) - t;
-    return m > T(0) ? copysign(m, v) : T(0);
-}
-
-// y = shrink(D x - u^y, lambda/rho) (Eq. (9)), z = max(0, x - u^z) (Eq. (10)),
-// u^y += y - D x, u^z += z - x (Eq. (11)); dy, dz = changes of y, z.
-// Partials: |y - Dx|^2 + |z - x|^2 per basis, |y_c|_1, |y_p|_1.
-template <typename T, bool BATCH>
-__global__ __launch_bounds__(256) void k_tv_dual(const TvArgs<T>* __restrict__ dev, TvArgs<T> one) {
-    using V2 = vec<T, 2>;
-    using V4 = vec<T, 4>;
-    const TvArgs<T> A = pick_args<BATCH>(dev, one);
-    const int nx = A.nx, ny = A.ny;
-    const long N = (long)nx * ny;
-    if ((long)blockIdx.x * blockDim.x >= N) return;  // beyond this slice (whole block)
-    const T* __restrict__ x = A.x;
-    T* __restrict__ y = A.y;
-    T* __restrict__ uy = A.uy;
-    T* __restrict__ dy = A.dy;
-    T* __restrict__ z = A.z;
-    T* __restrict__ uz = A.uz;
-    T* __restrict__ dz = A.dz;
-    const double* __restrict__ scal = A.scal;
-    const long pix = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    double part[4] = {0.0, 0.0, 0.0, 0.0};
-    if (pix < N) {
-        const int j = (int)(pix / nx), i = (int)(pix % nx);
-        const V2* x2 = reinterpret_cast<const V2*>(x);
-        const V2 xc = x2[pix];
-        V4 Dx;
-        if (i < nx - 1) {
-            const V2 xr = x2[pix + 1];
-            Dx.v[0] = xr.v[0] - xc.v[0];
-            Dx.v[1] = xr.v[1] - xc.v[1];
-        } else {
-            Dx.v[0] = Dx.v[1] = T(0);
-        }
-        if (j < ny - 1) {
-            const V2 xd = x2[pix + nx];
-            Dx.v[2] = xd.v[0] - xc.v[0];
-            Dx.v[3] = xd.v[1] - xc.v[1];
-        } else {
-            Dx.v[2] = Dx.v[3] = T(0);
-        }
-        const T th[2] = {(T)(scal[S_LAM] / scal[S_RHO]), (T)(scal[S_LAM + 1] / scal[S_RHO + 1])};
-        V4 u = reinterpret_cast<V4*>(uy)[pix];
-        const V4 yo = reinterpret_cast<V4*>(y)[pix];
-        V4 yn, d;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            yn.v[k] = soft<T>(Dx.v[k] - u.v[k], th[k & 1]);
-            u.v[k] += yn.v[k] - Dx.v[k];
-            d.v[k] = yn.v[k] - yo.v[k];
-            const double e = (double)(yn.v[k] - Dx.v[k]);
-            part[k & 1] += e * e;
-            part[2 + (k & 1)] += fabs((double)yn.v[k]);
-        }
-        reinterpret_cast<V4*>(y)[pix] = yn;
-        reinterpret_cast<V4*>(uy)[pix] = u;
-        reinterpret_cast<V4*>(dy)[pix] = d;
-        V2 w = reinterpret_cast<V2*>(uz)[pix];
-        const V2 zo = reinterpret_cast<V2*>(z)[pix];
-        V2 zn, dzv;
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            zn.v[c] = fmax(T(0), xc.v[c] - w.v[c]);
-            w.v[c] += zn.v[c] - xc.v[c];
-            dzv.v[c] = zn.v[c] - zo.v[c];
-            const double e = (double)(zn.v[c] - xc.v[c]);
-            part[c] += e * e;
-        }
-        reinterpret_cast<V2*>(z)[pix] = zn;
-        reinterpret_cast<V2*>(uz)[pix] = w;
-        reinterpret_cast<V2*>(dz)[pix] = dzv;
-    }
-    block_sum_store<4>(part, A.partials + (size_t)blockIdx.x * kPartialSlots);
-}
-
 // Scaled duals follow rho: u *= rho_old / rho_new, and t = a + u^a - R x again.
 template <typename T, bool BATCH>
 __global__ __launch_bounds__(256) void k_rescale(const RescaleArgs<T>* __restrict__ dev,
@@ -462,6 +382,9 @@ SliceJob<T> make_job(const dect_plan* p, const void* mh, const void* ml, const v
         J.pre1.z = zb;
     }
     J.tv = TvArgs<T>{p->nx, p->ny, x, y, uy, dy, z, uz, dz, scal, P.img};
+    // The TV/z/dual update runs in the a-update's launch, after its blocks.
+    u.udm_blocks = (int)nblk(p->M);
+    u.tv = J.tv;
     // The iterations keep R^T t tracked in h + u, not t itself (t is set at the start).
     J.resc = RescaleArgs<T>{p->M, p->N, p->sym, p->Vb, p->D, ua, nullptr, a, Rx, uy, uz, scal,
                             hh, uu};
@@ -526,15 +449,11 @@ hipError_t iteration_t(const SliceJob<T>& J, const JobArrays<T>* dev, int nsl,
         }
         DECT_TRY(hipGetLastError());
     }
+    // The a-update (Eq. (13)) and, in the same launch, the TV/z/dual update.
     if (dev)
-        DECT_TRY(launch_udm_batch<T>(dev->udm, nsl, (int)nblk(J.M), s));
+        DECT_TRY(launch_udm_batch<T>(dev->udm, nsl, (int)(nblk(J.M) + nblk(J.N)), s));
     else
         DECT_TRY(launch_udm<T>(nullptr, 2, J.udm, s));
-    {
-        ProfScope ps("tv_dual", s);
-        hipLaunchKernelGGL((k_tv_dual<T, BATCH>), gN, dim3(256), 0, s, dev ? dev->tv : nullptr, J.tv);
-    }
-    DECT_TRY(hipGetLastError());
     // R^T da: the dual residual (adaptive rho) and the tracked h in every mode.
     DECT_TRY(launch_backproject_admm<T>(J.sym, J.bp_waves, EPI_DUAL, dev ? dev->dual : nullptr,
                                         J.dual, nsl, J.bp_gx, J.bp_gy, s));

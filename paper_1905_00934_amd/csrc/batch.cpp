@@ -29,7 +29,7 @@ bool same_shape(const SliceJob<T>& a, const SliceJob<T>& b) {
 // Byte offsets of the ten argument arrays of a group of n slices.
 template <typename T>
 struct ArrayOffsets {
-    size_t orb, prj, rhs, q, dual, udm, vec, tv, resc, red, pre0, pre1, end;
+    size_t orb, prj, rhs, q, dual, udm, vec, resc, red, pre0, pre1, end;
     ArrayOffsets(size_t base, size_t n) {
         size_t off = base;
         auto take = [&](size_t bytes) {
@@ -44,7 +44,6 @@ struct ArrayOffsets {
         dual = take(n * sizeof(BpArgs<T>));
         udm = take(n * sizeof(UdmArgs<T>));
         vec = take(n * sizeof(VecArgs<T>));
-        tv = take(n * sizeof(TvArgs<T>));
         resc = take(n * sizeof(RescaleArgs<T>));
         red = take(n * sizeof(RedArgs));
         pre0 = take(n * sizeof(PrecArgs<T>));
@@ -111,7 +110,6 @@ hipError_t Runner<T>::set(const std::vector<SliceJob<T>>& jobs) {
             put(h, o.dual, k, J.dual);
             put(h, o.udm, k, J.udm);
             put(h, o.vec, k, J.vec);
-            put(h, o.tv, k, J.tv);
             put(h, o.resc, k, J.resc);
             put(h, o.red, k, J.red);
             put(h, o.pre0, k, J.pre0);
@@ -124,7 +122,6 @@ hipError_t Runner<T>::set(const std::vector<SliceJob<T>>& jobs) {
         g.dev.dual = reinterpret_cast<BpArgs<T>*>(b + o.dual);
         g.dev.udm = reinterpret_cast<UdmArgs<T>*>(b + o.udm);
         g.dev.vec = reinterpret_cast<VecArgs<T>*>(b + o.vec);
-        g.dev.tv = reinterpret_cast<TvArgs<T>*>(b + o.tv);
         g.dev.resc = reinterpret_cast<RescaleArgs<T>*>(b + o.resc);
         g.dev.red = reinterpret_cast<RedArgs*>(b + o.red);
         g.dev.pre0 = reinterpret_cast<PrecArgs<T>*>(b + o.pre0);

@@ -193,6 +193,20 @@ void fill_bp_plan(const dect_plan* p, BpArgs<T>& a);
 // Per-ray decomposition.  mode 0: standalone call; 1: ADMM initialisation; 2: ADMM a-step;
 // 3: constrained decomposition (a >= 0, no rho terms) from the projected linearised start.
 template <typename T>
+struct TvArgs {
+    int nx, ny;
+    const T* x;
+    T* y;
+    T* uy;
+    T* dy;
+    T* z;
+    T* uz;
+    T* dz;
+    const double* scal;
+    double* partials;
+};
+
+template <typename T>
 struct UdmArgs {
     const T* spec;     // spectral tables (plan)
     int kmax, kh, kl;
@@ -219,6 +233,10 @@ struct UdmArgs {
     int iters;
     double mu0;
     double lin[4];       // inverse of the linearisation matrix (init)
+    // ADMM a-step: blocks from udm_blocks on run the TV/z/dual update of the image
+    // (independent of the a-update) in the same launch; tv.x = nullptr: none.
+    int udm_blocks;
+    TvArgs<T> tv;
 };
 
 template <typename T>
@@ -268,19 +286,6 @@ struct VecArgs {
 };
 
 // Shrinkage, nonnegativity and the y, z duals (Eq. (9)-(11)).
-template <typename T>
-struct TvArgs {
-    int nx, ny;
-    const T* x;
-    T* y;
-    T* uy;
-    T* dy;
-    T* z;
-    T* uz;
-    T* dz;
-    const double* scal;
-    double* partials;
-};
 
 // Dual rescale after a change of rho.
 template <typename T>
@@ -346,7 +351,6 @@ struct JobArrays {
     BpArgs<T>* dual;
     UdmArgs<T>* udm;
     VecArgs<T>* vec;
-    TvArgs<T>* tv;
     RescaleArgs<T>* resc;
     RedArgs* red;
     PrecArgs<T>* pre0;

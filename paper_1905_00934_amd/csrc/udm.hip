@@ -12,6 +12,7 @@
 #include "common.h"
 #include "kernels.h"
 #include "profile.h"
+#include "tv.h"
 
 namespace dect {
 
@@ -37,9 +38,15 @@ template <> struct Cst<double> {
 // overflow threshold and the largest above underflow.  With exact = true M is
 // the largest exponent (one extra pass); otherwise the caller's M is used.
 template <typename T>
-__device__ inline void spectrum_eval(const T* __restrict__ lw, const T* __restrict__ kc,
-                                     const T* __restrict__ kp, int n, T ac, T ap, T shift,
+__device__ inline void spectrum_eval(const T* __restrict__ lw_, const T* __restrict__ kc_,
+                                     const T* __restrict__ kp_, int n, T ac, T ap, T shift,
                                      bool exact, T& f, T& gc, T& gp) {
+    // The tables are read-only for the whole launch: read them through the constant
+    // address space, so they stay on scalar loads whatever else the kernel stores.
+    using CT = const __attribute__((address_space(4))) T;
+    CT* lw = (CT*)lw_;
+    CT* kc = (CT*)kc_;
+    CT* kp = (CT*)kp_;
     constexpr T ln2 = T(0.6931471805599453);
     T m = shift;
     if (exact) {
@@ -173,6 +180,13 @@ __global__ __launch_bounds__(256) void k_udm(const UdmArgs<T>* __restrict__ dev,
     using V2 = vec<T, 2>;
     using V4 = vec<T, 4>;
     const UdmArgs<T> A = pick_args<BATCH>(dev, one);
+    if constexpr (MODE == 2) {
+        // Blocks past the a-update's run the image's TV/z/dual update.
+        if ((int)blockIdx.x >= A.udm_blocks) {
+            if (A.tv.x) tv_dual_block<T>(A.tv, (long)blockIdx.x - A.udm_blocks);
+            return;
+        }
+    }
     const T* __restrict__ spec = A.spec;
     const int kmax = A.kmax, kh = A.kh, kl = A.kl;
     const StepBound sb{A.kc_max, A.kp_max};
@@ -343,7 +357,9 @@ template <typename T>
 hipError_t launch_udm(const dect_plan* p, int mode, const UdmArgs<T>& a0, hipStream_t s) {
     UdmArgs<T> a = a0;
     if (p) fill_udm_tables<T>(p, a);  // else the tables are already in a
-    dim3 g((unsigned)((a.M + 255) / 256));
+    a.udm_blocks = (int)((a.M + 255) / 256);
+    const long tvb = mode == 2 && a.tv.x ? ((long)a.tv.nx * a.tv.ny + 255) / 256 : 0;
+    dim3 g((unsigned)(a.udm_blocks + tvb));
     ProfScope ps(mode == 1 ? "udm_init" : (mode == 3 ? "cdm" : "udm"), s);
     if (mode == 0)
         hipLaunchKernelGGL((k_udm<T, 0, false>), g, dim3(256), 0, s, nullptr, a);
