@@ -26,7 +26,7 @@ HBM_PEAK_GBS = 8000.0
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "admm_fan512_hbm_traffic.txt")
-KERNEL_SOURCES = ["tomo.hip", "udm.hip", "admm.hip", "kernels.h", "common.h"]
+KERNEL_SOURCES = ["tomo.hip", "udm.hip", "admm.hip", "kernels.h", "common.h", "epilogue.h", "tv.h"]
 
 
 def kernel_source_hash() -> str:
