@@ -72,6 +72,30 @@ def _setup(dect, dtype, params, mix):
     return out
 
 
+# Same image, ray count and grid sizes but different views and bins: the two plans
+# fall into one launch group, whose kernels must take each slice's own sizes.
+SMALL["sym_fan64_v120"] = S.fan_geometry_fov(64, 120, 96, fov_cm=25.6, src_iso_cm=40.0,
+                                             src_det_cm=70.0)
+SMALL["sym_fan64_v128"] = S.fan_geometry_fov(64, 128, 90, fov_cm=25.6, src_iso_cm=40.0,
+                                             src_det_cm=70.0)
+
+
+@pytest.mark.parametrize("dtype", [F32, F64])
+def test_batch_group_of_different_view_and_bin_counts(dect, dtype):
+    params = dect.AdmmParams(cg_iters=2)
+    mix = [("sym_fan64_v120", 5), ("sym_fan64_v128", 6), ("sym_fan64_v120", 7)]
+    sl = _setup(dect, dtype, params, mix)
+    b = dect.Batch([(p, m, bs) for p, m, _, bs in sl], params, graph=True)
+    assert b.groups == 1
+    b.iterate(3)
+    for p, m, alone, _ in sl:
+        p.admm_iterate(m, alone, params, 3)
+    torch.cuda.synchronize()
+    for k, (p, m, alone, batched) in enumerate(sl):
+        assert torch.equal(alone.buf, batched.buf), f"slice {k} ({mix[k][0]}) differs"
+    b.close()
+
+
 @pytest.mark.parametrize("dtype", [F32, F64])
 @pytest.mark.parametrize("graph", [False, True])
 def test_batch_slices_equal_alone(dect, dtype, graph):
