@@ -72,6 +72,39 @@ __global__ __launch_bounds__(256) void k_cg_step(const VecArgs<T>* __restrict__ 
     if constexpr (FULL) block_sum_store<2>(part, A.partials + (size_t)blockIdx.x * kPartialSlots);
 }
 
+// The last CG step of an outer iteration, with its alpha reduction: every block sums
+// the block partials of r . z and p . q in the same fixed order (so all obtain the same
+// alpha, and block 0 stores gamma, p . q and alpha), then x += alpha p and
+// h -= alpha R^T R p over the image (grid-stride).
+template <typename T, bool BATCH>
+__global__ __launch_bounds__(256) void k_cg_last(const VecArgs<T>* __restrict__ dev, VecArgs<T> one) {
+    using V2 = vec<T, 2>;
+    const VecArgs<T> A = pick_args<BATCH>(dev, one);
+    double g[2], pq[2], al[2];
+    partial_sum<2>(A.g_part, A.nb_g, g);
+    partial_sum<2>(A.pq_part, A.nb_pq, pq);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) al[c] = (pq[c] > 0.0 && g[c] > 0.0) ? g[c] / pq[c] : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        for (int c = 0; c < 2; ++c) {
+            A.scal[S_GAMMA + c] = g[c];
+            A.scal[S_PQ + c] = pq[c];
+            A.scal[S_ALPHA + c] = al[c];
+        }
+    const T alt[2] = {(T)al[0], (T)al[1]};
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < A.N;
+         i += (long)gridDim.x * blockDim.x) {
+        V2 xv = reinterpret_cast<V2*>(A.x)[i];
+        const V2 pv = reinterpret_cast<const V2*>(A.p)[i];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) xv.v[c] += alt[c] * pv.v[c];
+        reinterpret_cast<V2*>(A.x)[i] = xv;
+        const V2 rr = reinterpret_cast<const V2*>(A.rtrp)[i];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) A.h[2 * i + c] -= al[c] * (double)rr.v[c];
+    }
+}
+
 // R x += alpha R p (tracking, so no extra projection of x is needed).
 template <typename T, bool BATCH>
 __global__ __launch_bounds__(256) void k_rx_step(const VecArgs<T>* __restrict__ dev, VecArgs<T> one) {
@@ -371,7 +404,8 @@ SliceJob<T> make_job(const dect_plan* p, const void* mh, const void* ml, const v
     u.iters = prm->lm_iters;
     u.mu0 = prm->lm_mu0;
     J.vec = VecArgs<T>{p->N, p->M, p->sym, p->Vb, p->D, x, pp, r, pre ? zb : r, q, Rx, Rp, scal,
-                       P.img, hh, rtrp};
+                       P.img, hh, rtrp, pre ? P.pre : P.img, pre ? p->nb_pre : p->nb_img,
+                       P.tiles, p->nb_tiles};
     if (pre) {
         fill_precond_plan<T>(p, J.pre0);
         J.pre0.W = at<T>(st, p->off_fftw);
@@ -435,8 +469,8 @@ hipError_t iteration_t(const SliceJob<T>& J, const JobArrays<T>* dev, int nsl,
                                         J.pj_gy, s));
         DECT_TRY(launch_backproject_admm<T>(J.sym, J.bp_waves, EPI_Q, dev ? dev->q : nullptr, J.q,
                                             nsl, J.bp_gx, J.bp_gy, s));
-        DECT_TRY(reduce(RED_ALPHA));
         if (c < n - 1) {
+            DECT_TRY(reduce(RED_ALPHA));
             ProfScope ps("cg_vector", s);
             hipLaunchKernelGGL((k_rx_step<T, BATCH>), gM, dim3(256), 0, s, dvec, J.vec);
             hipLaunchKernelGGL((k_cg_step<T, true, BATCH>), gN, dim3(256), 0, s, dvec, J.vec);
@@ -444,8 +478,10 @@ hipError_t iteration_t(const SliceJob<T>& J, const JobArrays<T>* dev, int nsl,
             DECT_TRY(reduce(RED_BETA));
             hipLaunchKernelGGL((k_p_step<T, BATCH>), gN, dim3(256), 0, s, dvec, J.vec);
         } else {
+            // alpha is formed inside the step (its partials are still in place).
             ProfScope ps("cg_vector", s);
-            hipLaunchKernelGGL((k_cg_step<T, false, BATCH>), gN, dim3(256), 0, s, dvec, J.vec);
+            const unsigned blocks = nblk(J.N) < 256 ? nblk(J.N) : 256;
+            hipLaunchKernelGGL((k_cg_last<T, BATCH>), dim3(blocks, 1, z), dim3(256), 0, s, dvec, J.vec);
         }
         DECT_TRY(hipGetLastError());
     }

@@ -279,10 +279,16 @@ struct VecArgs {
     const T* q;
     T* Rx;
     const T* Rp;
-    const double* scal;
+    double* scal;       // device scalars; the last CG step of an iteration stores alpha
     double* partials;   // image partials
     double* h;          // tracked R^T (a - R x): minus alpha R^T R p per CG step
     const T* rtrp;      // R^T R p of the current CG step
+    // Block partials of r . z (r . r without the preconditioner) and of p . q, from
+    // which the last CG step of an iteration forms alpha itself.
+    const double* g_part;
+    int nb_g;
+    const double* pq_part;
+    int nb_pq;
 };
 
 // Shrinkage, nonnegativity and the y, z duals (Eq. (9)-(11)).
