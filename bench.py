@@ -30,11 +30,17 @@ KERNEL_SOURCES = ["tomo.hip", "udm.hip", "admm.hip", "kernels.h", "common.h", "e
 
 
 def kernel_source_hash() -> str:
+    """Hash of the kernel sources without their // comments and blank lines, so that
+    an edit of a comment does not retire counters taken on the same code."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_1905_00934_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1905_00934_amd", "csrc", f), encoding="utf-8") as fh:
+            for line in fh:
+                code = re.sub(r"//.*$", "", line).rstrip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

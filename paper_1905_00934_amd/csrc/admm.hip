@@ -3,12 +3,13 @@
 //
 // Per outer iteration (n CG steps, m LM steps), all on the caller's stream and
 // with every scalar (CG step sizes, rho, dual rescale) kept in device memory:
-//   R^T t + image terms -> r0 = p0, |r0|^2          (Eq. (12) right-hand side)
-//   n x { R p ; R^T R p + D^T D p + p ; alpha ; x += alpha p, R x += alpha R p ; beta }
-//   per-ray LM on Eq. (13), u^a and next t           (fused, one lane per ray)
-//   y, z, u^y, u^z (Eq. (9)-(11)), residual partials (fused, one lane per pixel)
-//   [adaptive rho] R^T da + D^T dy + dz              (dual residual)
-//   residual balancing, rho, dual rescale            (one block)
+//   R^T t + image terms -> r0 = p0, |r0|^2          (Eq. (12) right-hand side; R^T t is
+//                                                    tracked as h + u, no transpose)
+//   n x { R p ; R^T R p + D^T D p + p ; alpha ; x += alpha p, h -= alpha R^T R p ; beta }
+//   per-ray LM on Eq. (13) with R x += alpha R p and u^a (one lane per ray), and in
+//   the same launch y, z, u^y, u^z (Eq. (9)-(11)) with their partials (one lane per pixel)
+//   R^T da + D^T dy + dz                             (dual residual; R^T da also goes to h)
+//   residual balancing, rho, dual rescale            (one block, then elementwise)
 #include <cmath>
 #include <cstring>
 
