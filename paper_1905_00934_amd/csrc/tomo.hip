@@ -79,6 +79,63 @@ __global__ __launch_bounds__(256) void k_orbit(const OrbitArgs<T>* __restrict__ 
         orbit_record<T, CH, SYM>(X, nx, (int)(idx / ny), (int)(idx % ny));
 }
 
+// The same two orbit images for the quarter-turn symmetric square image, by tiles of
+// TS x TS pixels: the four rotated TS x TS regions of X that a tile's records draw on
+// are loaded into LDS with coalesced reads (each along its own contiguous axis), then
+// the tile's records are written to O along i and to OT along j, both coalesced.
+template <typename T, int CH, bool BATCH>
+__global__ __launch_bounds__(256) void k_orbit_tiled(const OrbitArgs<T>* __restrict__ dev,
+                                                     OrbitArgs<T> one) {
+    using X1 = vec<T, CH>;
+    using R = vec<T, CH * 4>;
+    constexpr int TS = 16;
+    __shared__ X1 xs[4][TS][TS + 1];  // xs[k][a][b] = X at rot^k(i0 + b, j0 + a)
+    const OrbitArgs<T> A = pick_args<BATCH>(dev, one);
+    const int n = A.nx;
+    const int tiles = (n + TS - 1) / TS;
+    if ((int)blockIdx.x >= tiles * tiles) return;  // beyond this slice (whole block)
+    const int i0 = (int)(blockIdx.x % tiles) * TS, j0 = (int)(blockIdx.x / tiles) * TS;
+    const X1* __restrict__ X = reinterpret_cast<const X1*>(A.X);
+    for (int t = threadIdx.x; t < TS * TS; t += blockDim.x) {
+        const int u = t / TS, w = t % TS;  // w is the fast index of this pass
+        // rot^0 (i, j) and rot^2 (n-1-i, n-1-j): X rows follow a, columns follow b.
+        // rot^1 (n-1-j, i) and rot^3 (j, n-1-i): X rows follow b, columns follow a.
+        {
+            const int a = u, b = w, i = i0 + b, j = j0 + a;
+            if (i < n && j < n) {
+                xs[0][a][b] = X[(size_t)j * n + i];
+                xs[2][a][b] = X[(size_t)(n - 1 - j) * n + (n - 1 - i)];
+            }
+        }
+        {
+            const int b = u, a = w, i = i0 + b, j = j0 + a;
+            if (i < n && j < n) {
+                xs[1][a][b] = X[(size_t)i * n + (n - 1 - j)];
+                xs[3][a][b] = X[(size_t)(n - 1 - i) * n + j];
+            }
+        }
+    }
+    __syncthreads();
+    auto rec = [&](int a, int b) {
+        R o;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int c = 0; c < CH; ++c) o.v[k * CH + c] = xs[k][a][b].v[c];
+        return o;
+    };
+    for (int t = threadIdx.x; t < TS * TS; t += blockDim.x) {
+        {
+            const int a = t / TS, b = t % TS, i = i0 + b, j = j0 + a;  // along i
+            if (i < n && j < n) reinterpret_cast<R*>(A.O)[(size_t)j * n + i] = rec(a, b);
+        }
+        {
+            const int b = t / TS, a = t % TS, i = i0 + b, j = j0 + a;  // along j
+            if (i < n && j < n) reinterpret_cast<R*>(A.OT)[(size_t)i * n + j] = rec(a, b);
+        }
+    }
+}
+
 // R for base rays: QUAD = true writes [Vb][D][SYM][CH] records, false writes the
 // standard [V][D][CH] layout (view v + k*Vb for rotation k).  A workgroup owns
 // 64 / kProjViews consecutive bins of kProjViews consecutive base views (one ray
@@ -588,8 +645,15 @@ void project_launch(const OrbitArgs<T>* odev, const OrbitArgs<T>& oone, const Pr
                     const ProjArgs<T>& pone, int n, long pixels, int gx, int gy, hipStream_t s) {
     {
         ProfScope pt("orbit", s);
-        hipLaunchKernelGGL((k_orbit<T, CH, SYM, BATCH>), dim3((unsigned)((pixels + 255) / 256), 1, n),
-                           dim3(256), 0, s, odev, oone);
+        if constexpr (SYM == 4) {
+            constexpr int TS = 16;
+            const unsigned tiles = (unsigned)((oone.nx + TS - 1) / TS);
+            hipLaunchKernelGGL((k_orbit_tiled<T, CH, BATCH>), dim3(tiles * tiles, 1, n), dim3(256),
+                               0, s, odev, oone);
+        } else {
+            hipLaunchKernelGGL((k_orbit<T, CH, SYM, BATCH>), dim3((unsigned)((pixels + 255) / 256), 1, n),
+                               dim3(256), 0, s, odev, oone);
+        }
     }
     ProfScope pp("project", s);
     hipLaunchKernelGGL((k_project<T, CH, SYM, QUAD, KS, BATCH>), dim3(proj_blocks(gx, gy), 1, n), dim3(64 * KS),
