@@ -135,8 +135,9 @@ __device__ inline void partial_sum(const double* __restrict__ base, int nb, doub
 // Projector workgroups: 64 / kProjViews consecutive bins of kProjViews consecutive
 // base views (lane = bin * kProjViews + view), so the lanes of a wave read nearby
 // image rows at every step.
+// Measured at 512^2 / 720 x 1024: 4 views (16 bins) 142 us, 8 views 146 us, 16 views 153 us.
 #ifndef DECT_PJ_VIEWS
-#define DECT_PJ_VIEWS 8
+#define DECT_PJ_VIEWS 4
 #endif
 constexpr int kProjViews = DECT_PJ_VIEWS;
 static_assert(kProjViews == 1 || kProjViews == 2 || kProjViews == 4 || kProjViews == 8 ||
@@ -152,8 +153,9 @@ __host__ __device__ inline int proj_grid_y(int Vb) { return (Vb + kProjViews - 1
 // narrow annuli of the image, whose part of the orbit images its L2 can hold, and
 // each XCD still gets bins from across the whole detector, so the XCDs' shares of
 // ray length balance.  Measured at 512^2 / 720 x 1024: chunks of 1, 2, 4, 8 and 16
-// bin groups take 146, 149, 153, 160 and 244 us against 163 us in the plain
-// bins-then-views order; 16 leaves one chunk per XCD and unequal ray lengths.
+// bin groups (of 8 bins, 8 views per wave) took 146, 149, 153, 160 and 244 us against
+// 163 us in the plain bins-then-views order; 16 leaves one chunk per XCD and unequal
+// ray lengths.
 #ifndef DECT_PJ_CHUNK
 #define DECT_PJ_CHUNK 1
 #endif
