@@ -51,11 +51,11 @@ __device__ inline void spectrum_eval(const T* __restrict__ lw_, const T* __restr
     T m = shift;
     if (exact) {
         m = -INFINITY;
-#pragma unroll 4
+#pragma unroll 8
         for (int k = 0; k < n; ++k) m = fmax(m, lw[k] - kc[k] * ac - kp[k] * ap);
     }
     T z = T(0), sc = T(0), sp = T(0);
-#pragma unroll 4
+#pragma unroll 8
     for (int k = 0; k < n; ++k) {
         const T q = Cst<T>::exp2((lw[k] - m) - kc[k] * ac - kp[k] * ap);
         z += q;
