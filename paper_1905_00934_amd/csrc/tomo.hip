@@ -140,8 +140,8 @@ __global__ __launch_bounds__(256) void k_orbit_tiled(const OrbitArgs<T>* __restr
 // standard [V][D][CH] layout (view v + k*Vb for rotation k).  A workgroup owns
 // 64 / kProjViews consecutive bins of kProjViews consecutive base views (one ray
 // per lane), in the XCD-aware order of proj_blocks; its KS waves step through KS
-// disjoint ranges of image lines (so the lanes of a wave read one image line
-// together) and wave 0 adds the KS partial sums in order.
+// disjoint ranges of the image lines its rays cross (so the lanes of a wave read
+// one image line together) and wave 0 adds the KS partial sums in order.
 template <typename T, int CH, int SYM, bool QUAD, int KS, bool BATCH>
 __global__ __launch_bounds__(64 * KS) void k_project(const ProjArgs<T>* __restrict__ dev,
                                                      ProjArgs<T> one) {
@@ -183,8 +183,20 @@ __global__ __launch_bounds__(64 * KS) void k_project(const ProjArgs<T>* __restri
     } else if (!(r.phi0 >= T(-1) && r.phi0 < T(n_lines))) {
         k1 = -1;
     }
-    // This wave's share of the lines.
-    const int c0 = (int)((long)wave * n_steps / KS), c1 = (int)((long)(wave + 1) * n_steps / KS) - 1;
+    // This wave's share of the lines: every wave holds the same 64 rays, so each
+    // computes the same union [s0, s1] of their ranges and takes its KS-th of it
+    // (an even split of all lines would leave most waves idle on short chords).
+    // An empty union gives [0, -1], so no wave enters the sample loops.
+    const bool any = valid && k0 <= k1;
+    int s0 = any ? k0 : 1 << 30, s1 = any ? k1 : -1;
+    for (int off = 32; off > 0; off >>= 1) {
+        const int a = __shfl_xor(s0, off, 64), c = __shfl_xor(s1, off, 64);
+        s0 = a < s0 ? a : s0;
+        s1 = c > s1 ? c : s1;
+    }
+    if (s1 < s0) s0 = 0, s1 = -1;
+    const int len = s1 - s0 + 1;
+    const int c0 = s0 + wave * len / KS, c1 = s0 + (wave + 1) * len / KS - 1;
     k0 = k0 > c0 ? k0 : c0;
     k1 = k1 < c1 ? k1 : c1;
     if (!valid) k1 = -1;
