@@ -135,9 +135,11 @@ __device__ inline void partial_sum(const double* __restrict__ base, int nb, doub
 // Projector workgroups: 64 / kProjViews consecutive bins of kProjViews consecutive
 // base views (lane = bin * kProjViews + view), so the lanes of a wave read nearby
 // image rows at every step.
-// Measured at 512^2 / 720 x 1024: 4 views (16 bins) 142 us, 8 views 146 us, 16 views 153 us.
+// Measured at 512^2 / 720 x 1024 with 8 waves, each taking its share of the lines the
+// workgroup's rays cross: 1 view (64 bins) 147 us, 2 views (32 bins) 120 us, 4 views
+// 141 us, 8 views 145 us.
 #ifndef DECT_PJ_VIEWS
-#define DECT_PJ_VIEWS 4
+#define DECT_PJ_VIEWS 2
 #endif
 constexpr int kProjViews = DECT_PJ_VIEWS;
 static_assert(kProjViews == 1 || kProjViews == 2 || kProjViews == 4 || kProjViews == 8 ||

@@ -74,16 +74,18 @@ def _setup(dect, dtype, params, mix):
 
 # Same image, ray count and grid sizes but different views and bins: the two plans
 # fall into one launch group, whose kernels must take each slice's own sizes.
-SMALL["sym_fan64_v120"] = S.fan_geometry_fov(64, 120, 96, fov_cm=25.6, src_iso_cm=40.0,
+# 124 x 96 and 128 x 93 rays: 11904 each, 31 and 32 base views, projector grids of
+# 3 x 16 workgroups at 2 base views per wave (4 x 8 at 4).
+SMALL["sym_fan64_v124"] = S.fan_geometry_fov(64, 124, 96, fov_cm=25.6, src_iso_cm=40.0,
                                              src_det_cm=70.0)
-SMALL["sym_fan64_v128"] = S.fan_geometry_fov(64, 128, 90, fov_cm=25.6, src_iso_cm=40.0,
+SMALL["sym_fan64_v128"] = S.fan_geometry_fov(64, 128, 93, fov_cm=25.6, src_iso_cm=40.0,
                                              src_det_cm=70.0)
 
 
 @pytest.mark.parametrize("dtype", [F32, F64])
 def test_batch_group_of_different_view_and_bin_counts(dect, dtype):
     params = dect.AdmmParams(cg_iters=2)
-    mix = [("sym_fan64_v120", 5), ("sym_fan64_v128", 6), ("sym_fan64_v120", 7)]
+    mix = [("sym_fan64_v124", 5), ("sym_fan64_v128", 6), ("sym_fan64_v124", 7)]
     sl = _setup(dect, dtype, params, mix)
     b = dect.Batch([(p, m, bs) for p, m, _, bs in sl], params, graph=True)
     assert b.groups == 1
