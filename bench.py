@@ -26,7 +26,8 @@ HBM_PEAK_GBS = 8000.0
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "admm_fan512_hbm_traffic.txt")
-KERNEL_SOURCES = ["tomo.hip", "udm.hip", "admm.hip", "kernels.h", "common.h", "epilogue.h", "tv.h"]
+KERNEL_SOURCES = ["tomo.hip", "udm.hip", "admm.hip", "kernels.h", "common.h", "epilogue.h", "tv.h",
+                  "reduce.h", "projidx.h"]
 
 
 def kernel_source_hash() -> str:
@@ -59,6 +60,36 @@ def counted_traffic() -> dict:
         else:
             meta[parts[0]] = parts[1]
     return table if meta.get("source_hash") == kernel_source_hash() else {}
+
+
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "admm_fan512_counters.txt")
+
+
+def binding_unit(kernel: str) -> dict | None:
+    """Busy fractions of the VALU and the texture addresser (the vector-memory path)
+    of a kernel from the committed counter summary, while the kernel sources are the
+    ones the counters were taken on."""
+    if not os.path.exists(COUNTERS_FILE):
+        return None
+    meta, rows = {}, {}
+    for line in open(COUNTERS_FILE):
+        parts = line.split()
+        if not parts:
+            continue
+        if parts[0] == "#" and len(parts) >= 3 and parts[1] == "source_hash":
+            meta["source_hash"] = parts[2]
+        elif parts[0].startswith("k_") and len(parts) >= 9:
+            rows[parts[0]] = {"valu_busy": float(parts[4]), "ta_busy": float(parts[6])}
+    if meta.get("source_hash") != kernel_source_hash():
+        return None
+    name = {"project": "k_project", "backproject_q": "k_backproject", "backproject_dual":
+            "k_backproject"}.get(kernel)
+    for k, v in rows.items():
+        if name and k.startswith(name + "<"):
+            unit = "texture addresser (vector-memory path)" if v["ta_busy"] >= v["valu_busy"] \
+                else "VALU issue"
+            return {**v, "busiest": unit, "source": os.path.relpath(COUNTERS_FILE, ROOT)}
+    return None
 
 
 def algorithmic_bytes(N: int, M: int, cg_iters: int, elem: int = 4) -> dict:
@@ -154,20 +185,33 @@ def parse():
                     help="timed iterations of the batched workloads")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrivals per s")
-    ap.add_argument("--serve-seconds", type=float, default=4.0, help="arrival window, s")
+    ap.add_argument("--serve-seconds", type=float, default=60.0, help="arrival window, s")
     ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--serve-queue", type=int, default=256,
+                    help="queue bound of the 200 req/s run (requests beyond it are shed)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device-to-device copy (reference for "
                          "hardware byte counters)")
-    ap.add_argument("--launch", default=None, metavar="BP,PJ",
-                    help="fix the waves per workgroup of the transpose and the projector "
-                         "(2, 4 or 8) instead of tuning them, e.g. for counter passes")
+    ap.add_argument("--launch", default=None, metavar="BP,PJ[,VIEWS,CHUNK]",
+                    help="fix the launch shapes instead of tuning them (waves per workgroup "
+                         "of the transpose and the projector, 2, 4 or 8; the projector's "
+                         "views per wave and XCD chunk), e.g. for counter passes")
     return ap.parse_args()
 
 
-def cpu_baseline(pr, iters: int):
-    """The FP64 oracle on the host cores: `iters` ADMM iterations of the same slice."""
-    import oracle as O
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_admm_rate(O, pr, iters: int):
+    """ADMM iterations/s of the FP64 oracle on one problem, after its initialisation."""
     orc = O.Oracle(pr.geom, pr.spec)
     mh, wh = O.ingest(pr.counts_high, pr.i0)
     ml, wl = O.ingest(pr.counts_low, pr.i0)
@@ -176,10 +220,36 @@ def cpu_baseline(pr, iters: int):
     t0 = time.perf_counter()
     orc.admm_iterate(st, mh, ml, wh, wl, prm, iters)
     dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": iters / dt, "unit": "iter/s", "cores": cores, "kind": "oracle",
+    return iters / dt, dt
+
+
+def cpu_baseline(pr, iters: int):
+    """The FP64 oracle on the host cores: `iters` ADMM iterations of the same 512x512
+    slice on all threads (the reported value) and one iteration on one thread, and the
+    tiny 64x64 parallel-beam problem in full (20 iterations) on both."""
+    import oracle as O
+    from paper_1905_00934_amd import synth
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    O.set_threads(threads)
+    rate, dt = _oracle_admm_rate(O, pr, iters)
+    tiny = synth.tiny_problem(0)
+    tiny_all, tiny_all_s = _oracle_admm_rate(O, tiny, 20)
+    O.set_threads(1)
+    rate1, dt1 = _oracle_admm_rate(O, pr, 1)
+    tiny_1, tiny_1_s = _oracle_admm_rate(O, tiny, 20)
+    O.set_threads(threads)
+    return {"value": round(rate, 4), "unit": "iter/s", "cores": threads, "kind": "oracle",
             "sample": f"{iters} ADMM iterations (UDM1-CG1, adaptive rho, FP64) of the same "
-                      f"512x512 slice after its initialisation; {dt:.1f} s"}
+                      f"512x512 slice after its initialisation, {threads} threads: {dt:.1f} s",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "one_thread": {"value": round(rate1, 4), "unit": "iter/s",
+                           "sample": f"1 iteration of the 512x512 slice: {dt1:.1f} s"},
+            "tiny64_full": {"iterations": 20, "all_threads_iter_per_s": round(tiny_all, 3),
+                            "all_threads_s": round(tiny_all_s, 2),
+                            "one_thread_iter_per_s": round(tiny_1, 3),
+                            "one_thread_s": round(tiny_1_s, 2),
+                            "workload": "64x64 parallel beam, 90 views x 95 bins, FP64, "
+                                        "20 ADMM iterations (the whole tiny configuration)"}}
 
 
 def batch_workload(dect, torch, dev, items, params, steps, warmup):
@@ -187,12 +257,14 @@ def batch_workload(dect, torch, dev, items, params, steps, warmup):
     slices; both start from the same initial states."""
     from paper_1905_00934_amd import synth
     spec = synth.default_spectra()
-    plans, slices = {}, []
+    plans, slices, tuned_shapes = {}, [], {}
     for _, _, geom, i0, ch, cl in items:
         key = (geom["nx"], geom["ny"], geom["n_views"], geom["n_det"])
         if key not in plans:
             plans[key] = dect.Plan(geom, spec, torch.float32, device=dev)
-            plans[key].tune()
+            t = plans[key].tune()
+            tuned_shapes[key] = {k: (round(v, 2) if isinstance(v, float) else v)
+                                 for k, v in t.items()}
         plan = plans[key]
         c = [torch.from_numpy(x).to(dev) for x in (ch, cl)]
         meas = list(plan.ingest(c[0], c[1], i0))
@@ -231,15 +303,18 @@ def batch_workload(dect, torch, dev, items, params, steps, warmup):
                            out["plain"]["slice_iters_per_s"], 4)
     out["identical_states"] = identical
     out["groups"] = len(plans)
-    out["launch"] = {f"{k[0]}x{k[1]}/{k[2]}x{k[3]}": p.launch() for k, p in plans.items()}
+    out["launch"] = {f"{k[0]}x{k[1]}/{k[2]}x{k[3]}": tuned_shapes[k] for k in plans}
     out["kernels_per_batch_iter_us"] = {k: round(1e3 * v[0] / 2, 2) for k, v in kt.items()}
     return out
 
 
 def serve_workload(dect, torch, dev, items, args):
-    """Requests of the uneven mix (relative objective change 1e-4, at most 100
-    iterations, checks every 5): plain one-slice-at-a-time processing against the
-    continuous-batching server, closed and with Poisson arrivals."""
+    """Requests drawn from the uneven mix's 96 slices (relative objective change 1e-4, at
+    most 100 iterations, checks every 5): plain one-slice-at-a-time processing against
+    the continuous-batching server, all at once and with Poisson arrivals: at the
+    configured 200 req/s (above capacity: the server's queue is bounded, so it sheds
+    load; throughput is the saturated capacity and the latency that of served requests)
+    and at 70 % of the measured capacity, each over a window of --serve-seconds."""
     import numpy as np
     from paper_1905_00934_amd import synth
     spec = synth.default_spectra()
@@ -259,53 +334,88 @@ def serve_workload(dect, torch, dev, items, args):
         meas = list(plan.ingest(c[0], c[1], i0))
         st = plan.new_state()
         plan.admm_init(meas, st, params)
-        it, phis = 0, []
+        it, phis, rels = 0, [], []
         while True:
             n = min(step, max_iters - it)
             log = plan.admm_iterate(meas, st, params, n, log=True)
             it += n
             phis += [e["data"] + e["tv"] for e in log]
             rel = abs(phis[-1] - phis[-2]) / abs(phis[-1]) if len(phis) >= 2 else math.inf
+            rels.append(rel)
             if rel <= tol or it >= max_iters:
-                return st.x.cpu().numpy(), it
+                return st.x.cpu().numpy(), it, rels
 
-    n_plain = min(len(reqs), 48)
+    n_plain = len(reqs)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    plain = [plain_one(*r) for r in reqs[:n_plain]]
+    plain = [plain_one(*r) for r in reqs]
     t_plain = time.perf_counter() - t0
-    out = {"requests": n_plain, "tol": tol, "max_iters": max_iters, "check_every": step,
+    iters = np.array([p[1] for p in plain])
+    last_rel = np.array([p[2][-1] for p in plain])
+    out = {"requests": n_plain, "pool": "the 96 uneven slices (256^2, 384^2, 512^2 in "
+                                        "ratio 1:1:1), each request one of them in turn",
+           "tol": tol, "max_iters": max_iters, "check_every": step,
            "plain": {"slices_per_s": round(n_plain / t_plain, 3),
-                     "mean_iters": round(float(np.mean([p[1] for p in plain])), 2)}}
+                     "mean_iters": round(float(iters.mean()), 2)},
+           "stop_rule": {"stopped_by_tol": int((iters < max_iters).sum()),
+                         "stopped_at_max_iters": int((iters >= max_iters).sum()),
+                         "iters_histogram": {str(k): int(v) for k, v in
+                                             zip(*np.unique(iters, return_counts=True))},
+                         "rel_change_at_last_check_quantiles": [
+                             float("%.3g" % q) for q in np.quantile(last_rel, [0.1, 0.5, 0.9])],
+                         "rel_change_per_check_slice0": [float("%.3g" % r)
+                                                         for r in plain[0][2]]}}
 
-    def run(arrivals, slots):
-        srv = dect.Server(max_slots=slots, step_iters=step)
+    def run(arrivals, slots, window, max_queue=0):
+        """Submit at the given arrival times; with a window, results are taken at its
+        end (requests still queued or running then are dropped and counted), else all
+        are awaited."""
+        srv = dect.Server(max_slots=slots, step_iters=step, max_queue=max_queue)
         t0 = time.perf_counter()
-        tickets = []
+        tickets, shed = [], 0
         for k, ta in enumerate(arrivals):
             wait = ta - (time.perf_counter() - t0)
             if wait > 0:
                 time.sleep(wait)
             plan, i0, ch, cl = reqs[k % n_plain]
-            tickets.append(srv.submit(plan, ch, cl, i0, params=params, tol=tol,
-                                      max_iters=max_iters))
-        res = [srv.wait(t, 600000) for t in tickets]
-        span = time.perf_counter() - t0
+            try:
+                tickets.append((ta, srv.submit(plan, ch, cl, i0, params=params, tol=tol,
+                                               max_iters=max_iters)))
+            except dect.DectError as e:
+                if e.status != -6:
+                    raise
+                shed += 1
+        if window is None:
+            res = [(ta, srv.wait(t, 600000)) for ta, t in tickets]
+            span = time.perf_counter() - t0
+            if any(r is None for _, r in res):
+                raise RuntimeError("a served request did not finish within 600 s")
+        else:
+            left = window - (time.perf_counter() - t0)
+            if left > 0:
+                time.sleep(left)
+            res = [(ta, srv.poll(t)) for ta, t in tickets]
+            span = window
         st = srv.stats()
         srv.close()
-        if any(r is None for r in res):
-            raise RuntimeError("a served request did not finish within 600 s")
-        lat = np.array([r[1]["latency_s"] for r in res])
-        return res, {"slices_per_s": round(len(res) / span, 3),
-                     "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
-                     "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
-                     "mean_queue_s": round(float(np.mean([r[1]["queue_s"] for r in res])), 4),
-                     "mean_iters": round(float(np.mean([r[1]["iters"] for r in res])), 2),
-                     "peak_in_flight": st["peak_in_flight"], "steps": st["steps"]}
+        done = [r for _, r in res if r is not None]
+        lat = np.array([r[1]["latency_s"] for r in done]) if done else np.zeros(1)
+        rec = {"offered": len(arrivals), "admitted_to_queue": len(tickets), "shed": shed,
+               "completed": len(done), "unfinished_at_end": len(res) - len(done),
+               "slices_per_s": round(len(done) / span, 3),
+               "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
+               "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
+               "mean_queue_s": round(float(np.mean([r[1]["queue_s"] for r in done])), 4)
+               if done else None,
+               "mean_iters": round(float(np.mean([r[1]["iters"] for r in done])), 2)
+               if done else None,
+               "peak_in_flight": st["peak_in_flight"], "steps": st["steps"]}
+        return res, rec
 
-    res, closed = run([0.0] * n_plain, args.serve_slots)
+    res, closed = run([0.0] * n_plain, args.serve_slots, None)
     closed["identical_to_plain"] = all(
-        np.array_equal(r[0], p[0]) and r[1]["iters"] == p[1] for r, p in zip(res, plain))
+        r is not None and np.array_equal(r[0], p[0]) and r[1]["iters"] == p[1]
+        for (_, r), p in zip(res, plain))
     out["served_closed"] = closed
     rng = np.random.default_rng(2024)
 
@@ -313,12 +423,18 @@ def serve_workload(dect, torch, dev, items, args):
         t = np.cumsum(rng.exponential(1.0 / rate, int(rate * seconds * 2) + 16))
         return t[t < seconds]
 
-    _, over = run(poisson(args.serve_rate, args.serve_seconds), args.serve_slots)
+    print(f"[bench] serving: Poisson {args.serve_rate} req/s for {args.serve_seconds} s",
+          file=sys.stderr, flush=True)
+    _, over = run(poisson(args.serve_rate, args.serve_seconds), args.serve_slots,
+                  args.serve_seconds, max_queue=args.serve_queue)
     over["offered_req_per_s"] = args.serve_rate
     over["arrival_window_s"] = args.serve_seconds
+    over["max_queue"] = args.serve_queue
     out["served_poisson"] = over
     rate = 0.7 * closed["slices_per_s"]
-    _, under = run(poisson(rate, args.serve_seconds), args.serve_slots)
+    print(f"[bench] serving: Poisson {rate:.1f} req/s (70 % of capacity) for "
+          f"{args.serve_seconds} s", file=sys.stderr, flush=True)
+    _, under = run(poisson(rate, args.serve_seconds), args.serve_slots, None)
     under["offered_req_per_s"] = round(rate, 3)
     under["arrival_window_s"] = args.serve_seconds
     out["served_poisson_70pct"] = under
@@ -349,9 +465,9 @@ def main():
     pr = synth.slice_problem(0, with_image=True)
     plan = dect.Plan(pr.geom, pr.spec, torch.float32, device=dev)
     if args.launch:
-        bpw, pjw = (int(v) for v in args.launch.split(","))
-        plan.set_launch(bpw, pjw)
-        tuned = {"bp_waves": bpw, "proj_waves": pjw}
+        vals = [int(v) for v in args.launch.split(",")]
+        plan.set_launch(*vals)
+        tuned = plan.launch()
         tuned_by = "fixed by --launch"
     else:
         tuned = plan.tune()
@@ -483,9 +599,11 @@ def main():
     info = plan.info()
     N, M = info["n_pixels"], info["n_rays"]
     # Algorithmic VALU operations of one two-channel R or R^T application: per Joseph
-    # sample the position (fma), floor and fraction; per channel the difference, the
-    # interpolating fma and the accumulation.
-    ops_apply = 3 * info["samples"] + 3 * 2 * info["samples"]
+    # sample of a base view the position (fma), floor and fraction, shared by the
+    # `symmetry` rotated views that reuse it; per sample and channel the difference,
+    # the interpolating fma and the accumulation.
+    sym = info["symmetry"]
+    ops_apply = 3 * info["samples"] // sym + 3 * 2 * info["samples"]
     alg = algorithmic_bytes(N, M, params.cg_iters)
     counted = counted_traffic()
     total = sum(t for t, _ in kt.values())
@@ -507,9 +625,14 @@ def main():
                 "peak": round(VALU_PEAK_TOPS, 2), "unit": "TOP/s",
                 "frac": round(achieved / VALU_PEAK_TOPS, 4),
                 "traffic": counted.get(dominant),
-                "ops_per_launch": ops_apply, "avg_launch_us": round(avg_s * 1e6, 2),
+                "ops_per_launch": ops_apply,
+                "ops_rule": f"3 per base-view sample (shared by {sym} rotated views) + 3 per "
+                            "sample and channel",
+                "samples_per_launch": info["samples"], "symmetry": sym,
+                "avg_launch_us": round(avg_s * 1e6, 2),
                 "hbm_alg_bytes_per_launch": alg.get(dominant),
-                "hbm_alg_frac": per_kernel[dominant].get("hbm_alg_frac")}
+                "hbm_alg_frac": per_kernel[dominant].get("hbm_alg_frac"),
+                "binding_unit": binding_unit(dominant)}
 
     out = {
         "metric": "ADMM iters/s on 512² fan-beam slice",
@@ -530,7 +653,10 @@ def main():
                    "slices": 1, "image": 512, "views": 720, "bins": 1024,
                    "lm_iters": 1, "cg_iters": 1},
         "roofline": roofline,
-        "launch": {"bp_waves": tuned["bp_waves"], "proj_waves": tuned["proj_waves"],
+        "launch": {**{k: tuned[k] for k in ("bp_waves", "proj_waves", "proj_views",
+                                             "proj_chunk")},
+                   **{k: round(tuned[k], 2) for k in ("bp_us", "proj_us", "bp_us_default",
+                                                      "proj_us_default") if k in tuned},
                    "tuned_by": tuned_by},
         "kernels": per_kernel,
         "accuracy": {"xi_c_db": round(xi[0], 3), "xi_p_db": round(xi[1], 3),

@@ -97,15 +97,18 @@ void dect_plan_destroy(dect_plan* plan);
 const char* dect_last_error(void);
 
 /* R: sino[v][b][c] = sum over the Joseph samples of ray (v,b) of the linearly
- * interpolated img[.][.][c] times the step length (Eq. (2), Sec. 3.1).
+ * interpolated img[.][.][c] times the step length (Eq. (2), Sec. 1).
  * img: device [ny][nx][ch]; sino: device [n_views][n_det][ch] (overwritten);
  * ch in {1, 2, 4}.  async.  Uses a plan-owned scratch image, so calls with one
  * plan must not run concurrently on different streams. */
 dect_status dect_project(const dect_plan* plan, const void* img, void* sino, int ch,
                          void* stream);
 
-/* R^T, the exact transpose of dect_project (same weights, gathered per pixel,
- * no atomics): img[j][i][c] = sum over rays of weight * sino[v][b][c].
+/* R^T, the transpose of dect_project up to rounding, gathered per pixel with no
+ * atomics: img[j][i][c] = sum over rays of weight * sino[v][b][c], each weight the
+ * projector's linear-interpolation weight of the pixel re-evaluated from the same
+ * ray geometry in a different but equivalent arithmetic form (so the pair is
+ * adjoint to rounding: <R x, y> = <x, R^T y> to 1e-12 relative in FP64).
  * sino: device [n_views][n_det][ch]; img: device [ny][nx][ch] (overwritten);
  * ch in {1, 2, 4}.  async.  On a quarter-turn symmetric plan one or two channels
  * are first reordered into a plan-owned scratch sinogram, so calls with one plan
@@ -229,13 +232,18 @@ typedef struct {
     size_t x, y, uy, z, uz;   /* images */
     size_t a, ua, Rx;         /* sinograms */
     size_t scalars;           /* device doubles: rho_c, rho_p, iteration, ... */
+    size_t lm_accept;         /* uint8 [n_views][n_det]: bit k set if LM iteration k (k < 8)
+                                 of the last a-update accepted its trial point */
 } dect_layout;
 
 /* Sizes of the operator, for cost accounting: Joseph samples (steps with at least
- * one tap inside the image) and nonzero taps (nonzeros of R) over all rays. */
+ * one tap inside the image) and nonzero taps (nonzeros of R) over all rays, and the
+ * number of views that share one weight evaluation (4 on a quarter-turn symmetric
+ * plan, whose views v + k n_views/4 are exact rotations of base view v; else 1). */
 typedef struct {
     int64_t n_pixels, n_rays;
     int64_t samples, taps;
+    int64_t symmetry;
 } dect_plan_info;
 
 /* Counted on the host on first call (a pass over every ray's samples). */
@@ -308,35 +316,50 @@ dect_status dect_lmcg_iterate(const dect_plan* plan, const void* m_h, const void
 
 /* ----------------------------------------------------------- autotuning --- */
 
-/* Workgroup shapes of the ADMM's transposed projector (waves of a workgroup
- * splitting the views) and projector (waves splitting the image lines): 2, 4 or
- * 8 each, 4 by default.  Every shape computes the same sums; only the order in
- * which a workgroup's partial sums are added changes.  Batches share launches
- * only between slices whose plans have the same shapes. */
+/* Launch shapes of the ADMM's transposed projector and projector:
+ *  - bp_waves: waves of a transpose workgroup, splitting the views (2, 4 or 8);
+ *  - proj_waves: waves of a projector workgroup, splitting the lines its rays cross
+ *    (2, 4 or 8);
+ *  - proj_views: base views whose rays share a projector wave (1, 2, 4 or 8; the wave
+ *    takes 64 / proj_views consecutive bins of each);
+ *  - proj_chunk: bin groups an XCD takes per turn of the workgroup order (1 to 16).
+ * Defaults 4, 8, 2, 1.  Every shape computes the same sums; only the order in which a
+ * workgroup's partial sums are added changes.  Batches share launches only between
+ * slices whose plans have the same shapes. */
 typedef struct {
     int bp_waves;      /* transposed projector */
     int proj_waves;    /* projector */
+    int proj_views;
+    int proj_chunk;
     double bp_us;      /* timed duration of the chosen shapes (0 when not timed) */
     double proj_us;
+    double bp_us_default;    /* timed duration of the default shapes (0 when not timed) */
+    double proj_us_default;
     int from_cache;    /* 1 if taken from the cache without timing */
 } dect_launch;
 
 #define DECT_TUNE_FORCE 1  /* time the candidates even if the cache has an entry */
 
-/* Choose the plan's workgroup shapes: from the cache file if it has an entry for
- * this device, precision and problem shape, else by timing every candidate on a
- * scratch state on `stream` (synchronises; allocates a temporary state) and
- * appending the result to the cache (cache_path NULL: no cache).  The plan is
- * updated; out (may be NULL) receives the choice. */
+/* Choose the plan's launch shapes: from the cache file if it has an entry for this
+ * device, precision and problem shape, else by timing every candidate on a scratch
+ * state on `stream` (synchronises; allocates a temporary state) and appending the
+ * result to the cache (cache_path NULL: no cache).  Candidates: bp_waves 2, 4, 8 for
+ * the transpose; proj_waves 2, 4, 8 x proj_views 1, 2, 4 x proj_chunk 1, 2, 4 for the
+ * projector; each timed as the median of 3 batches of 8 launches after 2 warm-up
+ * launches.  A candidate replaces the default only if it is faster by more than the
+ * larger of 1 % and the batches' spread, so run-to-run noise does not change the
+ * shapes.  The plan is updated; out (may be NULL) receives the choice. */
 dect_status dect_plan_tune(dect_plan* plan, const char* cache_path, int flags, dect_launch* out,
                            void* stream);
-dect_status dect_plan_set_launch(dect_plan* plan, int bp_waves, int proj_waves);
+dect_status dect_plan_set_launch(dect_plan* plan, int bp_waves, int proj_waves, int proj_views,
+                                 int proj_chunk);
 dect_status dect_plan_get_launch(const dect_plan* plan, dect_launch* out);
 
 /* ---------------------------------------------------------------- batch --- */
 
-/* Independent slices (Sec. 3.3 per slice: each detector row or table position
- * is its own problem) advanced together.  A batch groups its slices by shape
+/* Independent slices advanced together.  The paper reconstructs one 2-D slice;
+ * treating each slice (detector row or table position) as its own problem with no
+ * data shared between slices is this library's design choice for throughput.  A batch groups its slices by shape
  * (image, views, bins); every kernel of an outer iteration is ONE launch per
  * group, all slices of the group at once, and with use_graph one outer
  * iteration of all groups is captured once into a HIP graph and replayed.  A
@@ -365,8 +388,8 @@ void dect_batch_destroy(dect_batch* batch);
 
 /* -------------------------------------------------------------- serving --- */
 
-/* Continuous batching of slice reconstructions (each slice its own problem,
- * Sec. 3.3).  A server owns one worker thread and one stream on the device
+/* Continuous batching of slice reconstructions (each slice its own problem, as
+ * in the batch above).  A server owns one worker thread and one stream on the device
  * current at creation.  Requests wait in a FIFO queue and are admitted, in
  * order, while a slot is free and their device footprint (state, measurements
  * and counts: dect_serve_footprint) fits the memory budget.  An admitted request
@@ -382,6 +405,10 @@ typedef struct {
     size_t hbm_budget_bytes; /* device memory for slots; 0: half the free memory */
     int max_slots;           /* requests in flight at once, >= 1 */
     int step_iters;          /* iterations between a slot's checks, >= 1 */
+    int max_queue;           /* requests waiting for admission at most (0: no limit); a
+                                submit beyond it is refused with DECT_E_CAPACITY, so an
+                                overloaded server sheds load instead of queueing without
+                                bound */
 } dect_server_config;
 
 typedef struct {
@@ -408,6 +435,7 @@ typedef struct {
 typedef struct {
     int64_t submitted, completed, queued, in_flight, peak_in_flight, steps;
     size_t hbm_held;    /* device bytes held for slots (in use and cached) */
+    int64_t rejected;   /* submits refused because the queue was full */
 } dect_server_stats;
 
 typedef struct dect_server dect_server;
@@ -416,7 +444,8 @@ dect_status dect_server_create(const dect_server_config* cfg, dect_server** out)
 /* Device bytes one request of this plan holds while in flight. */
 size_t dect_serve_footprint(const dect_plan* plan);
 /* Queue a request; *ticket identifies it.  DECT_E_CAPACITY if its footprint
- * exceeds the whole budget, DECT_E_ARG for bad arguments. */
+ * exceeds the whole budget or the queue holds max_queue requests, DECT_E_ARG for bad
+ * arguments. */
 dect_status dect_serve_submit(dect_server* server, const dect_request* req, uint64_t* ticket);
 /* DECT_NOT_READY while the request is queued or running; once it has finished,
  * DECT_OK and *out, and the ticket is released (a later poll is DECT_E_ARG). */

@@ -63,11 +63,22 @@ def _lib():
         _LIB.orc_backproject.argtypes = [P(_Geom), pd, pd]
         _LIB.orc_forward.argtypes = [i, pd, pd, pd, i, pd, pd, pd, l, pd, pd, pd, pd, pd, pd]
         _LIB.orc_udm.argtypes = [i, pd, pd, pd, i, pd, pd, pd, l, pd, pd, pd, pd, pd, pd, d, d, i,
-                                 d, pd, pd, pd]
+                                 d, pd, pd, pd, P(ctypes.c_uint8), pd]
         _LIB.orc_udm.restype = i
         _LIB.orc_cdm.argtypes = [i, pd, pd, pd, i, pd, pd, pd, l, pd, pd, pd, pd, i, d, pd, pd, pd]
         _LIB.orc_cdm.restype = i
+        _LIB.orc_set_threads.argtypes = [i]
+        _LIB.orc_max_threads.restype = i
     return _LIB
+
+
+def set_threads(n: int) -> None:
+    """Threads of the C part's parallel loops (results do not depend on it)."""
+    _lib().orc_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(_lib().orc_max_threads())
 
 
 class _Geom(ctypes.Structure):
@@ -198,6 +209,7 @@ class State:
     rho: np.ndarray    # [2]
     it: int = 0
     log: list = field(default_factory=list)
+    lm_ties: np.ndarray | None = None  # per-ray near-tie ratios of the last replayed a-update
 
     def copy(self):
         return State(*(np.array(getattr(self, k)) for k in
@@ -272,16 +284,33 @@ class Oracle:
         sh = ac.shape
         return fh.reshape(sh), fl.reshape(sh), gh.reshape(sh + (2,)), gl.reshape(sh + (2,))
 
-    def udm(self, mh, ml, wh, wl, vc, vp, rho_c, rho_p, iters, a_c, a_p, mu0=1e-3):
-        """Eq. (13) per ray by `iters` LM iterations from (a_c, a_p); returns (a_c, a_p, Phi)."""
+    def udm(self, mh, ml, wh, wl, vc, vp, rho_c, rho_p, iters, a_c, a_p, mu0=1e-3,
+            force=None, ties: list | None = None):
+        """Eq. (13) per ray by `iters` LM iterations from (a_c, a_p); returns (a_c, a_p, Phi).
+
+        force: optional uint8 array of the rays' shape whose bit k replays the accept
+        decision of LM iteration k (k < 8) taken elsewhere, e.g. by single-precision
+        arithmetic.  The per-ray near-tie ratios of replayed decisions that disagree with
+        this one's own comparison (|Phi(trial) - Phi(current)| over their single-precision
+        rounding scale; 0 where none disagrees) are appended to `ties` if given."""
         sh = np.shape(a_c)
         ac, ap = _f64(a_c).ravel().copy(), _f64(a_p).ravel().copy()
         n = ac.size
         args = [_f64(v).ravel() if v is not None else None for v in (mh, ml, wh, wl, vc, vp)]
         phi = np.empty(n)
+        fz = None
+        tie = None
+        if force is not None:
+            fz = np.ascontiguousarray(force, dtype=np.uint8).ravel()
+            assert fz.size == n
+            tie = np.empty(n)
         nf = _lib().orc_udm(*self._spec_args(), n, *(_ptr(v) for v in args), float(rho_c),
-                            float(rho_p), int(iters), float(mu0), _ptr(ac), _ptr(ap), _ptr(phi))
+                            float(rho_p), int(iters), float(mu0), _ptr(ac), _ptr(ap), _ptr(phi),
+                            fz.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)) if fz is not None
+                            else None, _ptr(tie))
         self.counts["f"] += nf
+        if ties is not None and tie is not None:
+            ties.append(tie.reshape(sh))
         return ac.reshape(sh), ap.reshape(sh), phi.reshape(sh)
 
     def cdm(self, mh, ml, wh, wl, iters=20, mu0=1e-3):
@@ -425,15 +454,25 @@ class Oracle:
             gamma = gamma_new
         return x, Rx
 
-    def admm_iterate(self, st: State, mh, ml, wh, wl, params: Params, n_iters: int = 1) -> State:
-        """n_iters ADMM iterations: x (Eq. 12), a (Eq. 13), y and z (Eq. 9-10), u (Eq. 11), rho."""
+    def admm_iterate(self, st: State, mh, ml, wh, wl, params: Params, n_iters: int = 1,
+                     lm_force=None, rho_force=None) -> State:
+        """n_iters ADMM iterations: x (Eq. 12), a (Eq. 13), y and z (Eq. 9-10), u (Eq. 11), rho.
+
+        Replays for parity runs against single-precision arithmetic, whose discrete
+        decisions can differ from this one's on near-ties: lm_force[k] (uint8 [V, D], see
+        udm) replays the LM accept decisions of iteration k, and the log records how close
+        every replayed decision that differs from this one's own was ('lm_tie_max', 0 if
+        none; 'lm_flips', their count); rho_force[k] = (rho_c, rho_p) replaces the
+        residual-balancing rho chosen at the end of iteration k, and 'rho_tie' records how
+        far from a tie of the balancing test any differing decision of this one's was
+        (|max(r, s) - mu min(r, s)| / max(r, s); 0 if none differs)."""
         st = st.copy()
         filt = None
         if params.precond == "ramp":
             filt = ramp_filter(*pad_shape(*self.img_shape))
         elif params.precond is not None:
             raise ValueError(f"unknown preconditioner {params.precond!r}")
-        for _ in range(n_iters):
+        for it_k in range(n_iters):
             rho = st.rho.copy()
             a_prev, y_prev, z_prev = st.a.copy(), st.y.copy(), st.z.copy()
             # x-update, independently per basis (Eq. (12)); rho cancels.
@@ -443,8 +482,10 @@ class Oracle:
                     DT(st.y[b] + st.uy[b]) + st.z[b] + st.uz[b], params.cg_iters, filt)
             # a-update: per-ray decomposition (Eq. (13)) with v = R x - u^a.
             v = st.Rx - st.ua
+            ties = []
+            force = lm_force[it_k] if lm_force is not None else None
             ac, ap, _ = self.udm(mh, ml, wh, wl, v[0], v[1], rho[0], rho[1], params.lm_iters,
-                                 st.a[0], st.a[1], params.lm_mu0)
+                                 st.a[0], st.a[1], params.lm_mu0, force=force, ties=ties)
             st.a = np.stack([ac, ap])
             # y and z updates (Eq. (9)-(10)) and the scaled duals (Eq. (11)).
             for b in range(2):
@@ -472,14 +513,34 @@ class Oracle:
                         new_rho[b] = rho[b] * params.bal_tau
                     elif s_norm[b] > params.bal_mu * r_norm[b]:
                         new_rho[b] = rho[b] / params.bal_tau
+            rho_tie = 0.0
+            if rho_force is not None:
+                forced = np.array(rho_force[it_k], dtype=np.float64)
+                for b in range(2):
+                    if forced[b] != new_rho[b]:
+                        # How close the balancing test r > mu s (or s > mu r) was to a tie.
+                        hi, lo = max(r_norm[b], s_norm[b]), min(r_norm[b], s_norm[b])
+                        rho_tie = max(rho_tie, abs(hi - params.bal_mu * lo) / max(hi, 1e-300))
+                new_rho = forced
             for b in range(2):
                 k = rho[b] / new_rho[b]
                 st.ua[b] *= k
                 st.uy[b] *= k
                 st.uz[b] *= k
             st.rho = new_rho
-            st.log.append(dict(it=st.it, rho=rho.copy(), r=r_norm.copy(), s=s_norm.copy(),
-                               phi=self.split_objective(st, mh, ml, wh, wl, params.lam)))
+            # The split objective's two terms: the data fit at the new a (Eq. (13)'s first
+            # term) and lambda |y|_1 at the new y (Eq. (9)).
+            data = self.data_cost(st.a[0], st.a[1], mh, ml, wh, wl)
+            tv = sum(params.lam[b] * float(np.abs(st.y[b]).sum()) for b in range(2))
+            entry = dict(it=st.it, rho=rho.copy(), r=r_norm.copy(), s=s_norm.copy(),
+                         data=data, tv=tv, phi=data + tv)
+            if ties:
+                entry["lm_flips"] = int(np.count_nonzero(ties[0]))
+                entry["lm_tie_max"] = float(ties[0].max())
+                st.lm_ties = ties[0]
+            if rho_force is not None:
+                entry["rho_tie"] = rho_tie
+            st.log.append(entry)
             st.it += 1
         return st
 

@@ -28,6 +28,7 @@
  * Otherwise rows and columns swap roles.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -232,12 +233,50 @@ static void udm_eval(const orc_spec* sh, const orc_spec* sl, double mh, double m
              0.5 * (rc * (ac - vc) * (ac - vc) + rp * (ap - vp) * (ap - vp));
 }
 
-/* Returns the number of single-spectrum f evaluations made per ray. */
+/* Largest magnitude of the exponents ln omega_k - f_KN[k] a_c - f_p[k] a_p of one
+ * spectrum's log-sum-exp at (a_c, a_p), bounded term by term: the rounding error of
+ * f_s is a few units of it (f_s = -(M + ln Z) can be a small difference of such terms,
+ * e.g. near a = 0). */
+static double lse_scale(const orc_spec* s, double ac, double ap) {
+    double w = 0.0, k = 0.0, p = 0.0;
+    for (int i = 0; i < s->n; ++i) {
+        if (fabs(s->lnw[i]) > w) w = fabs(s->lnw[i]);
+        if (s->fkn[i] > k) k = s->fkn[i];
+        if (s->fp[i] > p) p = s->fp[i];
+    }
+    return w + k * fabs(ac) + p * fabs(ap);
+}
+
+/* First-order bound, in units of the rounding unit, of the error of Phi when f_s carries
+ * an absolute error of the order of its log-sum-exp's exponents and the residuals
+ * f_s - m_s and a_b - v_b are formed from values each carrying a relative rounding error:
+ * sum_s w_s |r_s| (|f_s| + |m_s| + lse_s) + sum_b rho_b |d_b| (|a_b| + |v_b|). */
+static double phi_scale(const orc_spec* sh, const orc_spec* sl, const orc_eval* e, double mh,
+                        double ml, double wh, double wl, double vc, double vp, double rc,
+                        double rp, double ac, double ap) {
+    return wh * fabs(e->fh - mh) * (fabs(e->fh) + fabs(mh) + lse_scale(sh, ac, ap)) +
+           wl * fabs(e->fl - ml) * (fabs(e->fl) + fabs(ml) + lse_scale(sl, ac, ap)) +
+           rc * fabs(ac - vc) * (fabs(ac) + fabs(vc)) + rp * fabs(ap - vp) * (fabs(ap) + fabs(vp));
+}
+
+/* Returns the number of single-spectrum f evaluations made per ray.
+ *
+ * force (NULL: none) replays accept decisions taken elsewhere: bit k of force[i] is the
+ * decision of LM iteration k (k < 8) on ray i, 1 = the trial point was accepted.  The
+ * iteration then follows that decision instead of its own comparison; where the two
+ * differ, tie_out[i] (if given) receives the largest |Phi(trial) - Phi(current)| over
+ * the single-precision rounding scale of the two values (2^-23 times phi_scale at both
+ * points), so a caller can check that every replayed decision was a near-tie; a
+ * replayed acceptance of a step this iteration cannot form (damped determinant not
+ * positive and finite) gives +inf.  Without disagreements tie_out[i] = 0.  The scale
+ * is phi_scale: the first-order rounding bound of Phi at single precision, including
+ * the log-sum-exp's own cancellation. */
 int orc_udm(int nh, const double* lnw_h, const double* fkn_h, const double* fp_h, int nl,
             const double* lnw_l, const double* fkn_l, const double* fp_l, long n,
             const double* mh, const double* ml, const double* wh, const double* wl,
             const double* vc, const double* vp, double rho_c, double rho_p, int iters,
-            double mu0, double* ac, double* ap, double* phi_out) {
+            double mu0, double* ac, double* ap, double* phi_out, const unsigned char* force,
+            double* tie_out) {
     orc_spec sh = {nh, lnw_h, fkn_h, fp_h}, sl = {nl, lnw_l, fkn_l, fp_l};
 #pragma omp parallel for schedule(static)
     for (long i = 0; i < n; ++i) {
@@ -246,7 +285,10 @@ int orc_udm(int nh, const double* lnw_h, const double* fkn_h, const double* fp_h
         orc_eval cur, tri;
         udm_eval(&sh, &sl, mh[i], ml[i], wh[i], wl[i], v_c, v_p, rho_c, rho_p, a_c, a_p, &cur);
         double mu = mu0;
+        double tie = 0.0;
         for (int it = 0; it < iters; ++it) {
+            const int forced = force && it < 8;
+            const int want = forced ? (force[i] >> it) & 1 : 0;
             double rh = cur.fh - mh[i], rl = cur.fl - ml[i];
             double Gc = wh[i] * rh * cur.ghc + wl[i] * rl * cur.glc + rho_c * (a_c - v_c);
             double Gp = wh[i] * rh * cur.ghp + wl[i] * rl * cur.glp + rho_p * (a_p - v_p);
@@ -256,6 +298,7 @@ int orc_udm(int nh, const double* lnw_h, const double* fkn_h, const double* fp_h
             double Dcc = (1.0 + mu) * Hcc, Dpp = (1.0 + mu) * Hpp;
             double det = Dcc * Dpp - Hcp * Hcp;
             if (!(det > 0.0) || !isfinite(det)) {
+                if (want) tie = INFINITY;
                 mu *= 10.0;
                 continue;
             }
@@ -263,7 +306,19 @@ int orc_udm(int nh, const double* lnw_h, const double* fkn_h, const double* fp_h
             double dp = -(Dcc * Gp - Hcp * Gc) / det;
             double tc = a_c + dc, tp = a_p + dp;
             udm_eval(&sh, &sl, mh[i], ml[i], wh[i], wl[i], v_c, v_p, rho_c, rho_p, tc, tp, &tri);
-            if (tri.phi < cur.phi) {
+            int take = tri.phi < cur.phi;
+            if (forced && want != take) {
+                const double scale =
+                    ldexp(phi_scale(&sh, &sl, &cur, mh[i], ml[i], wh[i], wl[i], v_c, v_p, rho_c,
+                                    rho_p, a_c, a_p) +
+                              phi_scale(&sh, &sl, &tri, mh[i], ml[i], wh[i], wl[i], v_c, v_p,
+                                        rho_c, rho_p, tc, tp),
+                          -23);
+                const double r = fabs(tri.phi - cur.phi) / (scale > 0.0 ? scale : 1e-300);
+                if (r > tie) tie = r;
+                take = want;
+            }
+            if (take) {
                 a_c = tc;
                 a_p = tp;
                 cur = tri;
@@ -275,6 +330,7 @@ int orc_udm(int nh, const double* lnw_h, const double* fkn_h, const double* fp_h
         ac[i] = a_c;
         ap[i] = a_p;
         if (phi_out) phi_out[i] = cur.phi;
+        if (tie_out) tie_out[i] = tie;
     }
     return 2 * (iters + 1);
 }
@@ -342,3 +398,7 @@ int orc_cdm(int nh, const double* lnw_h, const double* fkn_h, const double* fp_h
     }
     return 2 * (iters + 1);
 }
+
+/* Thread count of the parallel loops above (the CPU baseline times 1 and all). */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int orc_max_threads(void) { return omp_get_max_threads(); }

@@ -5,11 +5,14 @@
 // with every scalar (CG step sizes, rho, dual rescale) kept in device memory:
 //   R^T t + image terms -> r0 = p0, |r0|^2          (Eq. (12) right-hand side; R^T t is
 //                                                    tracked as h + u, no transpose)
-//   n x { R p ; R^T R p + D^T D p + p ; alpha ; x += alpha p, h -= alpha R^T R p ; beta }
+//   n x { R p ; R^T R p + D^T D p + p ; alpha ;
+//         except after the last: x += alpha p, h -= alpha R^T R p ; beta }
 //   per-ray LM on Eq. (13) with R x += alpha R p and u^a (one lane per ray), and in
-//   the same launch y, z, u^y, u^z (Eq. (9)-(11)) with their partials (one lane per pixel)
+//   the same launch y, z, u^y, u^z (Eq. (9)-(11)) with their partials (one lane per
+//   pixel), reading x through the pending last CG step
 //   R^T da + D^T dy + dz                             (dual residual; R^T da also goes to h)
-//   residual balancing, rho, dual rescale            (one block, then elementwise)
+//   residuals, rho and the log                        (one workgroup)
+//   the last CG step and the dual rescale            (elementwise)
 #include <cmath>
 #include <cstring>
 
@@ -17,12 +20,11 @@
 #include "epilogue.h"
 #include "kernels.h"
 #include "profile.h"
+#include "reduce.h"
 
 namespace dect {
 
 namespace {
-
-enum RedMode : int { RED_ALPHA = 1, RED_BETA = 2, RED_FINAL = 3 };
 
 __global__ __launch_bounds__(256) void k_zero(uint32_t* p, size_t n) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -53,12 +55,13 @@ __global__ __launch_bounds__(256) void k_cg_step(const VecArgs<T>* __restrict__ 
         V2 xv = reinterpret_cast<V2*>(A.x)[i];
         const V2 pv = reinterpret_cast<const V2*>(A.p)[i];
 #pragma unroll
-        for (int c = 0; c < 2; ++c) xv.v[c] += al[c] * pv.v[c];
+        for (int c = 0; c < 2; ++c) xv.v[c] = fma(al[c], pv.v[c], xv.v[c]);
         reinterpret_cast<V2*>(A.x)[i] = xv;
         // R x moves by alpha R p, so the tracked R^T (a - R x) by -alpha R^T R p.
         const V2 rr = reinterpret_cast<const V2*>(A.rtrp)[i];
 #pragma unroll
-        for (int c = 0; c < 2; ++c) A.h[2 * i + c] -= A.scal[S_ALPHA + c] * (double)rr.v[c];
+        for (int c = 0; c < 2; ++c)
+            A.h[2 * i + c] = fma(-A.scal[S_ALPHA + c], (double)rr.v[c], A.h[2 * i + c]);
         if constexpr (FULL) {
             V2 rv = reinterpret_cast<V2*>(A.r)[i];
             const V2 qv = reinterpret_cast<const V2*>(A.q)[i];
@@ -71,39 +74,6 @@ __global__ __launch_bounds__(256) void k_cg_step(const VecArgs<T>* __restrict__ 
         }
     }
     if constexpr (FULL) block_sum_store<2>(part, A.partials + (size_t)blockIdx.x * kPartialSlots);
-}
-
-// The last CG step of an outer iteration, with its alpha reduction: every block sums
-// the block partials of r . z and p . q in the same fixed order (so all obtain the same
-// alpha, and block 0 stores gamma, p . q and alpha), then x += alpha p and
-// h -= alpha R^T R p over the image (grid-stride).
-template <typename T, bool BATCH>
-__global__ __launch_bounds__(256) void k_cg_last(const VecArgs<T>* __restrict__ dev, VecArgs<T> one) {
-    using V2 = vec<T, 2>;
-    const VecArgs<T> A = pick_args<BATCH>(dev, one);
-    double g[2], pq[2], al[2];
-    partial_sum<2>(A.g_part, A.nb_g, g);
-    partial_sum<2>(A.pq_part, A.nb_pq, pq);
-#pragma unroll
-    for (int c = 0; c < 2; ++c) al[c] = (pq[c] > 0.0 && g[c] > 0.0) ? g[c] / pq[c] : 0.0;
-    if (blockIdx.x == 0 && threadIdx.x == 0)
-        for (int c = 0; c < 2; ++c) {
-            A.scal[S_GAMMA + c] = g[c];
-            A.scal[S_PQ + c] = pq[c];
-            A.scal[S_ALPHA + c] = al[c];
-        }
-    const T alt[2] = {(T)al[0], (T)al[1]};
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < A.N;
-         i += (long)gridDim.x * blockDim.x) {
-        V2 xv = reinterpret_cast<V2*>(A.x)[i];
-        const V2 pv = reinterpret_cast<const V2*>(A.p)[i];
-#pragma unroll
-        for (int c = 0; c < 2; ++c) xv.v[c] += alt[c] * pv.v[c];
-        reinterpret_cast<V2*>(A.x)[i] = xv;
-        const V2 rr = reinterpret_cast<const V2*>(A.rtrp)[i];
-#pragma unroll
-        for (int c = 0; c < 2; ++c) A.h[2 * i + c] -= al[c] * (double)rr.v[c];
-    }
 }
 
 // R x += alpha R p (tracking, so no extra projection of x is needed).
@@ -153,10 +123,26 @@ __global__ __launch_bounds__(256) void k_rescale(const RescaleArgs<T>* __restric
     if ((long)blockIdx.x * blockDim.x >= (M > N ? M : N)) return;
     const double k0 = A.scal[S_KAPPA], k1 = A.scal[S_KAPPA + 1];
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    // u^a <- kappa (u^a + a - R x) gives R^T u^a <- kappa (R^T u^a + R^T (a - R x)).
     if (i < N) {
-        A.u[2 * i] = k0 * (A.u[2 * i] + A.h[2 * i]);
-        A.u[2 * i + 1] = k1 * (A.u[2 * i + 1] + A.h[2 * i + 1]);
+        double hv[2] = {A.h[2 * i], A.h[2 * i + 1]};
+        if (A.x) {
+            // The iteration's last CG step: x += alpha p, and R x having moved by alpha R p,
+            // the tracked R^T (a - R x) by -alpha R^T R p.
+            const double al[2] = {A.scal[S_ALPHA], A.scal[S_ALPHA + 1]};
+            V2 xv = reinterpret_cast<V2*>(A.x)[i];
+            const V2 pv = reinterpret_cast<const V2*>(A.p)[i];
+            const V2 rr = reinterpret_cast<const V2*>(A.rtrp)[i];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                xv.v[c] = fma((T)al[c], pv.v[c], xv.v[c]);
+                hv[c] = fma(-al[c], (double)rr.v[c], hv[c]);
+                A.h[2 * i + c] = hv[c];
+            }
+            reinterpret_cast<V2*>(A.x)[i] = xv;
+        }
+        // u^a <- kappa (u^a + a - R x) gives R^T u^a <- kappa (R^T u^a + R^T (a - R x)).
+        A.u[2 * i] = k0 * (A.u[2 * i] + hv[0]);
+        A.u[2 * i + 1] = k1 * (A.u[2 * i + 1] + hv[1]);
     }
     if (k0 == 1.0 && k1 == 1.0) return;
     const T kc[2] = {(T)k0, (T)k1};
@@ -192,80 +178,12 @@ template <bool BATCH>
 __global__ __launch_bounds__(256) void k_reduce(const RedArgs* __restrict__ dev, RedArgs one,
                                                 int mode) {
     const RedArgs A = pick_args<BATCH>(dev, one);
-    double* s = A.scal;
-    if (!s) return;  // empty slot
-    if (mode == RED_ALPHA) {
-        // gamma = r . z of the current residual: its block partials are still in place
-        // (no kernel between the one that wrote them and this reduction writes there).
-        double g[2], pq[2];
-        if (A.precond)
-            partial_sum<2>(A.pre, A.nb_pre, g);
-        else
-            partial_sum<2>(A.img, A.nb_img, g);
-        partial_sum<2>(A.tiles, A.nb_tiles, pq);
-        if (threadIdx.x == 0)
-            for (int c = 0; c < 2; ++c) {
-                s[S_GAMMA + c] = g[c];
-                s[S_PQ + c] = pq[c];
-                s[S_ALPHA + c] = (pq[c] > 0.0 && g[c] > 0.0) ? g[c] / pq[c] : 0.0;
-            }
-    } else if (mode == RED_BETA) {
-        double g[2];
-        if (A.precond)
-            partial_sum<2>(A.pre, A.nb_pre, g);
-        else
-            partial_sum<2>(A.img, A.nb_img, g);
-        if (threadIdx.x == 0)
-            for (int c = 0; c < 2; ++c) {
-                s[S_BETA + c] = s[S_GAMMA + c] > 0.0 ? g[c] / s[S_GAMMA + c] : 0.0;
-                s[S_GAMMA + c] = g[c];
-            }
-    } else {
-        double sn[4], im[4], du[2] = {0.0, 0.0};
-        partial_sum<4>(A.sino, A.nb_sino, sn);
-        partial_sum<4>(A.img, A.nb_img, im);
-        if (A.dual) partial_sum<2>(A.tiles, A.nb_tiles, du);
-        if (threadIdx.x == 0) {
-            const double rho[2] = {s[S_RHO], s[S_RHO + 1]};
-            double r[2], sd[2], nr[2];
-            for (int c = 0; c < 2; ++c) {
-                r[c] = sqrt(sn[c] + im[c]);
-                sd[c] = rho[c] * sqrt(du[c]);
-                nr[c] = rho[c];
-                if (A.rho_mode == DECT_RHO_ADAPTIVE) {
-                    if (r[c] > A.bal_mu * sd[c]) nr[c] = rho[c] * A.bal_tau;
-                    else if (sd[c] > A.bal_mu * r[c]) nr[c] = rho[c] / A.bal_tau;
-                }
-            }
-            if (A.rho_mode == DECT_RHO_SCHEDULE) {
-                nr[0] = A.next_rho_c;
-                nr[1] = A.next_rho_p;
-            }
-            const double data = sn[2];
-            const double tv = s[S_LAM] * im[2] + s[S_LAM + 1] * im[3];
-            bool bad = sn[3] > 0.0;
-            for (int c = 0; c < 2; ++c) bad = bad || !isfinite(r[c]) || !isfinite(sd[c]);
-            bad = bad || !isfinite(data) || !isfinite(tv);
-            const long it = (long)s[S_ITER];
-            double* L = A.log + (size_t)(it % kLogCap) * kLogStride;
-            L[0] = (double)it;
-            L[1] = bad ? 1.0 : 0.0;
-            L[2] = rho[0];
-            L[3] = rho[1];
-            L[4] = r[0];
-            L[5] = r[1];
-            L[6] = sd[0];
-            L[7] = sd[1];
-            L[8] = data;
-            L[9] = tv;
-            for (int c = 0; c < 2; ++c) {
-                s[S_KAPPA + c] = rho[c] / nr[c];
-                s[S_RHO + c] = nr[c];
-            }
-            if (bad) s[S_FLAGS] = (double)((long)s[S_FLAGS] | 1L);
-            s[S_ITER] = (double)(it + 1);
-        }
-    }
+    if (mode == RED_ALPHA)
+        reduce_alpha(A);
+    else if (mode == RED_BETA)
+        reduce_beta(A);
+    else
+        reduce_final(A);
 }
 
 // Initial CG residual of Eq. (12): r0 = R^T t + D^T (y + u^y - D x) + (z + u^z - x)
@@ -344,11 +262,13 @@ SliceJob<T> make_job(const dect_plan* p, const void* mh, const void* ml, const v
     J.sym = p->sym;
     J.bp_waves = p->bp_waves;
     J.pj_waves = p->pj_waves;
-    J.pj_gx = proj_grid_x(p->D);
-    J.pj_gy = proj_grid_y(p->Vb);
+    J.pj_views = p->pj_views;
+    J.pj_chunk = p->pj_chunk;
+    J.pj_gx = proj_grid_x(p->D, p->pj_views);
+    J.pj_gy = proj_grid_y(p->Vb, p->pj_views);
     J.orb = OrbitArgs<T>{pp, pO, pOT, p->nx, p->ny};
     J.prj = ProjArgs<T>{static_cast<const RayParam<T>*>(p->rays), pO, pOT, Rp, p->nx, p->ny,
-                        p->Vb, p->D};
+                        p->Vb, p->D, p->pj_views, p->pj_chunk};
     // Right-hand side of Eq. (12) and the initial CG residual.
     BpArgs<T> b{};
     fill_bp_plan<T>(p, b);
@@ -382,6 +302,15 @@ SliceJob<T> make_job(const dect_plan* p, const void* mh, const void* ml, const v
     J.rhs.part_img = P.img;
     J.q.raw = rtrp;
     J.dual.h = hh;
+    // The scalar steps (CG step sizes; residuals, rho and the log) run as one
+    // workgroup per slice.  The last CG step of the iteration (x += alpha p,
+    // h -= alpha R^T R p) is applied by the rescale kernel at the end, and read through
+    // by the TV update before it.
+    J.red = RedArgs{P.tiles, p->nb_tiles, P.img, p->nb_img, P.sino, p->nb_sino, P.pre, p->nb_pre,
+                    pre ? 1 : 0, scal,
+                    at<double>(st, p->off_log), prm->rho_mode,
+                    prm->rho_mode == DECT_RHO_ADAPTIVE ? 1 : 0, prm->bal_mu, prm->bal_tau,
+                    0.0, 0.0};
     // a-update (Eq. (13)) fused with R x += alpha R p, u^a and the next t.
     UdmArgs<T>& u = J.udm;
     fill_udm_tables<T>(p, u);
@@ -400,6 +329,7 @@ SliceJob<T> make_job(const dect_plan* p, const void* mh, const void* ml, const v
     u.t = nullptr;  // R^T t is tracked in h + u
     u.da = da;
     u.fg = at<T>(st, p->off_fg);
+    u.lmbits = at<uint8_t>(st, L.lm_accept);
     u.scal = scal;
     u.partials = P.sino;
     u.iters = prm->lm_iters;
@@ -416,18 +346,13 @@ SliceJob<T> make_job(const dect_plan* p, const void* mh, const void* ml, const v
         J.pre0.z = pp;
         J.pre1.z = zb;
     }
-    J.tv = TvArgs<T>{p->nx, p->ny, x, y, uy, dy, z, uz, dz, scal, P.img};
+    J.tv = TvArgs<T>{p->nx, p->ny, x, y, uy, dy, z, uz, dz, scal, P.img, pp};
     // The TV/z/dual update runs in the a-update's launch, after its blocks.
     u.udm_blocks = (int)nblk(p->M);
     u.tv = J.tv;
     // The iterations keep R^T t tracked in h + u, not t itself (t is set at the start).
     J.resc = RescaleArgs<T>{p->M, p->N, p->sym, p->Vb, p->D, ua, nullptr, a, Rx, uy, uz, scal,
-                            hh, uu};
-    J.red = RedArgs{P.tiles, p->nb_tiles, P.img, p->nb_img, P.sino, p->nb_sino, P.pre, p->nb_pre,
-                    pre ? 1 : 0, scal,
-                    at<double>(st, p->off_log), prm->rho_mode,
-                    prm->rho_mode == DECT_RHO_ADAPTIVE ? 1 : 0, prm->bal_mu, prm->bal_tau,
-                    0.0, 0.0};
+                            hh, uu, x, pp, rtrp};
     return J;
 }
 
@@ -470,20 +395,16 @@ hipError_t iteration_t(const SliceJob<T>& J, const JobArrays<T>* dev, int nsl,
                                         J.pj_gy, s));
         DECT_TRY(launch_backproject_admm<T>(J.sym, J.bp_waves, EPI_Q, dev ? dev->q : nullptr, J.q,
                                             nsl, J.bp_gx, J.bp_gy, s));
+        DECT_TRY(reduce(RED_ALPHA));
         if (c < n - 1) {
-            DECT_TRY(reduce(RED_ALPHA));
             ProfScope ps("cg_vector", s);
             hipLaunchKernelGGL((k_rx_step<T, BATCH>), gM, dim3(256), 0, s, dvec, J.vec);
             hipLaunchKernelGGL((k_cg_step<T, true, BATCH>), gN, dim3(256), 0, s, dvec, J.vec);
             if (J.precond) DECT_TRY(launch_precond<T>(dev ? dev->pre1 : nullptr, J.pre1, nsl, s));
             DECT_TRY(reduce(RED_BETA));
             hipLaunchKernelGGL((k_p_step<T, BATCH>), gN, dim3(256), 0, s, dvec, J.vec);
-        } else {
-            // alpha is formed inside the step (its partials are still in place).
-            ProfScope ps("cg_vector", s);
-            const unsigned blocks = nblk(J.N) < 256 ? nblk(J.N) : 256;
-            hipLaunchKernelGGL((k_cg_last<T, BATCH>), dim3(blocks, 1, z), dim3(256), 0, s, dvec, J.vec);
         }
+        // The last step's x and h updates are applied by the rescale kernel.
         DECT_TRY(hipGetLastError());
     }
     // The a-update (Eq. (13)) and, in the same launch, the TV/z/dual update.

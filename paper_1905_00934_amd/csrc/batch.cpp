@@ -23,6 +23,7 @@ bool same_shape(const SliceJob<T>& a, const SliceJob<T>& b) {
            a.bp_gy == b.bp_gy && a.pj_gx == b.pj_gx && a.pj_gy == b.pj_gy &&
            a.prj.nx == b.prj.nx && a.prj.ny == b.prj.ny && a.cg_iters == b.cg_iters &&
            a.rho_mode == b.rho_mode && a.bp_waves == b.bp_waves && a.pj_waves == b.pj_waves &&
+           a.pj_views == b.pj_views && a.pj_chunk == b.pj_chunk &&
            a.precond == b.precond;
 }
 

@@ -44,8 +44,9 @@ struct alignas(sizeof(T) * N) vec {
 // every pixel column i at the fractional row phi(i) = phi0 + slope * i; a
 // y-stepped ray at every row j at the fractional column phi0 + slope * j.  Each
 // sample is weighted by `step`, the ray length between two samples.  The forward
-// projector and the transposed gather both evaluate phi with one fma on these
-// exact values, so their interpolation weights are bit-identical.
+// projector and the plain transposed gather both evaluate phi with one fma on these
+// values; the weights they then form differ only by rounding (the projector
+// interpolates a0 + alpha (a1 - a0) and scales by step at the end).
 template <typename T>
 struct alignas(sizeof(T) * 4) RayParam {
     T phi0, slope, step, pad;
@@ -96,7 +97,10 @@ struct dect_plan {
     double margin = 0.05;   // footprint margin of the transpose, in bins
     // Workgroup shapes of the ADMM transpose (waves splitting the views) and
     // projector (waves splitting the lines): 2, 4 or 8, set by dect_plan_tune.
-    int bp_waves = 4, pj_waves = 4;
+    int bp_waves = 4, pj_waves = 8;
+    // Projector lane layout (base views per wave) and XCD chunk (bin groups per XCD
+    // turn), also set by dect_plan_tune.
+    int pj_views = 2, pj_chunk = 1;
     // device tables
     void* rays = nullptr;   // RayParam<T>[Vb * D]
     void* views = nullptr;  // ViewParam<T>[Vb]

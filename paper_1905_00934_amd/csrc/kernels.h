@@ -2,6 +2,7 @@
 #pragma once
 
 #include "common.h"
+#include "projidx.h"
 
 namespace dect {
 
@@ -52,6 +53,28 @@ struct ProjArgs {
     const T* OT;
     T* sino;
     int nx, ny, Vb, D;
+    int views, chunk;  // base views per wave (a power of two) and bin groups per XCD turn
+};
+
+// Fixed-order reductions of block partials and the scalar updates (one block per
+// slice, or the last workgroup of a transpose).  scal == nullptr marks an empty slot.
+enum RedMode : int { RED_NONE = 0, RED_ALPHA = 1, RED_BETA = 2, RED_FINAL = 3 };
+
+struct RedArgs {
+    const double* tiles;
+    int nb_tiles;
+    const double* img;
+    int nb_img;
+    const double* sino;
+    int nb_sino;
+    const double* pre;   // preconditioner partials (r . z), used for gamma with PCG
+    int nb_pre;
+    int precond;
+    double* scal;
+    double* log;
+    int rho_mode;
+    int dual;  // dual-residual partials present
+    double bal_mu, bal_tau, next_rho_c, next_rho_p;
 };
 
 template <typename T>
@@ -98,77 +121,53 @@ __device__ inline void block_sum_store(double (&v)[K], double* out) {
         for (int k = 0; k < K; ++k) out[k] = (sh[0][k] + sh[1][k]) + (sh[2][k] + sh[3][k]);
 }
 
-// Fixed-order sum of K slots over nb block partials (kPartialSlots doubles each) by
-// a 256-thread block; the result reaches all threads.  Thread t adds partials t,
-// t + 256, ... in that order; the loads of 8 of them are issued before they are
-// added, so the thread waits on memory once per 8 partials.
+// Fixed-order sum of K slots over nb block partials (kPartialSlots doubles each); the
+// result reaches all threads.  The order is that of 256 summing threads whatever the
+// block size (any multiple of 64 of at least 128; every thread must call it):
+// summing thread t adds partials t, t + 256, ... in that order, the loads of 8 of them
+// issued before they are added, so it waits on memory once per 8 partials; each wave
+// of summing threads then adds its 64 sums by a fixed shuffle tree and the four wave
+// sums are added pairwise.  A block of 128 threads runs two summing threads per
+// thread, a block of 512 leaves its upper half idle.
 template <int K>
 __device__ inline void partial_sum(const double* __restrict__ base, int nb, double (&out)[K]) {
+    __shared__ double sh[4][K];
     __shared__ double res[K];
-    constexpr int U = 8;
-    const int nt = blockDim.x;
-    double v[K];
+    constexpr int NT = 256, U = 8;
+    for (int t = threadIdx.x; t < NT; t += blockDim.x) {  // uniform over each wave
+        double v[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = 0.0;
-    int b = threadIdx.x;
-    for (; b + (U - 1) * nt < nb; b += U * nt) {
-        double t[U][K];
+        for (int k = 0; k < K; ++k) v[k] = 0.0;
+        int b = t;
+        for (; b + (U - 1) * NT < nb; b += U * NT) {
+            double w[U][K];
 #pragma unroll
-        for (int u = 0; u < U; ++u)
+            for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int k = 0; k < K; ++k) t[u][k] = base[(size_t)(b + u * nt) * kPartialSlots + k];
+                for (int k = 0; k < K; ++k) w[u][k] = base[(size_t)(b + u * NT) * kPartialSlots + k];
 #pragma unroll
-        for (int u = 0; u < U; ++u)
+            for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int k = 0; k < K; ++k) v[k] += t[u][k];
+                for (int k = 0; k < K; ++k) v[k] += w[u][k];
+        }
+        for (; b < nb; b += NT)
+#pragma unroll
+            for (int k = 0; k < K; ++k) v[k] += base[(size_t)b * kPartialSlots + k];
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_down(v[k], off, 64);
+        if ((t & 63) == 0)
+#pragma unroll
+            for (int k = 0; k < K; ++k) sh[t >> 6][k] = v[k];
     }
-    for (; b < nb; b += nt)
+    __syncthreads();
+    if (threadIdx.x == 0)
 #pragma unroll
-        for (int k = 0; k < K; ++k) v[k] += base[(size_t)b * kPartialSlots + k];
-    block_sum_store<K>(v, res);
+        for (int k = 0; k < K; ++k) res[k] = (sh[0][k] + sh[1][k]) + (sh[2][k] + sh[3][k]);
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < K; ++k) out[k] = res[k];
     __syncthreads();
-}
-
-// Projector workgroups: 64 / kProjViews consecutive bins of kProjViews consecutive
-// base views (lane = bin * kProjViews + view), so the lanes of a wave read nearby
-// image rows at every step.
-// Measured at 512^2 / 720 x 1024 with 8 waves, each taking its share of the lines the
-// workgroup's rays cross: 1 view (64 bins) 147 us, 2 views (32 bins) 120 us, 4 views
-// 141 us, 8 views 145 us.
-#ifndef DECT_PJ_VIEWS
-#define DECT_PJ_VIEWS 2
-#endif
-constexpr int kProjViews = DECT_PJ_VIEWS;
-static_assert(kProjViews == 1 || kProjViews == 2 || kProjViews == 4 || kProjViews == 8 ||
-                  kProjViews == 16 || kProjViews == 32,
-              "projector views per wave");
-__host__ __device__ inline int proj_grid_x(int D) { return (D + 64 / kProjViews - 1) / (64 / kProjViews); }
-__host__ __device__ inline int proj_grid_y(int Vb) { return (Vb + kProjViews - 1) / kProjViews; }
-
-// Projector workgroup order.  The dispatcher hands consecutive workgroup ids to the
-// kXcds XCDs in turn, each with its own L2.  The gx bin groups form chunks of
-// kProjChunk; XCD x takes chunks x, x + kXcds, ... and runs every view group of a
-// chunk before the next one.  The rays in flight on one XCD then pass through a few
-// narrow annuli of the image, whose part of the orbit images its L2 can hold, and
-// each XCD still gets bins from across the whole detector, so the XCDs' shares of
-// ray length balance.  Measured at 512^2 / 720 x 1024: chunks of 1, 2, 4, 8 and 16
-// bin groups (of 8 bins, 8 views per wave) took 146, 149, 153, 160 and 244 us against
-// 163 us in the plain bins-then-views order; 16 leaves one chunk per XCD and unequal
-// ray lengths.
-#ifndef DECT_PJ_CHUNK
-#define DECT_PJ_CHUNK 1
-#endif
-constexpr int kXcds = 8;
-constexpr int kProjChunk = DECT_PJ_CHUNK;
-static_assert(kProjChunk >= 1, "projector chunk");
-// Workgroups of one slice's projector launch (a multiple of kXcds; ids whose chunk
-// lies past the last bin group exit at once).
-inline unsigned proj_blocks(int gx, int gy) {
-    const int chunks = (gx + kProjChunk - 1) / kProjChunk;
-    return (unsigned)(kXcds * ((chunks + kXcds - 1) / kXcds) * kProjChunk * gy);
 }
 
 template <typename T>
@@ -208,6 +207,10 @@ struct TvArgs {
     T* dz;
     const double* scal;
     double* partials;
+    // The pending last CG step (x + alpha p, alpha = scal[S_ALPHA]), which the rescale
+    // kernel stores at the end of the iteration: the TV update reads x through it.
+    // step_p == nullptr: none (x is current).
+    const T* step_p;
 };
 
 template <typename T>
@@ -231,6 +234,7 @@ struct UdmArgs {
     T* t;          // [M][2] next right-hand side a + u^a - R x, or nullptr (not kept)
     T* da;         // [M][2] a - a_prev
     T* fg;         // [M][8] f_h, f_l, grad f_h, grad f_l at the current a (internal order)
+    uint8_t* lmbits;  // ADMM a-step: [M] accept decisions of its LM iterations, or nullptr
     const double* scal;  // device scalars (rho, alpha)
     double* partials;
     double rho_c, rho_p;  // standalone/init penalties
@@ -311,26 +315,14 @@ struct RescaleArgs {
     const double* scal;
     double* h;  // R^T (a - R x) of the new iterate
     double* u;  // R^T u^a: u <- kappa (u + h)
+    // The iteration's last CG step, applied here: x += alpha p and h -= alpha R^T R p,
+    // alpha = scal[S_ALPHA] (the TV update read x through it before).  x == nullptr:
+    // none.
+    T* x;
+    const T* p;
+    const T* rtrp;
 };
 
-// Fixed-order reductions of block partials and the scalar updates (one block per
-// slice).  scal == nullptr marks an empty slot.
-struct RedArgs {
-    const double* tiles;
-    int nb_tiles;
-    const double* img;
-    int nb_img;
-    const double* sino;
-    int nb_sino;
-    const double* pre;   // preconditioner partials (r . z), used for gamma with PCG
-    int nb_pre;
-    int precond;
-    double* scal;
-    double* log;
-    int rho_mode;
-    int dual;  // dual-residual partials present
-    double bal_mu, bal_tau, next_rho_c, next_rho_p;
-};
 
 // Every argument block of one slice's outer iteration, and its launch extents.
 template <typename T>
@@ -348,6 +340,7 @@ struct SliceJob {
     long N, M;
     int sym, bp_gx, bp_gy, pj_gx, pj_gy;
     int bp_waves, pj_waves;  // workgroup shapes of the plan
+    int pj_views, pj_chunk;  // projector lane layout and workgroup order of the plan
     int cg_iters, rho_mode;  // launch structure: slices share launches only if these agree
 };
 

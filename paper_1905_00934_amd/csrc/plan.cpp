@@ -7,6 +7,7 @@
 #include <new>
 
 #include "common.h"
+#include "projidx.h"
 
 namespace dect {
 
@@ -32,46 +33,6 @@ dect_status fail(dect_status st, const char* fmt, ...) {
 }
 
 namespace {
-
-struct HostRay {
-    double phi0, slope, step;
-    bool xstep;
-};
-
-// Joseph parameters of ray (v, b), from the ray's line in scanner coordinates.
-HostRay host_ray(const dect_geometry& g, int v, int b) {
-    const double t = g.angle0 + (double)v * g.span / (double)g.n_views;
-    const double c = std::cos(t), s = std::sin(t);
-    const double u = ((double)b - 0.5 * (double)(g.n_det - 1) + g.det_offset) * g.det_cm;
-    double ox, oy, dx, dy;
-    if (g.kind == DECT_PARALLEL) {
-        ox = u * c;
-        oy = u * s;
-        dx = -s;
-        dy = c;
-    } else {
-        ox = g.src_iso_cm * c;
-        oy = g.src_iso_cm * s;
-        const double qx = -(g.src_det_cm - g.src_iso_cm) * c - u * s;
-        const double qy = -(g.src_det_cm - g.src_iso_cm) * s + u * c;
-        dx = qx - ox;
-        dy = qy - oy;
-    }
-    const double d = g.pixel_cm, cx = 0.5 * (g.nx - 1), cy = 0.5 * (g.ny - 1);
-    HostRay r;
-    if (std::fabs(dx) >= std::fabs(dy)) {
-        // Row coordinate where the ray crosses column i: linear in i.
-        r.xstep = true;
-        r.slope = dy / dx;
-        r.phi0 = (oy - ox * r.slope) / d - cx * r.slope + cy;
-    } else {
-        r.xstep = false;
-        r.slope = dx / dy;
-        r.phi0 = (ox - oy * r.slope) / d - cy * r.slope + cx;
-    }
-    r.step = d * std::sqrt(1.0 + r.slope * r.slope);
-    return r;
-}
 
 template <typename T>
 dect_status upload(const void* host, size_t bytes, void** dev) {
@@ -349,6 +310,8 @@ void make_layout(dect_plan* p) {
     p->off_partials = take((size_t)(p->nb_sino + p->nb_img + p->nb_tiles + p->nb_pre) *
                            kPartialSlots * sizeof(double));
     p->off_log = take((size_t)kLogCap * kLogStride * sizeof(double));
+    // Accept decisions of the last a-update's LM iterations, one byte per ray.
+    L.lm_accept = take(M);
     L.bytes = off;
 }
 
@@ -484,6 +447,7 @@ dect_status dect_plan_get_info(const dect_plan* p, dect_plan_info* out) {
     dect_plan_info info{};
     info.n_pixels = p->N;
     info.n_rays = p->M;
+    info.symmetry = p->sym;
     // Same sampling rule as the projector, in double precision.
     // Views beyond the base views are rotations of them: same counts.
     for (int v = 0; v < p->Vb; ++v)

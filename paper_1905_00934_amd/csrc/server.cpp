@@ -344,8 +344,8 @@ size_t dect_serve_footprint(const dect_plan* plan) { return plan ? footprint(pla
 dect_status dect_server_create(const dect_server_config* cfg, dect_server** out) {
     if (!out || !cfg) return fail(DECT_E_ARG, "null argument");
     *out = nullptr;
-    if (cfg->max_slots < 1 || cfg->step_iters < 1)
-        return fail(DECT_E_ARG, "max_slots and step_iters must be >= 1");
+    if (cfg->max_slots < 1 || cfg->step_iters < 1 || cfg->max_queue < 0)
+        return fail(DECT_E_ARG, "max_slots and step_iters must be >= 1, max_queue >= 0");
     std::unique_ptr<dect_server> S(new (std::nothrow) dect_server());
     if (!S) return fail(DECT_E_NOMEM, "out of host memory");
     S->cfg = *cfg;
@@ -390,6 +390,10 @@ dect_status dect_serve_submit(dect_server* S, const dect_request* req, uint64_t*
     r->t_submit = Clock::now();
     std::lock_guard<std::mutex> lk(S->mu);
     if (S->fatal) return fail(S->fatal, "the server stopped after a device error");
+    if (S->cfg.max_queue > 0 && (int64_t)S->queue.size() >= S->cfg.max_queue) {
+        S->stats.rejected++;
+        return fail(DECT_E_CAPACITY, "the queue holds its limit of %d requests", S->cfg.max_queue);
+    }
     r->ticket = S->next_ticket++;
     *ticket = r->ticket;
     S->pending.insert(r->ticket);

@@ -17,10 +17,12 @@
 // Transpose: one lane owns the rotation orbit of a pixel.  For every base view
 // and every orbit member it locates, from the central projection of the
 // two-pixel segment around the pixel, the bins whose samples can touch it, and
-// re-evaluates each candidate's interpolation weight with the projector's own
-// fma on the same table values; each weight serves SYM (pixel, view) pairs.
-// The weights are bit-identical to the projector's, so R^T is the transpose of R
-// up to summation order.  The views are split over the waves of a workgroup and
+// re-evaluates each candidate's interpolation weight from the same ray geometry;
+// each weight serves SYM (pixel, view) pairs.  The projector forms a0 + alpha (a1 -
+// a0) per sample and scales by the step length at the end, while the transpose
+// forms the weight step max(0, 1 - |d|) explicitly (on symmetric plans from the
+// signed-distance ray records), so the pair is a transpose up to rounding (FP64
+// adjointness to 1e-12), not bit for bit.  The views are split over the waves of a workgroup and
 // the wave sums are added in a fixed order through LDS.
 #include "common.h"
 #include "epilogue.h"
@@ -138,8 +140,8 @@ __global__ __launch_bounds__(256) void k_orbit_tiled(const OrbitArgs<T>* __restr
 
 // R for base rays: QUAD = true writes [Vb][D][SYM][CH] records, false writes the
 // standard [V][D][CH] layout (view v + k*Vb for rotation k).  A workgroup owns
-// 64 / kProjViews consecutive bins of kProjViews consecutive base views (one ray
-// per lane), in the XCD-aware order of proj_blocks; its KS waves step through KS
+// 64 / views consecutive bins of `views` consecutive base views (one ray per lane),
+// in the XCD-aware order of proj_blocks; its KS waves step through KS
 // disjoint ranges of the image lines its rays cross (so the lanes of a wave read
 // one image line together) and wave 0 adds the KS partial sums in order.
 template <typename T, int CH, int SYM, bool QUAD, int KS, bool BATCH>
@@ -149,20 +151,19 @@ __global__ __launch_bounds__(64 * KS) void k_project(const ProjArgs<T>* __restri
     __shared__ T red[KS > 1 ? KS - 1 : 1][64][W];
     const ProjArgs<T> A = pick_args<BATCH>(dev, one);
     const int nx = A.nx, ny = A.ny, Vb = A.Vb, D = A.D;
-    constexpr int BV = kProjViews, BB = 64 / kProjViews;
-    const int gy = proj_grid_y(Vb);
-    const int xcd = blockIdx.x % kXcds, nth = blockIdx.x / kXcds;
-    const int chunk = xcd + kXcds * (nth / (kProjChunk * gy)), within = nth % (kProjChunk * gy);
-    const int bg = chunk * kProjChunk + within / gy, vg = within % gy;
-    if (bg >= proj_grid_x(D)) return;  // past the last bin group of this slice
+    const int BV = A.views, lbv = __builtin_ctz((unsigned)A.views);
+    const int BB = 64 >> lbv;
+    int bg, vg;
+    proj_tile(blockIdx.x, proj_grid_y(Vb, BV), A.chunk, bg, vg);
+    if (bg >= proj_grid_x(D, BV)) return;  // past the last bin group of this slice
     const RayParam<T>* __restrict__ rays = A.rays;
     const vec<T, W>* __restrict__ O = reinterpret_cast<const vec<T, W>*>(A.O);
     const vec<T, W>* __restrict__ OT = reinterpret_cast<const vec<T, W>*>(A.OT);
     T* __restrict__ sino = A.sino;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int v = vg * BV + lane % BV;
-    const int b = bg * BB + lane / BV;
+    const int v = vg * BV + (lane & (BV - 1));
+    const int b = bg * BB + (lane >> lbv);
     const bool valid = b < D && v < Vb;
     RayParam<T> r = rays[(size_t)(v < Vb ? v : Vb - 1) * D + (b < D ? b : D - 1)];
     const bool xs = r.pad == T(0);
@@ -170,19 +171,9 @@ __global__ __launch_bounds__(64 * KS) void k_project(const ProjArgs<T>* __restri
     const int n_lines = xs ? ny : nx;   // interpolation axis
     const vec<T, W>* src = xs ? OT : O;  // [n_steps][n_lines]
     // Outside [k0, k1] both taps of every sample are outside the image, so the
-    // restriction changes no term; the one-step margin absorbs rounding.
-    int k0 = 0, k1 = n_steps - 1;
-    if (r.slope != T(0)) {
-        const T t1 = (T(-1) - r.phi0) / r.slope;
-        const T t2 = (T(n_lines) - r.phi0) / r.slope;
-        const T lo = fmax(t1 < t2 ? t1 : t2, T(-2));
-        const T hi = fmin(t1 < t2 ? t2 : t1, T(n_steps + 1));
-        const int kl = (int)floor(lo) - 1, kh = (int)ceil(hi) + 1;
-        k0 = kl > 0 ? kl : 0;
-        k1 = kh < n_steps - 1 ? kh : n_steps - 1;
-    } else if (!(r.phi0 >= T(-1) && r.phi0 < T(n_lines))) {
-        k1 = -1;
-    }
+    // restriction changes no term.
+    int k0, k1;
+    proj_ray_range<T>(r.phi0, r.slope, n_steps, n_lines, k0, k1);
     // This wave's share of the lines: every wave holds the same 64 rays, so each
     // computes the same union [s0, s1] of their ranges and takes its KS-th of it
     // (an even split of all lines would leave most waves idle on short chords).
@@ -194,9 +185,8 @@ __global__ __launch_bounds__(64 * KS) void k_project(const ProjArgs<T>* __restri
         s0 = a < s0 ? a : s0;
         s1 = c > s1 ? c : s1;
     }
-    if (s1 < s0) s0 = 0, s1 = -1;
-    const int len = s1 - s0 + 1;
-    const int c0 = s0 + wave * len / KS, c1 = s0 + (wave + 1) * len / KS - 1;
+    int c0, c1;
+    proj_wave_share(s0, s1, wave, KS, c0, c1);
     k0 = k0 > c0 ? k0 : c0;
     k1 = k1 < c1 ? k1 : c1;
     if (!valid) k1 = -1;
@@ -206,13 +196,9 @@ __global__ __launch_bounds__(64 * KS) void k_project(const ProjArgs<T>* __restri
     int k = k0;
     // Two samples per trip so that four loads are in flight per lane.
     for (; k + 1 <= k1; k += 2) {
-        const T pa = fma(r.slope, (T)k, r.phi0);
-        const T pb = fma(r.slope, (T)(k + 1), r.phi0);
-        T fa = floor(pa), fb = floor(pb);
-        const T aa = pa - fa, ab = pb - fb;
-        fa = fmin(fmax(fa, T(-2)), T(n_lines + 1));
-        fb = fmin(fmax(fb, T(-2)), T(n_lines + 1));
-        const int ja = (int)fa, jb = (int)fb;
+        T aa, ab;
+        const int ja = proj_tap<T>(r.phi0, r.slope, k, n_lines, aa);
+        const int jb = proj_tap<T>(r.phi0, r.slope, k + 1, n_lines, ab);
         const vec<T, W>* la = src + (size_t)k * n_lines;
         const vec<T, W>* lb = la + n_lines;
         vec<T, W> a0, a1, b0, b1;
@@ -226,11 +212,8 @@ __global__ __launch_bounds__(64 * KS) void k_project(const ProjArgs<T>* __restri
             acc[c] += (a0.v[c] + aa * (a1.v[c] - a0.v[c])) + (b0.v[c] + ab * (b1.v[c] - b0.v[c]));
     }
     if (k <= k1) {
-        const T pa = fma(r.slope, (T)k, r.phi0);
-        T fa = floor(pa);
-        const T aa = pa - fa;
-        fa = fmin(fmax(fa, T(-2)), T(n_lines + 1));
-        const int ja = (int)fa;
+        T aa;
+        const int ja = proj_tap<T>(r.phi0, r.slope, k, n_lines, aa);
         const vec<T, W>* la = src + (size_t)k * n_lines;
         vec<T, W> a0, a1;
         vzero(a0); vzero(a1);
@@ -284,7 +267,7 @@ __device__ inline float fast_rcp<float>(float x) { return __builtin_amdgcn_rcpf(
 // type says which pixel coordinate it samples along, and the weight
 // max(0, step (1 - |phi - p|)) is the projector's linear-interpolation weight of
 // the pixel at minor coordinate p for the sample at phi, phi computed with the
-// projector's own fma on the same table entries.
+// same fma on the same table entries as the projector's sample position.
 template <typename T, int CH, int SYM, int VS>
 __device__ inline void gather_orbit(const BpArgs<T>& a, int wave, int i, int j,
                                     T (&acc)[SYM][CH]) {
@@ -446,23 +429,47 @@ __device__ inline void gather_orbit_staged(const BpArgs<T>& a, int wave, int lan
 // ~35 for blocks near the source, so 16 bins left most waves loading some
 // candidates directly; with 32 that is rare.
 
-// Each lane stages WIN * SYM / 64 records.
+// A staged candidate of the wide window: its ray record and its quad of sinogram
+// values side by side (48 bytes for two FP32 channels), so that one address steps
+// through the window.
+template <typename T, int CH, int SYM>
+struct alignas(sizeof(T) * 4) Staged {
+    BpRay<T> r;
+    T s[SYM * CH];
+};
+constexpr int kWideWin = 32;
+// Candidates every lane takes from its window before looping over the rest: most
+// footprints hold two or three, and a candidate past a pixel's footprint has weight
+// exactly zero (its ray passes more than a pixel step away), so the loop's control
+// flow is saved where most lanes need it least.  Each orbit member's window is
+// followed by kBpFixed zero records, so that those reads never leave it.
+#ifndef DECT_BP_FIXED
+#define DECT_BP_FIXED 0
+#endif
+constexpr int kBpFixed = DECT_BP_FIXED;
+constexpr int kWideStride = kWideWin + kBpFixed;
+
+// Each lane stages WIN * SYM / 64 records.  s_win: the workgroup's staging windows,
+// [VS][SYM members][kWideStride]; each wave uses only its own row.
 template <typename T, int CH, int SYM, int VS>
 __device__ inline void gather_orbit_staged_wide(const BpArgs<T>& a, int wave, int lane, int i, int j,
-                                           bool inside, T (&acc)[SYM][CH]) {
-    constexpr int WIN = 32;
+                                                bool inside, T (&acc)[SYM][CH],
+                                                Staged<T, CH, SYM> (*s_win)[kWideStride * SYM]) {
+    constexpr int WIN = kWideWin;
     constexpr int REC = WIN * SYM;
     constexpr int PER = (REC + 63) / 64;
     static_assert(WIN % 16 == 0 && (REC <= 64 || REC % 64 == 0), "window layout");
+    static_assert(kBpFixed * SYM <= 64, "padding records per wave");
+    if constexpr (kBpFixed > 0) {
+        if (lane < kBpFixed * SYM) {  // the zero records after each window
+            Staged<T, CH, SYM>& z =
+                s_win[wave][(lane / kBpFixed) * kWideStride + WIN + lane % kBpFixed];
+            z.r = BpRay<T>{};
+#pragma unroll
+            for (int c = 0; c < SYM * CH; ++c) z.s[c] = T(0);
+        }
+    }
     using Q = vec<T, SYM * CH>;
-    // A staged candidate: its ray record and its quad of sinogram values side by
-    // side (48 bytes for two FP32 channels), so that one address steps through the
-    // window.
-    struct alignas(sizeof(T) * 4) Staged {
-        BpRay<T> r;
-        T s[SYM * CH];
-    };
-    __shared__ Staged s_win[VS][REC];
     const T m = (T)a.margin;
     const int D = a.D, Vb = a.Vb, n = a.nx;
     const T cx = T(0.5) * (T)(a.nx - 1), cy = T(0.5) * (T)(a.ny - 1);
@@ -514,9 +521,11 @@ __device__ inline void gather_orbit_staged_wide(const BpArgs<T>& a, int wave, in
 #pragma unroll
         for (int q = 0; q < PER; ++q)
             if (stager[q]) {
-                s_win[wave][lane + 64 * q].r = pr[q];
+                const int rec = lane + 64 * q;
+                Staged<T, CH, SYM>& d = s_win[wave][(rec / WIN) * kWideStride + rec % WIN];
+                d.r = pr[q];
 #pragma unroll
-                for (int c = 0; c < SYM * CH; ++c) s_win[wave][lane + 64 * q].s[c] = pq[q].v[c];
+                for (int c = 0; c < SYM * CH; ++c) d.s[c] = pq[q].v[c];
             }
         // LDS operations of one wave complete in order; the barrier only keeps the
         // compiler from moving the reads above the writes.
@@ -558,10 +567,13 @@ __device__ inline void gather_orbit_staged_wide(const BpArgs<T>& a, int wave, in
                 // nothing).  The rest (a steep footprint near the source, rare) are
                 // loaded directly, after them, when some lane of the wave has any.
                 const T x = bq + (w.boff - (T)L[mm]);
-                const int ilo = (int)ceil(fmax(x - h, T(0)));
+                const int ilo = min((int)ceil(fmax(x - h, T(0))), WIN);
                 const int ihi = (int)floor(fmin(x + h, T(WIN - 1)));
-                const Staged* sw = &s_win[wave][mm * WIN];
-                for (const Staged *c = sw + ilo, *e = sw + ihi; c <= e; ++c) add(c->r, c->s);
+                const Staged<T, CH, SYM>* sw = &s_win[wave][mm * kWideStride];
+                const Staged<T, CH, SYM>* c = sw + ilo;
+#pragma unroll
+                for (int t = 0; t < kBpFixed; ++t) add(c[t].r, c[t].s);
+                for (c += kBpFixed; c <= sw + ihi; ++c) add(c->r, c->s);
                 if (__any(x - h < T(0) || x + h > T(WIN - 1))) {
                     const T bc = bq + w.boff;
                     const int lo = (int)ceil(fmax(bc - h, T(0)));
@@ -583,7 +595,22 @@ __device__ inline void gather_orbit_staged_wide(const BpArgs<T>& a, int wave, in
 template <typename T, int CH, int SYM, bool QUAD, int EPI, int VS, bool BATCH>
 __global__ __launch_bounds__(64 * VS) void k_backproject(const BpArgs<T>* __restrict__ dev,
                                                          BpArgs<T> one) {
-    __shared__ T red[VS > 1 ? VS - 1 : 1][64][SYM * CH];
+    // The ADMM epilogues (q, dual) run one orbit member per wave; the plain transpose
+    // keeps the reduction into wave 0.
+    constexpr bool kFinish = EPI == EPI_Q || EPI == EPI_DUAL;
+    constexpr bool kWide = QUAD && SYM == 4;
+    // The wide staging windows, one row per wave.  For the ADMM epilogues each wave
+    // then stores its view sums over its own (by then idle) row.
+    using St = Staged<T, CH, SYM>;
+    __shared__ St s_win[kWide ? VS : 1][kWide ? kWideStride * SYM : 1];
+    constexpr int kRed = kFinish ? (kWide ? 1 : VS) : (VS > 1 ? VS - 1 : 1);
+    __shared__ T red_own[kRed][64][SYM * CH];
+    static_assert(!kWide || sizeof(T) * 64 * SYM * CH <= sizeof(St) * kWideStride * SYM,
+                  "a wave's view sums fit in its staging row");
+    auto red = [&](int w) -> T(*)[SYM * CH] {
+        if constexpr (kFinish && kWide) return reinterpret_cast<T(*)[SYM * CH]>(&s_win[w][0]);
+        else return red_own[w];
+    };
     const BpArgs<T> a = pick_args<BATCH>(dev, one);
     if ((int)blockIdx.x >= a.gx || (int)blockIdx.y >= a.gy) return;  // beyond this slice
     const int lane = threadIdx.x & 63;
@@ -597,52 +624,99 @@ __global__ __launch_bounds__(64 * VS) void k_backproject(const BpArgs<T>* __rest
     for (int k = 0; k < SYM; ++k)
 #pragma unroll
         for (int c = 0; c < CH; ++c) acc[k][c] = T(0);
-    if constexpr (QUAD && SYM == 4)
-        gather_orbit_staged_wide<T, CH, SYM, VS>(a, wave, lane, i, j, inside, acc);
+    if constexpr (kWide)
+        gather_orbit_staged_wide<T, CH, SYM, VS>(a, wave, lane, i, j, inside, acc, s_win);
     else if constexpr (QUAD)
         gather_orbit_staged<T, CH, SYM, VS>(a, wave, lane, i, j, inside, acc);
     else if (inside)
         gather_orbit<T, CH, SYM, VS>(a, wave, i, j, acc);
-    if constexpr (VS > 1) {
-        if (wave > 0)
+    if constexpr (kFinish) {
+        // Every wave's view sums go to LDS; wave w then finishes orbit members w, w + VS,
+        // ...: it adds the waves' sums in wave order, runs the epilogue of its member
+        // and reduces its partials over its lanes; thread 0 adds the members' partials
+        // in member order.
+        __shared__ double wpart[SYM][2];
+        {
+            T(*mine)[SYM * CH] = red(wave);
 #pragma unroll
             for (int k = 0; k < SYM; ++k)
 #pragma unroll
-                for (int c = 0; c < CH; ++c) red[wave - 1][lane][k * CH + c] = acc[k][c];
+                for (int c = 0; c < CH; ++c) mine[lane][k * CH + c] = acc[k][c];
+        }
         __syncthreads();
-        if (wave == 0)
-            for (int w = 0; w < VS - 1; ++w)
+        for (int k = wave; k < SYM; k += VS) {
+            T res[2] = {T(0), T(0)};
+            for (int w = 0; w < VS; ++w)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) res[c] += red(w)[lane][k * CH + (CH > 1 ? c : 0)];
+            double part[2] = {0.0, 0.0};
+            if (inside) {
+                int io, jo;
+                rot(k, a.nx, i, j, io, jo);
+                epilogue<T, EPI>(a, io, jo, res, part);
+            }
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+                for (int off = 32; off > 0; off >>= 1) part[c] += __shfl_down(part[c], off, 64);
+            if (lane == 0) {
+                wpart[k][0] = part[0];
+                wpart[k][1] = part[1];
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double o0 = 0.0, o1 = 0.0;
+            for (int k = 0; k < SYM; ++k) {
+                o0 += wpart[k][0];
+                o1 += wpart[k][1];
+            }
+            double* o = a.partials + (size_t)(blockIdx.y * a.gx + blockIdx.x) * kPartialSlots;
+            o[0] = o0;
+            o[1] = o1;
+        }
+        return;
+    } else {
+        if constexpr (VS > 1) {
+            if (wave > 0)
 #pragma unroll
                 for (int k = 0; k < SYM; ++k)
 #pragma unroll
-                    for (int c = 0; c < CH; ++c) acc[k][c] += red[w][lane][k * CH + c];
-    }
-    if (wave != 0) return;
-    double part[2] = {0.0, 0.0};
-    if (inside) {
+                    for (int c = 0; c < CH; ++c) red_own[wave - 1][lane][k * CH + c] = acc[k][c];
+            __syncthreads();
+            if (wave == 0)
+                for (int w = 0; w < VS - 1; ++w)
 #pragma unroll
-        for (int k = 0; k < SYM; ++k) {
-            int io, jo;
-            rot(k, a.nx, i, j, io, jo);
-            if constexpr (EPI == EPI_NONE) {
-                vec<T, CH> o;
+                    for (int k = 0; k < SYM; ++k)
 #pragma unroll
-                for (int c = 0; c < CH; ++c) o.v[c] = acc[k][c];
-                reinterpret_cast<vec<T, CH>*>(a.out)[(size_t)jo * a.nx + io] = o;
-            } else {
-                T res[2] = {acc[k][0], acc[k][CH > 1 ? 1 : 0]};
-                epilogue<T, EPI>(a, io, jo, res, part);
+                        for (int c = 0; c < CH; ++c) acc[k][c] += red_own[w][lane][k * CH + c];
+        }
+        if (wave != 0) return;
+        double part[2] = {0.0, 0.0};
+        if (inside) {
+#pragma unroll
+            for (int k = 0; k < SYM; ++k) {
+                int io, jo;
+                rot(k, a.nx, i, j, io, jo);
+                if constexpr (EPI == EPI_NONE) {
+                    vec<T, CH> o;
+#pragma unroll
+                    for (int c = 0; c < CH; ++c) o.v[c] = acc[k][c];
+                    reinterpret_cast<vec<T, CH>*>(a.out)[(size_t)jo * a.nx + io] = o;
+                } else {
+                    T res[2] = {acc[k][0], acc[k][CH > 1 ? 1 : 0]};
+                    epilogue<T, EPI>(a, io, jo, res, part);
+                }
             }
         }
-    }
-    if constexpr (EPI != EPI_NONE) {
+        if constexpr (EPI != EPI_NONE) {
 #pragma unroll
-        for (int c = 0; c < 2; ++c)
-            for (int off = 32; off > 0; off >>= 1) part[c] += __shfl_down(part[c], off, 64);
-        if (lane == 0) {
-            double* o = a.partials + (size_t)(blockIdx.y * a.gx + blockIdx.x) * kPartialSlots;
-            o[0] = part[0];
-            o[1] = part[1];
+            for (int c = 0; c < 2; ++c)
+                for (int off = 32; off > 0; off >>= 1) part[c] += __shfl_down(part[c], off, 64);
+            if (lane == 0) {
+                double* o = a.partials + (size_t)(blockIdx.y * a.gx + blockIdx.x) * kPartialSlots;
+                o[0] = part[0];
+                o[1] = part[1];
+            }
         }
     }
 }
@@ -669,7 +743,7 @@ void project_launch(const OrbitArgs<T>* odev, const OrbitArgs<T>& oone, const Pr
         }
     }
     ProfScope pp("project", s);
-    hipLaunchKernelGGL((k_project<T, CH, SYM, QUAD, KS, BATCH>), dim3(proj_blocks(gx, gy), 1, n), dim3(64 * KS),
+    hipLaunchKernelGGL((k_project<T, CH, SYM, QUAD, KS, BATCH>), dim3(proj_blocks(gx, gy, pone.chunk), 1, n), dim3(64 * KS),
                        0, s, pdev, pone);
 }
 
@@ -804,14 +878,17 @@ void fill_bp_plan(const dect_plan* p, BpArgs<T>& a) {
     a.gy = (dy + 7) / 8;
 }
 
+// R into the standard sinogram layout, with the two orbit images of the image in O and
+// OT (each N * ch * sym values of T).
 template <typename T>
-hipError_t launch_project(const dect_plan* p, const void* img, void* sino, int ch, hipStream_t s) {
-    OrbitArgs<T> o{static_cast<const T*>(img), static_cast<T*>(p->scratch_O),
-                   static_cast<T*>(p->scratch_OT), p->nx, p->ny};
-    ProjArgs<T> q{static_cast<const RayParam<T>*>(p->rays), static_cast<const T*>(p->scratch_O),
-                  static_cast<const T*>(p->scratch_OT), static_cast<T*>(sino), p->nx, p->ny,
-                  p->Vb, p->D};
-    const int gx = proj_grid_x(p->D), gy = proj_grid_y(p->Vb);
+hipError_t launch_project_with(const dect_plan* p, const void* img, void* sino, int ch, void* O_,
+                               void* OT_, hipStream_t s) {
+    T* O = static_cast<T*>(O_);
+    T* OT = static_cast<T*>(OT_);
+    OrbitArgs<T> o{static_cast<const T*>(img), O, OT, p->nx, p->ny};
+    ProjArgs<T> q{static_cast<const RayParam<T>*>(p->rays), O, OT, static_cast<T*>(sino), p->nx,
+                  p->ny, p->Vb, p->D, p->pj_views, p->pj_chunk};
+    const int gx = proj_grid_x(p->D, p->pj_views), gy = proj_grid_y(p->Vb, p->pj_views);
     if (p->sym == 4) {
         switch (ch) {
             case 1: return project_t<T, 1, 4, false, kLineSplit>(nullptr, o, nullptr, q, 1, p->N, gx, gy, s);
@@ -826,6 +903,11 @@ hipError_t launch_project(const dect_plan* p, const void* img, void* sino, int c
         }
     }
     return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_project(const dect_plan* p, const void* img, void* sino, int ch, hipStream_t s) {
+    return launch_project_with<T>(p, img, sino, ch, p->scratch_O, p->scratch_OT, s);
 }
 
 template <typename T>

@@ -35,17 +35,30 @@ __device__ inline void tv_dual_block(const TvArgs<T>& A, long blk) {
     if (pix < N) {
         const int j = (int)(pix / nx), i = (int)(pix % nx);
         const V2* x2 = reinterpret_cast<const V2*>(x);
-        const V2 xc = x2[pix];
+        const V2* p2 = reinterpret_cast<const V2*>(A.step_p);
+        // x after the iteration's last CG step, x + alpha p, when that step is still
+        // pending (the rescale kernel stores it with the same fma).
+        const T al[2] = {(T)scal[S_ALPHA], (T)scal[S_ALPHA + 1]};
+        auto xat = [&](long q) {
+            V2 v = x2[q];
+            if (p2) {
+                const V2 pv = p2[q];
+#pragma unroll
+                for (int c = 0; c < 2; ++c) v.v[c] = fma(al[c], pv.v[c], v.v[c]);
+            }
+            return v;
+        };
+        const V2 xc = xat(pix);
         V4 Dx;
         if (i < nx - 1) {
-            const V2 xr = x2[pix + 1];
+            const V2 xr = xat(pix + 1);
             Dx.v[0] = xr.v[0] - xc.v[0];
             Dx.v[1] = xr.v[1] - xc.v[1];
         } else {
             Dx.v[0] = Dx.v[1] = T(0);
         }
         if (j < ny - 1) {
-            const V2 xd = x2[pix + nx];
+            const V2 xd = xat(pix + nx);
             Dx.v[2] = xd.v[0] - xc.v[0];
             Dx.v[3] = xd.v[1] - xc.v[1];
         } else {

@@ -109,11 +109,14 @@ __device__ inline T det2(T a, T d, T b, T c) {
 // CONSTR (the constrained decomposition, a >= 0): a coordinate at zero whose
 // gradient is positive is held at zero and the damped step is taken in the other
 // coordinate alone; trial points are projected onto a >= 0.
+//
+// accepted: bit k set when LM iteration k (k < 32) accepted its trial point.
 template <typename T, bool CONSTR = false>
 __device__ inline void lm_solve(const T* __restrict__ spec, int kmax, int kh, int kl, T mh, T ml,
                                 T wh, T wl, T vc, T vp, T rc, T rp, int iters, T mu,
-                                StepBound sb, Point<T>& P) {
+                                StepBound sb, Point<T>& P, unsigned& accepted) {
     constexpr T log2e = T(1.4426950408889634);
+    accepted = 0u;
     for (int it = 0; it < iters; ++it) {
         const T rh = P.fh - mh, rl = P.fl - ml;
         const T Gc = wh * rh * P.ghc + wl * rl * P.glc + rc * (P.ac - vc);
@@ -169,6 +172,7 @@ __device__ inline void lm_solve(const T* __restrict__ spec, int kmax, int kh, in
         if (Q.phi < P.phi) {
             P = Q;
             mu *= T(0.1);
+            if (it < 32) accepted |= 1u << it;
         } else {
             mu *= T(10);
         }
@@ -252,8 +256,12 @@ __global__ __launch_bounds__(256) void k_udm(const UdmArgs<T>* __restrict__ dev,
         } else {
             evaluate<T>(spec, kmax, kh, kl, mh, ml, wh, wl, vc, vp, rc, rp, T(0), T(0), true, P);
         }
+        unsigned accepted;
         lm_solve<T, MODE == 3>(spec, kmax, kh, kl, mh, ml, wh, wl, vc, vp, rc, rp, A.iters,
-                               (T)A.mu0, sb, P);
+                               (T)A.mu0, sb, P, accepted);
+        if constexpr (MODE == 2) {
+            if (A.lmbits) A.lmbits[i] = (uint8_t)(accepted & 0xffu);
+        }
         V2 an;
         an.v[0] = P.ac;
         an.v[1] = P.ap;

@@ -61,7 +61,8 @@ class IterLog(ctypes.Structure):
 
 
 class PlanInfo(ctypes.Structure):
-    _fields_ = [(k, ctypes.c_int64) for k in ("n_pixels", "n_rays", "samples", "taps")]
+    _fields_ = [(k, ctypes.c_int64) for k in ("n_pixels", "n_rays", "samples", "taps",
+                                              "symmetry")]
 
 
 class KernelTime(ctypes.Structure):
@@ -71,7 +72,7 @@ class KernelTime(ctypes.Structure):
 
 class Layout(ctypes.Structure):
     _fields_ = [(k, ctypes.c_size_t) for k in
-                ("bytes", "x", "y", "uy", "z", "uz", "a", "ua", "Rx", "scalars")]
+                ("bytes", "x", "y", "uy", "z", "uz", "a", "ua", "Rx", "scalars", "lm_accept")]
 
 
 class LmcgLayout(ctypes.Structure):
@@ -81,13 +82,15 @@ class LmcgLayout(ctypes.Structure):
 
 class Launch(ctypes.Structure):
     _fields_ = [("bp_waves", ctypes.c_int), ("proj_waves", ctypes.c_int),
+                ("proj_views", ctypes.c_int), ("proj_chunk", ctypes.c_int),
                 ("bp_us", ctypes.c_double), ("proj_us", ctypes.c_double),
+                ("bp_us_default", ctypes.c_double), ("proj_us_default", ctypes.c_double),
                 ("from_cache", ctypes.c_int)]
 
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_slots", ctypes.c_int),
-                ("step_iters", ctypes.c_int)]
+                ("step_iters", ctypes.c_int), ("max_queue", ctypes.c_int)]
 
 
 class Request(ctypes.Structure):
@@ -106,7 +109,7 @@ class Result(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in ("submitted", "completed", "queued", "in_flight",
                                               "peak_in_flight", "steps")] + [
-        ("hbm_held", ctypes.c_size_t)]
+        ("hbm_held", ctypes.c_size_t), ("rejected", ctypes.c_int64)]
 
 
 _lib = None
@@ -155,7 +158,7 @@ def lib():
             "dect_cdm_fbp_start": [vp, vp, vp, vp, vp, i, vp, vp, vp, vp],
             "dect_admm_init_image": [vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(Params), vp],
             "dect_plan_tune": [vp, ctypes.c_char_p, i, ctypes.POINTER(Launch), vp],
-            "dect_plan_set_launch": [vp, i, i],
+            "dect_plan_set_launch": [vp, i, i, i, i],
             "dect_plan_get_launch": [vp, ctypes.POINTER(Launch)],
             "dect_server_create": [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)],
             "dect_serve_footprint": [vp],
@@ -289,6 +292,7 @@ class State:
         self.ua = view(L.ua, (V, D, 2))
         self.Rx = view(L.Rx, (V, D, 2))
         self.scalars = self.buf[L.scalars:L.scalars + 24 * 8].view(torch.float64)
+        self.lm_accept = self.buf[L.lm_accept:L.lm_accept + V * D].view(V, D)
 
     @property
     def ptr(self):
@@ -445,18 +449,22 @@ class Plan:
                                     1 if force else 0, ctypes.byref(L), _stream()))
         return {k: getattr(L, k) for k, _ in Launch._fields_}
 
-    def set_launch(self, bp_waves: int, proj_waves: int):
-        _check(lib().dect_plan_set_launch(self.handle, int(bp_waves), int(proj_waves)))
+    def set_launch(self, bp_waves: int, proj_waves: int, proj_views: int = 2,
+                   proj_chunk: int = 1):
+        _check(lib().dect_plan_set_launch(self.handle, int(bp_waves), int(proj_waves),
+                                          int(proj_views), int(proj_chunk)))
 
     def launch(self) -> dict:
         L = Launch()
         _check(lib().dect_plan_get_launch(self.handle, ctypes.byref(L)))
-        return {"bp_waves": L.bp_waves, "proj_waves": L.proj_waves}
+        return {"bp_waves": L.bp_waves, "proj_waves": L.proj_waves,
+                "proj_views": L.proj_views, "proj_chunk": L.proj_chunk}
 
     def info(self) -> dict:
         I = PlanInfo()
         _check(lib().dect_plan_get_info(self.handle, ctypes.byref(I)))
-        return dict(n_pixels=I.n_pixels, n_rays=I.n_rays, samples=I.samples, taps=I.taps)
+        return dict(n_pixels=I.n_pixels, n_rays=I.n_rays, samples=I.samples, taps=I.taps,
+                    symmetry=I.symmetry)
 
     def new_state(self) -> State:
         return State(self)
@@ -556,9 +564,11 @@ class Server:
     images as a host array.
     """
 
-    def __init__(self, max_slots: int = 64, step_iters: int = 5, hbm_budget: int = 0):
+    def __init__(self, max_slots: int = 64, step_iters: int = 5, hbm_budget: int = 0,
+                 max_queue: int = 0):
         C = ServerConfig()
         C.hbm_budget_bytes, C.max_slots, C.step_iters = int(hbm_budget), int(max_slots), int(step_iters)
+        C.max_queue = int(max_queue)
         h = ctypes.c_void_p()
         _check(lib().dect_server_create(ctypes.byref(C), ctypes.byref(h)))
         self.handle = h

@@ -217,6 +217,19 @@ def test_admm_fp64_tiny_matches_oracle(dect):
     for eg, eo in zip(log, ost.log):
         np.testing.assert_allclose(eg["r"], eo["r"], rtol=1e-7)
         np.testing.assert_allclose(eg["s"], eo["s"], rtol=1e-7)
+    _check_objective_log(log, ost.log)
+
+
+def _check_objective_log(log, olog, rtol_data=1e-9, rtol_tv=1e-8):
+    """The logged split objective (the serving stop criterion) against the oracle's:
+    the data fit 1/2 sum w (f(a) - m)^2 at the new a and lambda |y|_1 at the new y,
+    iteration by iteration."""
+    assert len(log) == len(olog)
+    for eg, eo in zip(log, olog):
+        assert eg["flags"] == 0
+        assert eg["data"] == pytest.approx(eo["data"], rel=rtol_data)
+        assert eg["tv"] == pytest.approx(eo["tv"], rel=rtol_tv, abs=1e-14)
+        assert eg["data"] + eg["tv"] == pytest.approx(eo["phi"], rel=rtol_data)
 
 
 def test_admm_fp64_symmetric_fan_matches_oracle(dect):
@@ -234,29 +247,100 @@ def test_admm_fp64_symmetric_fan_matches_oracle(dect):
     for b in range(2):
         assert rel(x[..., b], ost.x[b]) <= 1e-8
     assert [e["rho"] for e in log] == [tuple(e["rho"]) for e in ost.log]
+    _check_objective_log(log, ost.log)
 
 
-@pytest.mark.parametrize("n_iters,size", [(50, 256), (3, 512)])
-def test_admm_fp32_matches_oracle_after_fixed_iterations(dect, n_iters, size):
-    """FP32 fan-beam slices against the FP64 oracle; rho follows the oracle's own
-    residual-balancing decisions (a threshold decision that flips on rounding
-    would otherwise change the trajectory)."""
-    if size == 256:
-        pr = S.uneven_problem(0, with_image=False)
-    else:
-        pr = S.slice_problem(0, with_image=False)
+# Problems of the FP32 parity runs: the uneven mix's 256^2 / 360 x 512 and
+# 384^2 / 540 x 768 classes, and the single 512^2 / 720 x 1024 luggage slice.
+FP32_CASES = {
+    "fan256": lambda: S.uneven_problem(0, with_image=False),
+    "fan384": lambda: S.uneven_problem(1, with_image=False),
+    "fan512": lambda: S.slice_problem(0, with_image=False),
+}
+
+# A replayed single-precision decision that the oracle takes the other way, on a ray
+# whose decomposition both sides start from the same point (within SAME_A, absolute plus
+# relative), must be a near-tie.  LM accept test: |Phi(trial) - Phi(current)| within
+# LM_TIE_MAX rounding scales (2^-23 times the first-order error bound of Phi, which
+# includes the cancellation of f's log-sum-exp; the single-precision f carries besides
+# the rounding of a ~110-term sum and the hardware exp2/log2, a few tens of such units
+# at most).  Balancing test: r and mu s (or s and mu r) within RHO_TIE_MAX of each other,
+# relative (the residual norms agree with the oracle's to ~1e-5 in single precision).
+# The per-ray problem of Eq. (13) is not convex: where the two sides' starting points
+# have drifted apart, LM may follow different local paths; such rays are counted, and at
+# most SPLIT_MAX of them may end more than 1e-2 (absolute plus relative) apart.
+LM_TIE_MAX = 512.0
+RHO_TIE_MAX = 1e-3
+SAME_A = 1e-4
+SPLIT_MAX = 1e-3
+
+
+def _fp32_lockstep(dect, pr, n_iters):
+    """n_iters ADMM iterations of the FP32 library, one call each with its own adaptive rho,
+    and of the oracle on the same single-precision inputs replaying, iteration by
+    iteration, the library's LM accept decisions and rho choices.  Returns the oracle's
+    state, the library's state and log, and the largest near-tie ratio of a replayed LM
+    decision on a ray both sides started from the same point."""
+    r32 = lambda a: np.asarray(a, dtype=np.float32).astype(np.float64)
+    meas64 = [r32(m) for m in _meas(pr)]
+    orc = O.Oracle(pr.geom, pr.spec)
     prm = O.Params()
-    ost = _admm_oracle(pr, prm, n_iters)
-    sched = [tuple(e["rho"]) for e in ost.log] + [tuple(ost.rho)]
-    params = dect.AdmmParams(rho_mode=dect.RHO_SCHEDULE, rho_schedule=sched)
-    _, st, log = _admm_gpu(dect, pr, F32, params, n_iters)
+    ost = orc.admm_init(*meas64, prm)
+    plan = dect.Plan(pr.geom, pr.spec, F32)
+    meas = [dev(m, F32) for m in meas64]
+    params = dect.AdmmParams()
+    st = plan.new_state()
+    plan.admm_init(meas, st, params)
+    log, tie = [], 0.0
+    for k in range(n_iters):
+        a_lib = host(st.a)
+        same = np.all(np.abs(a_lib - np.moveaxis(ost.a, 0, -1))
+                      <= SAME_A * (1.0 + np.abs(a_lib)), axis=-1)
+        log += plan.admm_iterate(meas, st, params, 1, log=True)
+        bits = st.lm_accept.cpu().numpy().copy()
+        rho_next = tuple(float(v) for v in st.scalars[:2].cpu().numpy())
+        ost = orc.admm_iterate(ost, *meas64, prm, 1, lm_force=[bits], rho_force=[rho_next])
+        tie = max(tie, float(np.max(np.where(same, ost.lm_ties, 0.0))))
+    return ost, st, log, tie
+
+
+@pytest.mark.parametrize("n_iters,case", [
+    (3, "fan512"),
+    (50, "fan256"),
+    pytest.param(50, "fan384", marks=[pytest.mark.slow, pytest.mark.timeout(600)]),
+    pytest.param(50, "fan512", marks=[pytest.mark.slow, pytest.mark.timeout(900)]),
+])
+def test_admm_fp32_matches_oracle_after_fixed_iterations(dect, n_iters, case):
+    """FP32 fan-beam slices against the FP64 oracle after the configured 50 iterations (and
+    3 at 512^2), x_c within 1e-3 and x_p within 5e-3.  The per-ray LM accept test and the
+    residual-balancing test are discrete decisions taken in each side's precision; the
+    oracle replays the library's, on the same single-precision inputs, and every one it
+    would have taken the other way from the same starting point must be a near-tie at
+    single precision.  The 384^2 class has 135 base views, an odd count, so the
+    projector's last group of base views is partial."""
+    pr = FP32_CASES[case]()
+    print(f"\n[fp32 parity] {case} {pr.geom['nx']}^2 {pr.geom['n_views']}x{pr.geom['n_det']} "
+          f"{n_iters} iterations in lockstep", flush=True)
+    ost, st, log, tie = _fp32_lockstep(dect, pr, n_iters)
     x = host(st.x)
-    assert rel(x[..., 0], ost.x[0]) <= 1e-3
-    assert rel(x[..., 1], ost.x[1]) <= 5e-3
-    # The GPU's own adaptive decisions mostly agree with the oracle's.
-    _, st2, log2 = _admm_gpu(dect, pr, F32, dect.AdmmParams(), n_iters)
-    agree = np.mean([tuple(e["rho"]) == tuple(o["rho"]) for e, o in zip(log2, ost.log)])
-    assert agree >= 0.9
+    a = host(st.a)
+    flips = sum(e.get("lm_flips", 0) for e in ost.log)
+    rtie = max(e.get("rho_tie", 0.0) for e in ost.log)
+    split = float(np.mean(np.any(np.abs(a - np.moveaxis(ost.a, 0, -1))
+                                 > 1e-2 * (1.0 + np.abs(a)), axis=-1)))
+    ec, ep = rel(x[..., 0], ost.x[0]), rel(x[..., 1], ost.x[1])
+    print(f"[fp32 parity] {case}: x_c {ec:.3e} x_p {ep:.3e}; replayed LM decisions the oracle "
+          f"would have taken the other way: {flips}, largest near-tie ratio from a shared "
+          f"start {tie:.3g}; rays ending apart {split:.2e}; rho tie {rtie:.3g}", flush=True)
+    assert ec <= 1e-3
+    assert ep <= 5e-3
+    assert tie <= LM_TIE_MAX
+    assert rtie <= RHO_TIE_MAX
+    assert split <= SPLIT_MAX
+    # The logged objective follows the oracle's: single-precision a and y change the
+    # data fit and the TV term by far less than the x tolerance.
+    _check_objective_log(log, ost.log, rtol_data=1e-3, rtol_tv=1e-3)
+    assert [tuple(e["rho"]) for e in log] == [tuple(e["rho"]) for e in ost.log]
 
 
 def test_checkpoint_resume_and_determinism(dect):

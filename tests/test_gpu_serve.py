@@ -164,3 +164,28 @@ def test_server_errors(dect, plans):
         R = dect.Result()
         dect._check(lib.dect_serve_poll(srv.handle, t, R))
     srv.close()
+
+
+def test_bounded_queue_sheds_load(dect, plans):
+    """With max_queue the server refuses submits beyond the queue bound
+    (DECT_E_CAPACITY) instead of queueing them; accepted requests are served normally."""
+    plan = plans[("sym_fan64", F32)]
+    pr = _problem("sym_fan64", 14)
+    srv = dect.Server(max_slots=1, step_iters=5, max_queue=2)
+    accepted, refused = [], 0
+    for _ in range(12):
+        try:
+            accepted.append(srv.submit(plan, pr.counts_high, pr.counts_low, pr.i0, tol=0.0,
+                                       max_iters=20))
+        except dect.DectError as e:
+            assert e.status == -6 and "queue" in str(e)
+            refused += 1
+    out = [srv.wait(t, 60000) for t in accepted]
+    st = srv.stats()
+    srv.close()
+    # One slot and two queue places: the back-to-back submits cannot all be taken.
+    assert refused >= 1 and len(accepted) >= 2
+    assert st["rejected"] == refused and st["submitted"] == len(accepted)
+    assert all(r["status"] == 0 and r["iters"] == 20 for _, r in out)
+    for x, _ in out[1:]:
+        np.testing.assert_array_equal(x, out[0][0])

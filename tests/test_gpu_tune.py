@@ -61,12 +61,14 @@ def oracle_run():
 
 
 @pytest.mark.parametrize("name", ["sym", "ragged"])
-@pytest.mark.parametrize("bp,pj", [(2, 2), (4, 4), (8, 8), (2, 8), (8, 2)])
-def test_every_shape_matches_oracle_fp64(dect, oracle_run, name, bp, pj):
+@pytest.mark.parametrize("bp,pj,views,chunk", [(2, 2, 2, 1), (4, 4, 1, 2), (8, 8, 4, 4),
+                                               (2, 8, 1, 1), (8, 2, 4, 2), (4, 8, 8, 16)])
+def test_every_shape_matches_oracle_fp64(dect, oracle_run, name, bp, pj, views, chunk):
     pr, ost = oracle_run[name]
     plan = dect.Plan(pr.geom, pr.spec, F64)
-    plan.set_launch(bp, pj)
-    assert plan.launch() == {"bp_waves": bp, "proj_waves": pj}
+    plan.set_launch(bp, pj, views, chunk)
+    assert plan.launch() == {"bp_waves": bp, "proj_waves": pj, "proj_views": views,
+                             "proj_chunk": chunk}
     meas = _meas(pr, F64)
     params = dect.AdmmParams(cg_iters=2, lm_iters=2)
     st = plan.new_state()
@@ -83,8 +85,8 @@ def test_batch_with_tuned_shapes_equals_alone(dect):
     params = dect.AdmmParams()
     a = dect.Plan(SYM_FAN, S.default_spectra(), F32)
     b = dect.Plan(SYM_FAN, S.default_spectra(), F32)
-    a.set_launch(8, 2)
-    b.set_launch(2, 8)
+    a.set_launch(8, 2, 4, 2)
+    b.set_launch(2, 8, 2, 1)
     slices = []
     for plan, seed in ((a, 1), (b, 2), (a, 3)):
         pr = _problem(SYM_FAN, seed)
@@ -110,13 +112,21 @@ def test_tune_times_caches_and_reuses(dect, tmp_path):
     t1 = p1.tune(cache)
     assert t1["from_cache"] == 0
     assert t1["bp_waves"] in (2, 4, 8) and t1["proj_waves"] in (2, 4, 8)
+    assert t1["proj_views"] in (1, 2, 4) and t1["proj_chunk"] in (1, 2, 4)
     assert t1["bp_us"] > 0 and t1["proj_us"] > 0
-    assert p1.launch() == {"bp_waves": t1["bp_waves"], "proj_waves": t1["proj_waves"]}
+    # A choice other than the default must beat it by at least 1 %.
+    assert t1["bp_us"] <= t1["bp_us_default"] and t1["proj_us"] <= t1["proj_us_default"]
+    if t1["bp_waves"] != 4:
+        assert t1["bp_us"] < 0.99 * t1["bp_us_default"]
+    if (t1["proj_waves"], t1["proj_views"], t1["proj_chunk"]) != (8, 2, 1):
+        assert t1["proj_us"] < 0.99 * t1["proj_us_default"]
+    assert p1.launch() == {k: t1[k] for k in ("bp_waves", "proj_waves", "proj_views",
+                                              "proj_chunk")}
     assert os.path.exists(cache)
     p2 = dect.Plan(SYM_FAN, S.default_spectra(), F32)
     t2 = p2.tune(cache)
     assert t2["from_cache"] == 1
-    assert (t2["bp_waves"], t2["proj_waves"]) == (t1["bp_waves"], t1["proj_waves"])
+    assert all(t2[k] == t1[k] for k in ("bp_waves", "proj_waves", "proj_views", "proj_chunk"))
     t3 = p2.tune(cache, force=True)
     assert t3["from_cache"] == 0
     # Another shape or precision has its own entry.
@@ -128,7 +138,8 @@ def test_tune_times_caches_and_reuses(dect, tmp_path):
 
 def test_launch_shape_errors(dect):
     p = dect.Plan(SYM_FAN, S.default_spectra(), F32)
-    for bad in ((3, 4), (4, 16), (0, 4)):
+    for bad in ((3, 4), (4, 16), (0, 4), (4, 4, 3, 1), (4, 4, 16, 1), (4, 4, 2, 0),
+                (4, 4, 2, 17)):
         with pytest.raises(dect.DectError):
             p.set_launch(*bad)
-    assert p.launch() == {"bp_waves": 4, "proj_waves": 4}
+    assert p.launch() == {"bp_waves": 4, "proj_waves": 8, "proj_views": 2, "proj_chunk": 1}

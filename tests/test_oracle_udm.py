@@ -146,3 +146,36 @@ def test_udm_counts_forward_evaluations():
         orc.udm(np.ones(3), np.ones(3), np.ones(3), np.ones(3), np.ones(3), np.ones(3), 0.1,
                 0.1, m, np.zeros(3), np.zeros(3))
         assert orc.counts["f"] - before == 2 * (m + 1)
+
+
+def test_udm_replayed_decisions():
+    """Replaying accept decisions: the oracle's own decisions reproduce its unforced run
+    bit for bit with no disagreement recorded; the opposite decisions are followed, and
+    each one is reported far from a single-precision near-tie."""
+    orc = _orc()
+    rng = np.random.default_rng(11)
+    n = 400
+    ac_t, ap_t = rng.uniform(0, 12, n), rng.uniform(0, 10, n)
+    fh, fl, _, _ = orc.forward(ac_t, ap_t)
+    mh, ml = fh + rng.normal(0, 0.02, n), fl + rng.normal(0, 0.02, n)
+    wh, wl = rng.uniform(0.05, 1, n), rng.uniform(0.05, 1, n)
+    vc, vp = ac_t + rng.normal(0, 0.3, n), ap_t + rng.normal(0, 0.3, n)
+    a0c, a0p = ac_t + rng.normal(0, 1.0, n), ap_t + rng.normal(0, 1.0, n)
+    args = (mh, ml, wh, wl, vc, vp, 1e-3, 2e-3, 1)
+    # One LM iteration: it accepted exactly where a moved.
+    c1, p1, phi1 = orc.udm(*args, a0c, a0p)
+    own = ((c1 != a0c) | (p1 != a0p)).astype(np.uint8)
+    assert 0 < own.sum() < n
+    ties = []
+    c2, p2, phi2 = orc.udm(*args, a0c, a0p, force=own, ties=ties)
+    np.testing.assert_array_equal(c2, c1)
+    np.testing.assert_array_equal(p2, p1)
+    assert not ties[0].any()
+    # The opposite decisions: accepted steps are undone, rejected ones taken.
+    ties = []
+    c3, p3, _ = orc.udm(*args, a0c, a0p, force=1 - own, ties=ties)
+    np.testing.assert_array_equal(c3[own == 1], a0c[own == 1])
+    assert np.all((c3 != a0c)[own == 0])
+    assert np.all(ties[0] > 0)
+    # A real disagreement is thousands of rounding scales away from a tie.
+    assert np.median(ties[0]) > 1e3
