@@ -104,6 +104,24 @@ const char* dect_last_error(void);
 dect_status dect_project(const dect_plan* plan, const void* img, void* sino, int ch,
                          void* stream);
 
+/* dect_project for callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same arguments,
+ * kernels and results as dect_project (bit for bit), but the two orbit images the
+ * projector reads live in a static device array of 32 MiB that the library holds
+ * on each device it runs on until the process ends, not in the plan's scratch; the
+ * call allocates nothing.  Its size limits the plan: 2 * nx * ny * ch * s * bytes
+ * per value (+ up to 255 bytes of alignment), with s = 4 on a quarter-turn
+ * symmetric plan and 1 otherwise, must not exceed 32 MiB (e.g. 512x512 with two
+ * channels in FP64 or four in FP32 on a symmetric plan); larger calls return
+ * DECT_E_CAPACITY before anything is enqueued.  Every call on one device shares
+ * that device's array: calls that overlap on one GPU (on different streams, or
+ * from different threads) race and must not be issued; calls in order on one
+ * stream are safe (each call writes the array in full before reading it).  The
+ * first call on a device looks up the array's device address, with that device
+ * current.  img: device [ny][nx][ch]; sino: device [n_views][n_det][ch]. async. */
+dect_status dect_project_noalloc(const dect_plan* plan, const void* img, void* sino, int ch,
+                                 void* stream);
+
 /* R^T, the transpose of dect_project up to rounding, gathered per pixel with no
  * atomics: img[j][i][c] = sum over rays of weight * sino[v][b][c], each weight the
  * projector's linear-interpolation weight of the pixel re-evaluated from the same

@@ -24,6 +24,8 @@
 // signed-distance ray records), so the pair is a transpose up to rounding (FP64
 // adjointness to 1e-12), not bit for bit.  The views are split over the waves of a workgroup and
 // the wave sums are added in a fixed order through LDS.
+#include <mutex>
+
 #include "common.h"
 #include "epilogue.h"
 #include "kernels.h"
@@ -963,3 +965,74 @@ DECT_INST(double)
 #undef DECT_INST
 
 }  // namespace dect
+
+// ------------------------------------------------------------------------------
+// R without any allocation: the orbit images live in a static device array.
+//
+// `scratch` is a file-scope device array of kNoAllocScratchBytes.  Each device the
+// library runs on holds its own copy until the process ends.  In host code its
+// name is only a stand-in for the device symbol, so the device address of each
+// device's copy is looked up once (hipGetSymbolAddress, with that device current)
+// and kept; kernels receive that address, never the name.
+namespace dect {
+namespace {
+
+constexpr size_t kNoAllocScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `device`'s copy of scratch (looked up on first use).
+dect_status scratch_address(int device, void** out) {
+    if (device < 0 || device >= kMaxDevices)
+        return fail(DECT_E_DEVICE, "device %d is beyond the %d the library tracks", device,
+                    kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        int cur = -1;
+        DECT_HIP(hipGetDevice(&cur));
+        if (cur != device) DECT_HIP(hipSetDevice(device));
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (cur != device) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !ptr)
+            return fail(DECT_E_DEVICE, "no address for the static scratch on device %d: %s",
+                        device, hipGetErrorString(e));
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return DECT_OK;
+}
+
+}  // namespace
+}  // namespace dect
+
+extern "C" dect_status dect_project_noalloc(const dect_plan* p, const void* img, void* sino,
+                                            int ch, void* stream) {
+    using namespace dect;
+    if (!p || !img || !sino) return fail(DECT_E_ARG, "null argument");
+    if (ch != 1 && ch != 2 && ch != 4) return fail(DECT_E_ARG, "ch must be 1, 2 or 4 (got %d)", ch);
+    // The orbit image and its transpose, the second at the next 256-byte boundary.
+    const size_t image = (size_t)p->N * (size_t)ch * (size_t)p->sym * p->elem;
+    const size_t second = (image + 255) / 256 * 256;
+    if (second + image > kNoAllocScratchBytes)
+        return fail(DECT_E_CAPACITY,
+                    "the two orbit images need %zu bytes; the static scratch holds %zu "
+                    "(%dx%d, %d channels, symmetry %d, %zu-byte values)",
+                    second + image, kNoAllocScratchBytes, p->nx, p->ny, ch, p->sym, p->elem);
+    void* base = nullptr;
+    const dect_status st = scratch_address(p->device, &base);
+    if (st != DECT_OK) return st;
+    // Both orbit images are written in full before the projector reads them, so the
+    // previous call's contents need no clearing.
+    void* O = base;
+    void* OT = static_cast<char*>(base) + second;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const hipError_t e = p->dtype == DECT_F32
+                             ? launch_project_with<float>(p, img, sino, ch, O, OT, s)
+                             : launch_project_with<double>(p, img, sino, ch, O, OT, s);
+    if (e != hipSuccess) return fail(DECT_E_DEVICE, "launch failed: %s", hipGetErrorString(e));
+    return DECT_OK;
+}

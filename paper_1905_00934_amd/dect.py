@@ -129,6 +129,7 @@ def lib():
                                  ctypes.POINTER(vp)],
             "dect_plan_destroy": [vp],
             "dect_project": [vp, vp, vp, i, vp],
+            "dect_project_noalloc": [vp, vp, vp, i, vp],
             "dect_backproject": [vp, vp, vp, i, vp],
             "dect_decompose_rays": [vp, vp, vp, vp, vp, vp, d, d, i, vp, vp, vp],
             "dect_ingest_counts": [vp, vp, vp, d, d, vp, vp, vp, vp, vp],
