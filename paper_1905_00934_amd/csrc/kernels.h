@@ -23,19 +23,41 @@ enum Epilogue : int { EPI_NONE = 0, EPI_RHS = 1, EPI_Q = 2, EPI_DUAL = 3 };
 // unit into SGPRs, as a by-value argument does.  The single-slice kernels are
 // separate instantiations that never touch the array.
 template <bool BATCH, typename A>
-__device__ inline A pick_args(const A* __restrict__ dev, const A& one) {
+__device__ inline A pick_args(const A* __restrict__ dev, const A& one, unsigned slice) {
     static_assert(sizeof(A) % 4 == 0 && alignof(A) >= 4, "argument blocks are whole words");
     if constexpr (!BATCH) {
         return one;
     } else {
         using CW = const __attribute__((address_space(4))) uint32_t;
-        CW* src = (CW*)(dev + blockIdx.z);
+        CW* src = (CW*)(dev + slice);
         A out;
         uint32_t* dst = reinterpret_cast<uint32_t*>(&out);
 #pragma unroll
         for (unsigned k = 0; k < sizeof(A) / 4; ++k) dst[k] = src[k];
         return out;
     }
+}
+
+template <bool BATCH, typename A>
+__device__ inline A pick_args(const A* __restrict__ dev, const A& one) {
+    return pick_args<BATCH>(dev, one, blockIdx.z);
+}
+
+// Workgroups of a batched launch of n slices of T workgroups each, placed so that all
+// workgroups of a slice run on one XCD: the dispatcher deals consecutive workgroup ids
+// to the kXcds XCDs in turn, so id = XCD + kXcds k, and XCD x takes slices x, x + kXcds,
+// ... one after the other (k = T j + tile).  A slice's data then passes through one
+// XCD's L2 instead of being fetched by all of them.  Returns false for the padding
+// workgroups of XCDs with fewer slices.
+__device__ inline bool xcd_slice_tile(unsigned id, unsigned T, unsigned n, unsigned& slice,
+                                      unsigned& tile) {
+    const unsigned x = id % kXcds, k = id / kXcds;
+    slice = x + kXcds * (k / T);
+    tile = k % T;
+    return slice < n;
+}
+__host__ __device__ inline unsigned xcd_slice_blocks(unsigned T, unsigned n) {
+    return kXcds * ((n + kXcds - 1) / kXcds) * T;
 }
 
 template <typename T>

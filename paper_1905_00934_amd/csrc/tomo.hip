@@ -334,7 +334,7 @@ __device__ inline void rotf(int k, int n, T i, T j, T& io, T& jo) {
 // outside the window (a steep footprint near the source) is loaded directly.
 template <typename T, int CH, int SYM, int VS>
 __device__ inline void gather_orbit_staged(const BpArgs<T>& a, int wave, int lane, int i, int j,
-                                           bool inside, T (&acc)[SYM][CH]) {
+                                           int bx, int by, bool inside, T (&acc)[SYM][CH]) {
     constexpr int WIN = 16;
     using Q = vec<T, SYM * CH>;
     __shared__ RayParam<T> s_ray[VS][WIN * SYM];
@@ -348,7 +348,7 @@ __device__ inline void gather_orbit_staged(const BpArgs<T>& a, int wave, int lan
     const int sm = lane / WIN, sk = lane % WIN;
     const bool stager = lane < WIN * SYM;
     T icm, jcm;
-    rotf<T>(sm, n, (T)(blockIdx.x * 8) + T(3.5), (T)(blockIdx.y * 8) + T(3.5), icm, jcm);
+    rotf<T>(sm, n, (T)(bx * 8) + T(3.5), (T)(by * 8) + T(3.5), icm, jcm);
     const T ipc = icm - cx, jpc = jcm - cy;
     RayParam<T> pr{};
     Q pq;
@@ -455,7 +455,7 @@ constexpr int kWideStride = kWideWin + kBpFixed;
 // [VS][SYM members][kWideStride]; each wave uses only its own row.
 template <typename T, int CH, int SYM, int VS>
 __device__ inline void gather_orbit_staged_wide(const BpArgs<T>& a, int wave, int lane, int i, int j,
-                                                bool inside, T (&acc)[SYM][CH],
+                                                int bx, int by, bool inside, T (&acc)[SYM][CH],
                                                 Staged<T, CH, SYM> (*s_win)[kWideStride * SYM]) {
     constexpr int WIN = kWideWin;
     constexpr int REC = WIN * SYM;
@@ -487,7 +487,7 @@ __device__ inline void gather_orbit_staged_wide(const BpArgs<T>& a, int wave, in
         stager[q] = rec < REC;
         sk[q] = rec % WIN;
         T icm, jcm;
-        rotf<T>(rec / WIN, n, (T)(blockIdx.x * 8) + T(3.5), (T)(blockIdx.y * 8) + T(3.5), icm, jcm);
+        rotf<T>(rec / WIN, n, (T)(bx * 8) + T(3.5), (T)(by * 8) + T(3.5), icm, jcm);
         ipc[q] = icm - cx;
         jpc[q] = jcm - cy;
     }
@@ -596,7 +596,7 @@ __device__ inline void gather_orbit_staged_wide(const BpArgs<T>& a, int wave, in
 // disjoint subset of the base views; wave 0 adds the others' sums in order.
 template <typename T, int CH, int SYM, bool QUAD, int EPI, int VS, bool BATCH>
 __global__ __launch_bounds__(64 * VS) void k_backproject(const BpArgs<T>* __restrict__ dev,
-                                                         BpArgs<T> one) {
+                                                         BpArgs<T> one, unsigned nslices) {
     // The ADMM epilogues (q, dual) run one orbit member per wave; the plain transpose
     // keeps the reduction into wave 0.
     constexpr bool kFinish = EPI == EPI_Q || EPI == EPI_DUAL;
@@ -613,12 +613,27 @@ __global__ __launch_bounds__(64 * VS) void k_backproject(const BpArgs<T>* __rest
         if constexpr (kFinish && kWide) return reinterpret_cast<T(*)[SYM * CH]>(&s_win[w][0]);
         else return red_own[w];
     };
-    const BpArgs<T> a = pick_args<BATCH>(dev, one);
-    if ((int)blockIdx.x >= a.gx || (int)blockIdx.y >= a.gy) return;  // beyond this slice
+    // The orbit block (bx, by) of this workgroup: its 2-D grid position for one slice;
+    // in a batch, a 1-D grid with every slice's blocks on one XCD (one.gx, one.gy: the
+    // group's block grid, the same for all its slices).
+    int bx, by;
+    unsigned slice = 0;
+    if constexpr (BATCH) {
+        unsigned tile;
+        if (!xcd_slice_tile(blockIdx.x, (unsigned)(one.gx * one.gy), nslices, slice, tile))
+            return;
+        bx = (int)(tile % (unsigned)one.gx);
+        by = (int)(tile / (unsigned)one.gx);
+    } else {
+        bx = (int)blockIdx.x;
+        by = (int)blockIdx.y;
+    }
+    const BpArgs<T> a = pick_args<BATCH>(dev, one, slice);
+    if (bx >= a.gx || by >= a.gy) return;  // beyond this slice
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int i = blockIdx.x * 8 + (lane & 7);
-    const int j = blockIdx.y * 8 + (lane >> 3);
+    const int i = bx * 8 + (lane & 7);
+    const int j = by * 8 + (lane >> 3);
     const int dom_x = SYM == 4 ? a.nx / 2 : a.nx, dom_y = SYM == 4 ? a.ny / 2 : a.ny;
     const bool inside = i < dom_x && j < dom_y;
     T acc[SYM][CH];
@@ -627,9 +642,9 @@ __global__ __launch_bounds__(64 * VS) void k_backproject(const BpArgs<T>* __rest
 #pragma unroll
         for (int c = 0; c < CH; ++c) acc[k][c] = T(0);
     if constexpr (kWide)
-        gather_orbit_staged_wide<T, CH, SYM, VS>(a, wave, lane, i, j, inside, acc, s_win);
+        gather_orbit_staged_wide<T, CH, SYM, VS>(a, wave, lane, i, j, bx, by, inside, acc, s_win);
     else if constexpr (QUAD)
-        gather_orbit_staged<T, CH, SYM, VS>(a, wave, lane, i, j, inside, acc);
+        gather_orbit_staged<T, CH, SYM, VS>(a, wave, lane, i, j, bx, by, inside, acc);
     else if (inside)
         gather_orbit<T, CH, SYM, VS>(a, wave, i, j, acc);
     if constexpr (kFinish) {
@@ -672,7 +687,7 @@ __global__ __launch_bounds__(64 * VS) void k_backproject(const BpArgs<T>* __rest
                 o0 += wpart[k][0];
                 o1 += wpart[k][1];
             }
-            double* o = a.partials + (size_t)(blockIdx.y * a.gx + blockIdx.x) * kPartialSlots;
+            double* o = a.partials + (size_t)(by * a.gx + bx) * kPartialSlots;
             o[0] = o0;
             o[1] = o1;
         }
@@ -715,7 +730,7 @@ __global__ __launch_bounds__(64 * VS) void k_backproject(const BpArgs<T>* __rest
             for (int c = 0; c < 2; ++c)
                 for (int off = 32; off > 0; off >>= 1) part[c] += __shfl_down(part[c], off, 64);
             if (lane == 0) {
-                double* o = a.partials + (size_t)(blockIdx.y * a.gx + blockIdx.x) * kPartialSlots;
+                double* o = a.partials + (size_t)(by * a.gx + bx) * kPartialSlots;
                 o[0] = part[0];
                 o[1] = part[1];
             }
@@ -786,7 +801,7 @@ hipError_t bp_quad_plain(const BpArgs<T>& one, T* quad, hipStream_t s) {
     BpArgs<T> a = one;
     a.sino = quad;
     hipLaunchKernelGGL((k_backproject<T, CH, 4, true, EPI_NONE, VS, false>), dim3(a.gx, a.gy),
-                       dim3(64 * VS), 0, s, nullptr, a);
+                       dim3(64 * VS), 0, s, nullptr, a, 1u);
     return hipGetLastError();
 }
 
@@ -803,7 +818,7 @@ hipError_t bp_quad_plain_w(int waves, const BpArgs<T>& one, T* quad, hipStream_t
 template <typename T, int CH, int SYM>
 hipError_t bp_plain(const BpArgs<T>& one, hipStream_t s) {
     hipLaunchKernelGGL((k_backproject<T, CH, SYM, false, EPI_NONE, kViewSplit, false>),
-                       dim3(one.gx, one.gy), dim3(64 * kViewSplit), 0, s, nullptr, one);
+                       dim3(one.gx, one.gy), dim3(64 * kViewSplit), 0, s, nullptr, one, 1u);
     return hipGetLastError();
 }
 
@@ -811,14 +826,20 @@ hipError_t bp_plain(const BpArgs<T>& one, hipStream_t s) {
 template <typename T, int SYM, bool BATCH, int VS>
 hipError_t bp_admm_t(int epi, const BpArgs<T>* dev, const BpArgs<T>& one, int n, int gx, int gy,
                      hipStream_t s) {
-    const dim3 g(gx, gy, n);
+    // One slice: a (gx, gy) grid.  A batch: every slice's blocks on one XCD; the kernel
+    // takes the block grid from `one`, the same for every slice of the group.
+    if (gx != one.gx || gy != one.gy) return hipErrorInvalidValue;
+    const dim3 g = BATCH ? dim3(xcd_slice_blocks((unsigned)(gx * gy), (unsigned)n)) : dim3(gx, gy);
     const dim3 blk(64 * VS);
+    const unsigned nsl = (unsigned)n;
     switch (epi) {
         case EPI_Q:
-            hipLaunchKernelGGL((k_backproject<T, 2, SYM, true, EPI_Q, VS, BATCH>), g, blk, 0, s, dev, one);
+            hipLaunchKernelGGL((k_backproject<T, 2, SYM, true, EPI_Q, VS, BATCH>), g, blk, 0, s, dev,
+                               one, nsl);
             break;
         case EPI_DUAL:
-            hipLaunchKernelGGL((k_backproject<T, 2, SYM, true, EPI_DUAL, VS, BATCH>), g, blk, 0, s, dev, one);
+            hipLaunchKernelGGL((k_backproject<T, 2, SYM, true, EPI_DUAL, VS, BATCH>), g, blk, 0, s,
+                               dev, one, nsl);
             break;
         default:
             return hipErrorInvalidValue;
