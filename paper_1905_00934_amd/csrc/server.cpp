@@ -142,6 +142,9 @@ struct dect_server {
         pending.erase(s.r->ticket);
         done[s.r->ticket] = res;
         stats.completed++;
+        // Counted out of flight in the same step that publishes the result, so a
+        // caller that has every result sees none in flight.
+        if (stats.in_flight > 0) stats.in_flight--;
         cv_done.notify_all();
     }
 
