@@ -102,9 +102,50 @@ DECT_HD inline void proj_tile(unsigned id, int gy, int chunk, int& bg, int& vg) 
     vg = within % gy;
 }
 
+// Sample k of a ray (phi0, slope) on a line of n_lines >= 2 pixels: Joseph's linear
+// interpolation at phi = phi0 + slope k between taps floor(phi) and floor(phi) + 1,
+// with the line extended by zeros.  Returned as two taps j0, j0 + 1 that always lie
+// inside the line (0 <= j0 <= n_lines - 2) and their weights w0, w1, each the tent
+// max(0, 1 - |phi - j|): 1 - alpha and alpha for an interior sample (alpha = phi -
+// floor(phi)), alpha on tap 0 when only floor(phi) + 1 = 0 is inside, 1 - alpha on tap
+// n_lines - 1 when only floor(phi) = n_lines - 1 is, and zero for a sample with no tap
+// inside.  So the loads need no bounds test.
+template <typename T>
+DECT_HD inline int proj_taps(T phi0, T slope, T k, int n_lines, T& w0, T& w1) {
+    const T ph = fma(slope, k, phi0);
+    const T j0 = fmin(fmax(floor(ph), T(0)), T(n_lines - 2));
+    const T t = ph - j0;
+    w0 = fmax(T(0), T(1) - fabs(t));
+    w1 = fmax(T(0), T(1) - fabs(t - T(1)));
+    return (int)j0;
+}
+
+// Staged image lines of the projector.  A wave whose rays all step along the same
+// axis reads, at sample k, line k of one orbit image; its 64 lanes stage the
+// kProjWin taps s(k) .. s(k) + kProjWin - 1 of that line into LDS (one each) and
+// read their two taps from there.  s(k) centres the window on the mean trajectory
+// of lanes 0 and 63 (the first bin of the first view and the last bin of the last:
+// the extreme rays of the wave), so that a wave's rays fall inside as long as they
+// spread over fewer than about kProjWin - 2 pixels of the line; a lane whose taps
+// are outside loads them directly.
+constexpr int kProjWin = 64;
+template <typename T>
+DECT_HD inline int proj_window(T ac, T bc, int k) {
+    return (int)floor(fma(bc, (T)k, ac)) - (kProjWin / 2 - 1);
+}
+// The centre trajectory ac + bc k from the (phi0, slope) of lanes 0 and 63.
+template <typename T>
+DECT_HD inline void proj_window_line(T phi0_first, T slope_first, T phi0_last, T slope_last,
+                                     T& ac, T& bc) {
+    ac = T(0.5) * (phi0_first + phi0_last);
+    bc = T(0.5) * (slope_first + slope_last);
+}
+
 // The samples k0..k1 of a ray (phi0, slope) with n_steps samples over n_lines image
-// lines that can have a tap inside the image (outside [k0, k1] both taps of every
-// sample are outside; the one-step margin absorbs rounding); k1 < k0 if none.
+// lines that have a tap inside the image: outside [k0, k1] both taps of every sample
+// are outside (the range is first taken with a one-step margin, which absorbs
+// rounding, then trimmed at both ends to samples with a nonzero weight as proj_taps
+// evaluates them); k1 < k0 if none.
 template <typename T>
 DECT_HD inline void proj_ray_range(T phi0, T slope, int n_steps, int n_lines, int& k0, int& k1) {
     k0 = 0;
@@ -120,6 +161,13 @@ DECT_HD inline void proj_ray_range(T phi0, T slope, int n_steps, int n_lines, in
     } else if (!(phi0 >= T(-1) && phi0 < T(n_lines))) {
         k1 = -1;
     }
+    auto inside = [&](int k) {
+        T w0, w1;
+        proj_taps<T>(phi0, slope, (T)k, n_lines, w0, w1);
+        return w0 > T(0) || w1 > T(0);
+    };
+    while (k0 <= k1 && !inside(k0)) ++k0;
+    while (k1 >= k0 && !inside(k1)) --k1;
 }
 
 // Wave `wave` of KS takes lines c0..c1 of the union s0..s1 of its workgroup's ray
@@ -129,17 +177,6 @@ DECT_HD inline void proj_wave_share(int s0, int s1, int wave, int KS, int& c0, i
     const int len = s1 - s0 + 1;
     c0 = s0 + wave * len / KS;
     c1 = s0 + (wave + 1) * len / KS - 1;
-}
-
-// Tap line j (taps j and j + 1) and weight alpha of sample k of a ray: phi = phi0 +
-// slope k, j = floor(phi) clamped to [-2, n_lines + 1] (a clamped j has no tap inside).
-template <typename T>
-DECT_HD inline int proj_tap(T phi0, T slope, int k, int n_lines, T& alpha) {
-    const T ph = fma(slope, (T)k, phi0);
-    T f = floor(ph);
-    alpha = ph - f;
-    f = fmin(fmax(f, T(-2)), T(n_lines + 1));
-    return (int)f;
 }
 
 }  // namespace dect

@@ -140,6 +140,17 @@ __global__ __launch_bounds__(256) void k_orbit_tiled(const OrbitArgs<T>* __restr
     }
 }
 
+// The value of x in lane l (uniform).
+__device__ inline float lane_value(float x, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+__device__ inline double lane_value(double x, int l) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 // R for base rays: QUAD = true writes [Vb][D][SYM][CH] records, false writes the
 // standard [V][D][CH] layout (view v + k*Vb for rotation k).  A workgroup owns
 // 64 / views consecutive bins of `views` consecutive base views (one ray per lane),
@@ -150,7 +161,16 @@ template <typename T, int CH, int SYM, bool QUAD, int KS, bool BATCH>
 __global__ __launch_bounds__(64 * KS) void k_project(const ProjArgs<T>* __restrict__ dev,
                                                      ProjArgs<T> one) {
     constexpr int W = CH * SYM;
-    __shared__ T red[KS > 1 ? KS - 1 : 1][64][W];
+    using V = vec<T, W>;
+    // Each wave's staged line window, a tap record split into NCH chunks of up to 16
+    // bytes held in separate arrays: the lanes of a wave read nearby records, and
+    // 16-byte records put records r and r + 8 (not r + 4) on the same LDS banks.
+    // After the sample loops wave w > 0 leaves its partial sums in its own window for
+    // wave 0.
+    constexpr int CE = W * (int)sizeof(T) > 16 ? 16 / (int)sizeof(T) : W;  // values per chunk
+    constexpr int NCH = W / CE;
+    using VC = vec<T, CE>;
+    __shared__ VC s_win[KS][NCH][kProjWin];
     const ProjArgs<T> A = pick_args<BATCH>(dev, one);
     const int nx = A.nx, ny = A.ny, Vb = A.Vb, D = A.D;
     const int BV = A.views, lbv = __builtin_ctz((unsigned)A.views);
@@ -189,50 +209,100 @@ __global__ __launch_bounds__(64 * KS) void k_project(const ProjArgs<T>* __restri
     }
     int c0, c1;
     proj_wave_share(s0, s1, wave, KS, c0, c1);
+    c0 = __builtin_amdgcn_readfirstlane(c0);  // the same in every lane
+    c1 = __builtin_amdgcn_readfirstlane(c1);
     k0 = k0 > c0 ? k0 : c0;
     k1 = k1 < c1 ? k1 : c1;
     if (!valid) k1 = -1;
     T acc[W];
 #pragma unroll
     for (int c = 0; c < W; ++c) acc[c] = T(0);
-    int k = k0;
-    // Two samples per trip so that four loads are in flight per lane.
-    for (; k + 1 <= k1; k += 2) {
-        T aa, ab;
-        const int ja = proj_tap<T>(r.phi0, r.slope, k, n_lines, aa);
-        const int jb = proj_tap<T>(r.phi0, r.slope, k + 1, n_lines, ab);
-        const vec<T, W>* la = src + (size_t)k * n_lines;
-        const vec<T, W>* lb = la + n_lines;
-        vec<T, W> a0, a1, b0, b1;
-        vzero(a0); vzero(a1); vzero(b0); vzero(b1);
-        if ((unsigned)ja < (unsigned)n_lines) a0 = la[ja];
-        if ((unsigned)(ja + 1) < (unsigned)n_lines) a1 = la[ja + 1];
-        if ((unsigned)jb < (unsigned)n_lines) b0 = lb[jb];
-        if ((unsigned)(jb + 1) < (unsigned)n_lines) b1 = lb[jb + 1];
+    auto add = [&](T w0, const V& a0, T w1, const V& a1) {
 #pragma unroll
-        for (int c = 0; c < W; ++c)
-            acc[c] += (a0.v[c] + aa * (a1.v[c] - a0.v[c])) + (b0.v[c] + ab * (b1.v[c] - b0.v[c]));
-    }
-    if (k <= k1) {
-        T aa;
-        const int ja = proj_tap<T>(r.phi0, r.slope, k, n_lines, aa);
-        const vec<T, W>* la = src + (size_t)k * n_lines;
-        vec<T, W> a0, a1;
-        vzero(a0); vzero(a1);
-        if ((unsigned)ja < (unsigned)n_lines) a0 = la[ja];
-        if ((unsigned)(ja + 1) < (unsigned)n_lines) a1 = la[ja + 1];
+        for (int c = 0; c < W; ++c) {
+            acc[c] = fma(w0, a0.v[c], acc[c]);
+            acc[c] = fma(w1, a1.v[c], acc[c]);
+        }
+    };
+    const unsigned long long vmask = __ballot(valid);
+    const unsigned long long xmask = __ballot(valid && xs);
+    if (vmask != 0ull && (xmask == 0ull || xmask == vmask)) {
+        // Every ray of the wave steps along the same axis: stage each line's window
+        // (proj_window) in LDS, one tap per lane, the next line's loads in flight
+        // while the current line is summed.
+        using GV = const __attribute__((address_space(1))) V;
+        GV* __restrict__ wimg = (GV*)(xmask != 0ull ? OT : O);
+        const int wl = xmask != 0ull ? ny : nx;  // this wave's interpolation axis
+        T ac, bc;
+        proj_window_line<T>(lane_value(r.phi0, 0), lane_value(r.slope, 0),
+                            lane_value(r.phi0, 63), lane_value(r.slope, 63), ac, bc);
+        auto load = [&](GV* q) {
+            V o;
 #pragma unroll
-        for (int c = 0; c < W; ++c) acc[c] += a0.v[c] + aa * (a1.v[c] - a0.v[c]);
+            for (int c = 0; c < W; ++c) o.v[c] = q->v[c];
+            return o;
+        };
+        V staged;
+        int s_next = 0;
+        if (c0 <= c1) {
+            s_next = __builtin_amdgcn_readfirstlane(proj_window<T>(ac, bc, c0));
+            staged = load(wimg + (size_t)c0 * wl + min(max(s_next + lane, 0), wl - 1));
+        }
+        for (int k = c0; k <= c1; ++k) {
+            const int s0w = s_next;
+#pragma unroll
+            for (int h = 0; h < NCH; ++h)
+#pragma unroll
+                for (int c = 0; c < CE; ++c) s_win[wave][h][lane].v[c] = staged.v[h * CE + c];
+            // LDS operations of one wave complete in order; the barrier only keeps
+            // the compiler from moving the reads above the write.
+            __builtin_amdgcn_wave_barrier();
+            if (k < c1) {
+                s_next = __builtin_amdgcn_readfirstlane(proj_window<T>(ac, bc, k + 1));
+                staged = load(wimg + (size_t)(k + 1) * wl + min(max(s_next + lane, 0), wl - 1));
+            }
+            if (k >= k0 && k <= k1) {
+                T w0, w1;
+                const int j = proj_taps<T>(r.phi0, r.slope, (T)k, wl, w0, w1);
+                const int idx = j - s0w;
+                if ((unsigned)idx <= (unsigned)(kProjWin - 2)) {
+                    V a0, a1;
+#pragma unroll
+                    for (int h = 0; h < NCH; ++h) {
+                        const VC x0 = s_win[wave][h][idx], x1 = s_win[wave][h][idx + 1];
+#pragma unroll
+                        for (int c = 0; c < CE; ++c) {
+                            a0.v[h * CE + c] = x0.v[c];
+                            a1.v[h * CE + c] = x1.v[c];
+                        }
+                    }
+                    add(w0, a0, w1, a1);
+                } else {
+                    GV* line = wimg + (size_t)k * wl;
+                    add(w0, load(line + j), w1, load(line + j + 1));
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+    } else {
+        // Rays of both orientations: each lane reads its own taps.
+        const V* __restrict__ img = xs ? OT : O;
+        for (int k = k0; k <= k1; ++k) {
+            T w0, w1;
+            const int j = proj_taps<T>(r.phi0, r.slope, (T)k, n_lines, w0, w1);
+            const V* line = img + (size_t)k * n_lines;
+            add(w0, line[j], w1, line[j + 1]);
+        }
     }
     if constexpr (KS > 1) {
         if (wave > 0)
 #pragma unroll
-            for (int c = 0; c < W; ++c) red[wave - 1][lane][c] = acc[c];
+            for (int c = 0; c < W; ++c) s_win[wave][c / CE][lane].v[c % CE] = acc[c];
         __syncthreads();
         if (wave != 0) return;
-        for (int w = 0; w < KS - 1; ++w)
+        for (int w = 1; w < KS; ++w)
 #pragma unroll
-            for (int c = 0; c < W; ++c) acc[c] += red[w][lane][c];
+            for (int c = 0; c < W; ++c) acc[c] += s_win[w][c / CE][lane].v[c % CE];
     }
     if (!valid) return;
     if constexpr (QUAD) {

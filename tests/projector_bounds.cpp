@@ -1,14 +1,19 @@
 // Host check of the ray-driven projector's index arithmetic, with the kernel's own
 // helpers (projidx.h): for every workgroup of a launch, every wave and lane, the ray
-// a lane takes, its sample range, the wave's share of the lines, and every tap it
-// would load.  Checks that every load lies inside its orbit image line (or is skipped
-// by the kernel's bounds test), that each valid ray's samples are split over the waves
-// exactly once with none lost, and that the only exit before the workgroup barrier is
-// taken by the whole workgroup.  Plain C++: built with g++ by the CPU test suite.
+// a lane takes, its sample range, the wave's share of the lines, the line windows a
+// wave stages and every tap a lane loads.  Checks that every load (staged or direct)
+// lies inside its orbit image, that a tap read from a window is the tap staged in that
+// slot, that the two tap weights are those of linear interpolation on the
+// zero-extended line, that the samples next to a ray's range have no tap inside the
+// image, that each valid ray's samples are split over the waves exactly once with none
+// lost, and that the only exit before the workgroup barrier is taken by the whole
+// workgroup.  Plain C++: built with g++ by the CPU test suite.
 //
 // usage: projector_bounds kind nx ny pixel V D det_cm offset src_iso src_det angle0
 //        span sym precision(32|64)
 #include <algorithm>
+#include <cmath>
+#include <limits>
 #include <cstdio>
 #include <cstdlib>
 #include <vector>
@@ -19,7 +24,7 @@ using namespace dect;
 
 template <typename T>
 static int check(const dect_geometry& g, int sym, int KS, int BV, int chunk, long& taps,
-                 long& trips) {
+                 long& trips, long& staged_lines, long& fallbacks) {
     const int Vb = g.n_views / sym, D = g.n_det, nx = g.nx, ny = g.ny;
     std::vector<T> phi0((size_t)Vb * D), slope((size_t)Vb * D);
     std::vector<char> xs((size_t)Vb * D);
@@ -60,6 +65,15 @@ static int check(const dect_geometry& g, int sym, int KS, int BV, int chunk, lon
             nl[lane] = xs[ri] ? ny : nx;
             proj_ray_range<T>(phi0[ri], slope[ri], ns[lane], nl[lane], k0[lane], k1[lane]);
             if (valid[lane]) {
+                // The samples next to the range have no tap inside the image.
+                for (int k : {k0[lane] - 2, k0[lane] - 1, k1[lane] + 1, k1[lane] + 2}) {
+                    if (k < 0 || k >= ns[lane] || (k >= k0[lane] && k <= k1[lane])) continue;
+                    T w0, w1;
+                    proj_taps<T>(phi0[ri], slope[ri], (T)k, nl[lane], w0, w1);
+                    if ((w0 != T(0) || w1 != T(0)) && errors++ < 10)
+                        std::printf("ray (%d,%d): sample %d outside [%d,%d] has weights %g %g\n",
+                                    v, b, k, k0[lane], k1[lane], (double)w0, (double)w1);
+                }
                 expected[(size_t)v * D + b] = k1[lane] >= k0[lane] ? k1[lane] - k0[lane] + 1 : 0;
                 if (k0[lane] <= k1[lane]) {
                     s0 = std::min(s0, k0[lane]);
@@ -68,33 +82,109 @@ static int check(const dect_geometry& g, int sym, int KS, int BV, int chunk, lon
             }
         }
         if (s1 < s0) s0 = 0, s1 = -1;
+        // Staged windows: a wave whose valid rays all step along the same axis.
+        bool any_valid = false, all_x = true, all_y = true;
+        int wl = 0, wn = 0;
+        for (int lane = 0; lane < 64; ++lane)
+            if (valid[lane]) {
+                const size_t ri = (size_t)v_[lane] * D + b_[lane];
+                any_valid = true;
+                all_x = all_x && xs[ri];
+                all_y = all_y && !xs[ri];
+                wl = nl[lane];
+                wn = ns[lane];
+            }
+        const bool windowed = any_valid && (all_x || all_y);
+        T ac = 0, bc = 0;
+        {
+            // Lanes 0 and 63 hold real rays even past the last bin (their ray index
+            // is clamped), as in the kernel.
+            auto ray_of = [&](int lane) {
+                return (size_t)(v_[lane] < Vb ? v_[lane] : Vb - 1) * D +
+                       (b_[lane] < D ? b_[lane] : D - 1);
+            };
+            const size_t r0 = ray_of(0), r63 = ray_of(63);
+            proj_window_line<T>(phi0[r0], slope[r0], phi0[r63], slope[r63], ac, bc);
+        }
         for (int wave = 0; wave < KS; ++wave) {
             int c0, c1;
             proj_wave_share(s0, s1, wave, KS, c0, c1);
-            for (int lane = 0; lane < 64; ++lane) {
-                if (!valid[lane]) continue;
-                const size_t ri = (size_t)v_[lane] * D + b_[lane];
-                const int a = std::max(k0[lane], c0), e = std::min(k1[lane], c1);
-                for (int k = a; k <= e; ++k) {
+            std::vector<int> slot(kProjWin);
+            for (int k = c0; k <= c1; ++k) {
+                int s = 0;
+                if (windowed) {
+                    // The staging loads of line k: tap clamp(s + lane) of that line.
+                    if (k < 0 || k >= wn) {
+                        if (errors++ < 10) std::printf("staged line %d outside [0,%d)\n", k, wn);
+                        continue;
+                    }
+                    s = proj_window<T>(ac, bc, k);
+                    for (int lane = 0; lane < 64; ++lane)
+                        slot[lane] = std::min(std::max(s + lane, 0), wl - 1);
+                    ++staged_lines;
+                }
+                for (int lane = 0; lane < 64; ++lane) {
+                    if (!valid[lane] || k < std::max(k0[lane], c0) || k > std::min(k1[lane], c1))
+                        continue;
+                    const size_t ri = (size_t)v_[lane] * D + b_[lane];
                     ++trips;
-                    if (k < 0 || k >= ns[lane]) {
+                    if (k >= ns[lane]) {
                         if (errors++ < 10)
                             std::printf("ray (%d,%d) sample %d outside [0,%d)\n", v_[lane],
                                         b_[lane], k, ns[lane]);
                         continue;
                     }
-                    T alpha;
-                    const int j = proj_tap<T>(phi0[ri], slope[ri], k, nl[lane], alpha);
-                    // The kernel loads tap j only if 0 <= j < n_lines, and j + 1 likewise.
-                    for (int t = j; t <= j + 1; ++t)
-                        if ((unsigned)t < (unsigned)nl[lane]) ++taps;
-                    if (j < -2 || j > nl[lane] + 1 || !(alpha >= T(0) && alpha <= T(1))) {
+                    T w0, w1;
+                    const int j = proj_taps<T>(phi0[ri], slope[ri], (T)k, nl[lane], w0, w1);
+                    taps += 2;
+                    if (j < 0 || j + 1 >= nl[lane]) {
                         if (errors++ < 10)
-                            std::printf("ray (%d,%d) sample %d: tap %d alpha %g\n", v_[lane],
-                                        b_[lane], k, j, (double)alpha);
+                            std::printf("ray (%d,%d) sample %d: taps %d, %d outside [0,%d)\n",
+                                        v_[lane], b_[lane], k, j, j + 1, nl[lane]);
+                        continue;
+                    }
+                    if (windowed) {
+                        const int idx = j - s;
+                        if ((unsigned)idx <= (unsigned)(kProjWin - 2)) {
+                            if (slot[idx] != j || slot[idx + 1] != j + 1) {
+                                if (errors++ < 10)
+                                    std::printf("ray (%d,%d) sample %d: window slots %d, %d "
+                                                "hold taps %d, %d, not %d, %d\n",
+                                                v_[lane], b_[lane], k, idx, idx + 1, slot[idx],
+                                                slot[idx + 1], j, j + 1);
+                            }
+                        } else {
+                            ++fallbacks;
+                        }
+                    }
+                    // The weights are those of linear interpolation on the zero-extended
+                    // line, evaluated in double from the same position: taps floor(phi)
+                    // and floor(phi) + 1 with 1 - alpha and alpha, zero outside the line,
+                    // and no weight on a tap other than j, j + 1.
+                    const double ph = (double)std::fma(slope[ri], (T)k, phi0[ri]);
+                    const double fl = std::floor(ph), al = ph - fl;
+                    auto ref = [&](long t) {
+                        if (t < 0 || t >= nl[lane]) return 0.0;
+                        return t == (long)fl ? 1.0 - al : t == (long)fl + 1 ? al : 0.0;
+                    };
+                    const double tol = 8.0 * std::numeric_limits<T>::epsilon();
+                    double lost = 0.0;
+                    for (long t = (long)fl; t <= (long)fl + 1; ++t)
+                        if (t != j && t != j + 1) lost += ref(t);
+                    if (std::fabs((double)w0 - ref(j)) > tol ||
+                        std::fabs((double)w1 - ref(j + 1)) > tol || lost > tol) {
+                        if (errors++ < 10)
+                            std::printf("ray (%d,%d) sample %d: phi %.17g taps %d,%d weights "
+                                        "%.9g %.9g, expected %.9g %.9g\n",
+                                        v_[lane], b_[lane], k, ph, j, j + 1, (double)w0,
+                                        (double)w1, ref(j), ref(j + 1));
                     }
                 }
-                if (e >= a) covered[ri] += e - a + 1;
+            }
+            for (int lane = 0; lane < 64; ++lane) {
+                if (!valid[lane]) continue;
+                const int a = std::max(k0[lane], c0), e = std::min(k1[lane], c1);
+                if (e >= a) covered[(size_t)v_[lane] * D + b_[lane]] += e - a + 1;
             }
         }
     }
@@ -135,12 +225,14 @@ int main(int argc, char** argv) {
     for (int KS : {2, 4, 8})
         for (int BV : {1, 2, 4, 8})
             for (int chunk : {1, 2, 4, 16}) {
-                long taps = 0, trips = 0;
-                const int e = prec == 64 ? check<double>(g, sym, KS, BV, chunk, taps, trips)
-                                         : check<float>(g, sym, KS, BV, chunk, taps, trips);
+                long taps = 0, trips = 0, staged = 0, fallbacks = 0;
+                const int e = prec == 64
+                                  ? check<double>(g, sym, KS, BV, chunk, taps, trips, staged, fallbacks)
+                                  : check<float>(g, sym, KS, BV, chunk, taps, trips, staged, fallbacks);
                 if (e || (BV == 2 && chunk == 1))
-                    std::printf("KS=%d views=%d chunk=%d: %ld samples, %ld taps inside, %d "
-                                "errors\n", KS, BV, chunk, trips, taps, e);
+                    std::printf("KS=%d views=%d chunk=%d: %ld samples, %ld taps loaded, %ld "
+                                "staged lines, %ld samples read outside their window, %d "
+                                "errors\n", KS, BV, chunk, trips, taps, staged, fallbacks, e);
                 bad |= e != 0;
             }
     std::printf(bad ? "FAILED\n" : "OK\n");
