@@ -192,6 +192,65 @@ __device__ inline void partial_sum(const double* __restrict__ base, int nb, doub
     __syncthreads();
 }
 
+// partial_sum of up to three arrays in one sweep (the loads of all of them in flight
+// together), each summed in exactly the order partial_sum gives it: summing thread t
+// adds the partials t, t + 256, ... of every array in increasing order (an array
+// shorter than the longest adds zeros past its end, which leaves its sum unchanged).
+// An unused array passes nb = 0 and reads as zeros.
+template <int K0, int K1, int K2>
+__device__ inline void partial_sums(const double* __restrict__ b0, int n0, double (&o0)[K0],
+                                    const double* __restrict__ b1, int n1, double (&o1)[K1],
+                                    const double* __restrict__ b2, int n2, double (&o2)[K2]) {
+    constexpr int K = K0 + K1 + K2;
+    __shared__ double sh[4][K];
+    __shared__ double res[K];
+    constexpr int NT = 256, U = 8;
+    const int nmax = max(n0, max(n1, n2));
+    for (int t = threadIdx.x; t < NT; t += blockDim.x) {  // uniform over each wave
+        double v[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = 0.0;
+        for (int b = t; b < nmax; b += U * NT) {
+            double w[U][K];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const size_t e = (size_t)(b + u * NT);
+#pragma unroll
+                for (int k = 0; k < K0; ++k)
+                    w[u][k] = b + u * NT < n0 ? b0[e * kPartialSlots + k] : 0.0;
+#pragma unroll
+                for (int k = 0; k < K1; ++k)
+                    w[u][K0 + k] = b + u * NT < n1 ? b1[e * kPartialSlots + k] : 0.0;
+#pragma unroll
+                for (int k = 0; k < K2; ++k)
+                    w[u][K0 + K1 + k] = b + u * NT < n2 ? b2[e * kPartialSlots + k] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int k = 0; k < K; ++k) v[k] += w[u][k];
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_down(v[k], off, 64);
+        if ((t & 63) == 0)
+#pragma unroll
+            for (int k = 0; k < K; ++k) sh[t >> 6][k] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < K; ++k) res[k] = (sh[0][k] + sh[1][k]) + (sh[2][k] + sh[3][k]);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K0; ++k) o0[k] = res[k];
+#pragma unroll
+    for (int k = 0; k < K1; ++k) o1[k] = res[K0 + k];
+#pragma unroll
+    for (int k = 0; k < K2; ++k) o2[k] = res[K0 + K1 + k];
+    __syncthreads();
+}
+
 template <typename T>
 hipError_t launch_project(const dect_plan* p, const void* img, void* sino, int ch, hipStream_t s);
 // Two-channel projection of the ADMM direction into quad-interleaved records, for

@@ -16,12 +16,9 @@ namespace dect {
 __device__ inline void reduce_alpha(const RedArgs& A) {
     double* s = A.scal;
     if (!s) return;  // empty slot
-    double g[2], pq[2];
-    if (A.precond)
-        partial_sum<2>(A.pre, A.nb_pre, g);
-    else
-        partial_sum<2>(A.img, A.nb_img, g);
-    partial_sum<2>(A.tiles, A.nb_tiles, pq);
+    double g[2], pq[2], none[1];
+    partial_sums<2, 2, 1>(A.precond ? A.pre : A.img, A.precond ? A.nb_pre : A.nb_img, g,
+                          A.tiles, A.nb_tiles, pq, nullptr, 0, none);
     if (threadIdx.x == 0)
         for (int c = 0; c < 2; ++c) {
             s[S_GAMMA + c] = g[c];
@@ -54,10 +51,9 @@ __device__ inline void reduce_beta(const RedArgs& A) {
 __device__ inline void reduce_final(const RedArgs& A) {
     double* s = A.scal;
     if (!s) return;
-    double sn[4], im[4], du[2] = {0.0, 0.0};
-    partial_sum<4>(A.sino, A.nb_sino, sn);
-    partial_sum<4>(A.img, A.nb_img, im);
-    if (A.dual) partial_sum<2>(A.tiles, A.nb_tiles, du);
+    double sn[4], im[4], du[2];
+    partial_sums<4, 4, 2>(A.sino, A.nb_sino, sn, A.img, A.nb_img, im, A.tiles,
+                          A.dual ? A.nb_tiles : 0, du);
     if (threadIdx.x != 0) return;
     const double rho[2] = {s[S_RHO], s[S_RHO + 1]};
     double r[2], sd[2], nr[2];
