@@ -110,13 +110,22 @@ DECT_HD inline void proj_tile(unsigned id, int gy, int chunk, int& bg, int& vg) 
 // floor(phi)), alpha on tap 0 when only floor(phi) + 1 = 0 is inside, 1 - alpha on tap
 // n_lines - 1 when only floor(phi) = n_lines - 1 is, and zero for a sample with no tap
 // inside.  So the loads need no bounds test.
+// The median of three values (no NaN): the hardware's three-operand median on the
+// device in single precision, the same selection elsewhere.
+template <typename T>
+DECT_HD inline T med3(T a, T b, T c) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    if constexpr (sizeof(T) == 4) return __builtin_amdgcn_fmed3f(a, b, c);
+#endif
+    return fmax(fmin(a, b), fmin(fmax(a, b), c));
+}
 template <typename T>
 DECT_HD inline int proj_taps(T phi0, T slope, T k, int n_lines, T& w0, T& w1) {
     const T ph = fma(slope, k, phi0);
-    const T j0 = fmin(fmax(floor(ph), T(0)), T(n_lines - 2));
+    const T j0 = med3<T>(floor(ph), T(0), T(n_lines - 2));
     const T t = ph - j0;
-    w0 = fmax(T(0), T(1) - fabs(t));
-    w1 = fmax(T(0), T(1) - fabs(t - T(1)));
+    w0 = fmax(T(0), T(1) - fabs(t));  // the tent at j0
+    w1 = med3<T>(t, T(2) - t, T(0));  // the tent at j0 + 1: max(0, min(t, 2 - t))
     return (int)j0;
 }
 
@@ -127,18 +136,25 @@ DECT_HD inline int proj_taps(T phi0, T slope, T k, int n_lines, T& w0, T& w1) {
 // of lanes 0 and 63 (the first bin of the first view and the last bin of the last:
 // the extreme rays of the wave), so that a wave's rays fall inside as long as they
 // spread over fewer than about kProjWin - 2 pixels of the line; a lane whose taps
-// are outside loads them directly.
+// are outside loads them directly.  The trajectory is held in fixed point with
+// kProjWinFrac fraction bits, so that the window start of each line is integer
+// arithmetic on the wave's scalar unit (any start is correct: it only decides which
+// taps come from LDS).
 constexpr int kProjWin = 64;
-template <typename T>
-DECT_HD inline int proj_window(T ac, T bc, int k) {
-    return (int)floor(fma(bc, (T)k, ac)) - (kProjWin / 2 - 1);
+constexpr int kProjWinFrac = 8;
+DECT_HD inline int proj_window(int A, int B, int k) {
+    return ((A + B * k) >> kProjWinFrac) - (kProjWin / 2 - 1);
 }
-// The centre trajectory ac + bc k from the (phi0, slope) of lanes 0 and 63.
+// The centre trajectory (A + B k) / 2^kProjWinFrac from the (phi0, slope) of lanes 0
+// and 63, clamped so that A + B k cannot overflow for k < 2^15.
 template <typename T>
 DECT_HD inline void proj_window_line(T phi0_first, T slope_first, T phi0_last, T slope_last,
-                                     T& ac, T& bc) {
-    ac = T(0.5) * (phi0_first + phi0_last);
-    bc = T(0.5) * (slope_first + slope_last);
+                                     int& A, int& B) {
+    const T scale = T(1 << kProjWinFrac);
+    const T ac = fmin(fmax(T(0.5) * (phi0_first + phi0_last), T(-(1 << 20))), T(1 << 20));
+    const T bc = fmin(fmax(T(0.5) * (slope_first + slope_last), T(-2)), T(2));
+    A = (int)floor(ac * scale);
+    B = (int)floor(bc * scale);
 }
 
 // The samples k0..k1 of a ray (phi0, slope) with n_steps samples over n_lines image

@@ -233,20 +233,29 @@ __global__ __launch_bounds__(64 * KS) void k_project(const ProjArgs<T>* __restri
         using GV = const __attribute__((address_space(1))) V;
         GV* __restrict__ wimg = (GV*)(xmask != 0ull ? OT : O);
         const int wl = xmask != 0ull ? ny : nx;  // this wave's interpolation axis
-        T ac, bc;
+        int wa, wb;
         proj_window_line<T>(lane_value(r.phi0, 0), lane_value(r.slope, 0),
-                            lane_value(r.phi0, 63), lane_value(r.slope, 63), ac, bc);
+                            lane_value(r.phi0, 63), lane_value(r.slope, 63), wa, wb);
+        wa = __builtin_amdgcn_readfirstlane(wa);
+        wb = __builtin_amdgcn_readfirstlane(wb);
         auto load = [&](GV* q) {
             V o;
 #pragma unroll
             for (int c = 0; c < W; ++c) o.v[c] = q->v[c];
             return o;
         };
+        // Tap t of line k, addressed from the line's start (uniform) by a 32-bit byte
+        // offset.
+        using GC = const __attribute__((address_space(1))) char;
+        auto tap = [&](int k, int t) {
+            GC* line = (GC*)(wimg + (size_t)k * wl);
+            return load((GV*)(line + (unsigned)t * (unsigned)sizeof(V)));
+        };
         V staged;
         int s_next = 0;
         if (c0 <= c1) {
-            s_next = __builtin_amdgcn_readfirstlane(proj_window<T>(ac, bc, c0));
-            staged = load(wimg + (size_t)c0 * wl + min(max(s_next + lane, 0), wl - 1));
+            s_next = proj_window(wa, wb, c0);
+            staged = tap(c0, min(max(s_next + lane, 0), wl - 1));
         }
         for (int k = c0; k <= c1; ++k) {
             const int s0w = s_next;
@@ -258,8 +267,8 @@ __global__ __launch_bounds__(64 * KS) void k_project(const ProjArgs<T>* __restri
             // the compiler from moving the reads above the write.
             __builtin_amdgcn_wave_barrier();
             if (k < c1) {
-                s_next = __builtin_amdgcn_readfirstlane(proj_window<T>(ac, bc, k + 1));
-                staged = load(wimg + (size_t)(k + 1) * wl + min(max(s_next + lane, 0), wl - 1));
+                s_next = proj_window(wa, wb, k + 1);
+                staged = tap(k + 1, min(max(s_next + lane, 0), wl - 1));
             }
             if (k >= k0 && k <= k1) {
                 T w0, w1;
@@ -278,8 +287,7 @@ __global__ __launch_bounds__(64 * KS) void k_project(const ProjArgs<T>* __restri
                     }
                     add(w0, a0, w1, a1);
                 } else {
-                    GV* line = wimg + (size_t)k * wl;
-                    add(w0, load(line + j), w1, load(line + j + 1));
+                    add(w0, tap(k, j), w1, tap(k, j + 1));
                 }
             }
             __builtin_amdgcn_wave_barrier();
