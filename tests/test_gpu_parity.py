@@ -275,20 +275,21 @@ SAME_A = 1e-4
 SPLIT_MAX = 1e-3
 
 
-def _fp32_lockstep(dect, pr, n_iters):
+def _fp32_lockstep(dect, pr, n_iters, pcg=False):
     """n_iters ADMM iterations of the FP32 library, one call each with its own adaptive rho,
     and of the oracle on the same single-precision inputs replaying, iteration by
-    iteration, the library's LM accept decisions and rho choices.  Returns the oracle's
-    state, the library's state and log, and the largest near-tie ratio of a replayed LM
-    decision on a ray both sides started from the same point."""
+    iteration, the library's LM accept decisions and rho choices (pcg: both with the ramp
+    preconditioner).  Returns the oracle's state, the library's state and log, and the
+    largest near-tie ratio of a replayed LM decision on a ray both sides started from the
+    same point."""
     r32 = lambda a: np.asarray(a, dtype=np.float32).astype(np.float64)
     meas64 = [r32(m) for m in _meas(pr)]
     orc = O.Oracle(pr.geom, pr.spec)
-    prm = O.Params()
+    prm = O.Params(precond="ramp" if pcg else None)
     ost = orc.admm_init(*meas64, prm)
     plan = dect.Plan(pr.geom, pr.spec, F32)
     meas = [dev(m, F32) for m in meas64]
-    params = dect.AdmmParams()
+    params = dect.AdmmParams(precond=dect.PRECOND_RAMP) if pcg else dect.AdmmParams()
     st = plan.new_state()
     plan.admm_init(meas, st, params)
     log, tie = [], 0.0
@@ -339,6 +340,62 @@ def test_admm_fp32_matches_oracle_after_fixed_iterations(dect, n_iters, case):
     assert split <= SPLIT_MAX
     # The logged objective follows the oracle's: single-precision a and y change the
     # data fit and the TV term by far less than the x tolerance.
+    _check_objective_log(log, ost.log, rtol_data=1e-3, rtol_tv=1e-3)
+    assert [tuple(e["rho"]) for e in log] == [tuple(e["rho"]) for e in ost.log]
+
+
+def test_admm_pcg_fp64_256_matches_oracle_after_50_iterations(dect):
+    """UDM1-PCG1 (the ramp-preconditioned CG of the x-update, Sec. 3.3) on the 256^2
+    fan slice in double precision: after 50 iterations, with the oracle replaying the
+    library's LM decisions and rho choices (exact ties can fall either way), x_c and
+    x_p agree to 1e-9."""
+    pr = FP32_CASES["fan256"]()
+    meas64 = list(_meas(pr))
+    orc = O.Oracle(pr.geom, pr.spec)
+    prm = O.Params(precond="ramp")
+    ost = orc.admm_init(*meas64, prm)
+    plan = dect.Plan(pr.geom, pr.spec, F64)
+    meas = [dev(m, F64) for m in meas64]
+    params = dect.AdmmParams(precond=dect.PRECOND_RAMP)
+    st = plan.new_state()
+    plan.admm_init(meas, st, params)
+    for _ in range(50):
+        plan.admm_iterate(meas, st, params, 1)
+        bits = st.lm_accept.cpu().numpy().copy()
+        rho_next = tuple(float(v) for v in st.scalars[:2].cpu().numpy())
+        ost = orc.admm_iterate(ost, *meas64, prm, 1, lm_force=[bits], rho_force=[rho_next])
+    x = host(st.x)
+    ec, ep = rel(x[..., 0], ost.x[0]), rel(x[..., 1], ost.x[1])
+    print(f"\n[pcg fp64] fan256 50 iterations: x_c {ec:.3e} x_p {ep:.3e}", flush=True)
+    assert ec <= 1e-9 and ep <= 1e-9
+
+
+@pytest.mark.parametrize("case", [
+    "fan256",
+    pytest.param("fan512", marks=[pytest.mark.slow, pytest.mark.timeout(900)]),
+])
+def test_admm_pcg_fp32_matches_oracle_after_20_iterations(dect, case):
+    """UDM1-PCG1 in single precision against the FP64 oracle in lockstep (as above),
+    after 20 iterations: x_c within 1e-3 and x_p within 5e-3.  The preconditioned
+    direction is ramp filtered, so its line integrals nearly cancel: the single-
+    precision sums of R p and R^T R p lose about two more digits than with plain CG,
+    and the iterates drift from the oracle by about 3e-5 per iteration in x_c (1.4e-3
+    after 50 iterations at 256^2, where the double-precision library stays within
+    1e-11), against 2e-6 with plain CG.  The near-tie check of the LM decisions is not
+    applied: once the states differ by more than rounding, so do the inputs of a
+    decision."""
+    pr = FP32_CASES[case]()
+    print(f"\n[pcg fp32] {case} 20 iterations in lockstep", flush=True)
+    ost, st, log, tie = _fp32_lockstep(dect, pr, 20, pcg=True)
+    x = host(st.x)
+    ec, ep = rel(x[..., 0], ost.x[0]), rel(x[..., 1], ost.x[1])
+    rtie = max(e.get("rho_tie", 0.0) for e in ost.log)
+    print(f"[pcg fp32] {case}: x_c {ec:.3e} x_p {ep:.3e}; largest LM near-tie ratio {tie:.3g}; "
+          f"rho tie {rtie:.3g}", flush=True)
+    assert ec <= 1e-3
+    assert ep <= 5e-3
+    assert rtie <= RHO_TIE_MAX
+    # The logged objective follows the oracle's, and the rho sequences are the same.
     _check_objective_log(log, ost.log, rtol_data=1e-3, rtol_tv=1e-3)
     assert [tuple(e["rho"]) for e in log] == [tuple(e["rho"]) for e in ost.log]
 
