@@ -198,7 +198,9 @@ __global__ __launch_bounds__(256) void k_rhs(const BpArgs<T>* __restrict__ dev, 
     double part[2] = {0.0, 0.0};
     if (pix < N) {
         T res[2] = {(T)(a.h[2 * pix] + a.u[2 * pix]), (T)(a.h[2 * pix + 1] + a.u[2 * pix + 1])};
-        epilogue<T, EPI_RHS>(a, (int)(pix % a.nx), (int)(pix / a.nx), res, part);
+        int pi, pj;
+        pixel_ij(pix, a.nx, pi, pj);
+        epilogue<T, EPI_RHS>(a, pi, pj, res, part);
     }
     block_sum_store<2>(part, a.part_img + (size_t)blockIdx.x * kPartialSlots);
 }

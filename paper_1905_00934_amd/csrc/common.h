@@ -148,13 +148,24 @@ namespace dect {
 // Workgroups of the transposed projector (8x8 pixel orbits each).
 int bp_blocks(const dect_plan* p);
 
+// Column i and row j of pixel pix of an image nx wide; images hold fewer than 2^30
+// pixels, so the division is unsigned 32-bit.
+__host__ __device__ inline void pixel_ij(long pix, int nx, int& i, int& j) {
+    const unsigned u = (unsigned)pix, r = u / (unsigned)nx;
+    j = (int)r;
+    i = (int)(u - r * (unsigned)nx);
+}
+
 // Standard sinogram index of internal (quad-interleaved when sym = 4) index l:
 // internal order is [Vb][D][sym], standard order [V][D] with view vb + k Vb.
+//
+// sym is 1 or 4 and a plan keeps a sinogram below 2^30 rays, so the index arithmetic
+// is unsigned 32-bit (a 64-bit division costs several times as many instructions).
 __host__ __device__ inline long std_ray(long l, int sym, int Vb, int D) {
     if (sym == 1) return l;
-    const long base = l / sym;
-    const int k = (int)(l % sym);
-    return ((base / D) + (long)k * Vb) * D + base % D;
+    const unsigned u = (unsigned)l, base = u >> 2, k = u & 3u;
+    const unsigned vb = base / (unsigned)D, b = base - vb * (unsigned)D;
+    return ((long)vb + (long)k * Vb) * D + b;
 }
 
 constexpr int kMaxFft = 2048;     // longest padded side of the preconditioner's FFT

@@ -144,7 +144,8 @@ __global__ __launch_bounds__(256) void k_init_image(const T* __restrict__ x0, in
                                                     T* __restrict__ y) {
     const long pix = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (pix >= (long)nx * ny) return;
-    const int j = (int)(pix / nx), i = (int)(pix % nx);
+    int i, j;
+    pixel_ij(pix, nx, i, j);
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
         const T v = x0[2 * pix + c];

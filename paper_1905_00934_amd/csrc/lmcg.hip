@@ -193,7 +193,9 @@ __global__ __launch_bounds__(256) void k_lm_grad(ImgArgs I, int b, const T* __re
     const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     if (k < I.N) {
-        const int i = (int)(k % I.nx), j = (int)(k / I.nx), nx = I.nx, ny = I.ny;
+        int i, j;
+        pixel_ij(k, I.nx, i, j);
+        const int nx = I.nx, ny = I.ny;
         const double rho_d = sc[L_RHO + b];
         const T rho = (T)rho_d;
         T s = T(0);
@@ -227,7 +229,8 @@ __global__ __launch_bounds__(256) void k_lm_hp(ImgArgs I, int b, const T* __rest
     const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     if (k < I.N) {
-        const int i = (int)(k % I.nx), j = (int)(k / I.nx);
+        int i, j;
+        pixel_ij(k, I.nx, i, j);
         const T rho = (T)sc[L_RHO + b];
         const T hp = bp[k] + rho * (dtd(p, i, j, I.nx, I.ny, k) + p[k]);
         q[k] = hp;
@@ -279,7 +282,9 @@ __global__ __launch_bounds__(256) void k_lm_trial_x(ImgArgs I, int b, const T* _
     const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     if (k < I.N) {
-        const int i = (int)(k % I.nx), j = (int)(k / I.nx), nx = I.nx, ny = I.ny;
+        int i, j;
+        pixel_ij(k, I.nx, i, j);
+        const int nx = I.nx, ny = I.ny;
         const T c = x[k] + d[k];
         xt[k] = c;
         // The penalty at x + d, from x and d (xt is being written by other threads).
@@ -327,7 +332,8 @@ __global__ __launch_bounds__(256) void k_lm_tv(ImgArgs I, const T* __restrict__ 
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     if (k < I.N) {
         const long N = I.N;
-        const int i = (int)(k % I.nx), j = (int)(k / I.nx);
+        int i, j;
+        pixel_ij(k, I.nx, i, j);
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
             const T* xb = x + b * N;
@@ -368,7 +374,8 @@ __global__ __launch_bounds__(256) void k_lm_dual(ImgArgs I, const T* __restrict_
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     if (k < I.N) {
         const long N = I.N;
-        const int i = (int)(k % I.nx), j = (int)(k / I.nx);
+        int i, j;
+        pixel_ij(k, I.nx, i, j);
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
             const T s = dt(dy + 2 * b * N, dy + (2 * b + 1) * N, i, j, I.nx, I.ny, k) + dz[b * N + k];
@@ -504,7 +511,8 @@ __global__ __launch_bounds__(256) void k_lm_init(ImgArgs I, const T* __restrict_
     const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= I.N) return;
     const long N = I.N;
-    const int i = (int)(k % I.nx), j = (int)(k / I.nx);
+    int i, j;
+    pixel_ij(k, I.nx, i, j);
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
         const T c = x0 ? x0[2 * k + b] : T(0);

@@ -33,7 +33,8 @@ __device__ inline void tv_dual_block(const TvArgs<T>& A, long blk) {
     const long pix = blk * (long)blockDim.x + threadIdx.x;
     double part[4] = {0.0, 0.0, 0.0, 0.0};
     if (pix < N) {
-        const int j = (int)(pix / nx), i = (int)(pix % nx);
+        int i, j;
+        pixel_ij(pix, nx, i, j);
         const V2* x2 = reinterpret_cast<const V2*>(x);
         const V2* p2 = reinterpret_cast<const V2*>(A.step_p);
         // x after the iteration's last CG step, x + alpha p, when that step is still
