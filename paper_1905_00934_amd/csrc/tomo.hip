@@ -7,23 +7,23 @@
 // views as exact rotations of the V/4 base views (SYM = 4): one Joseph weight
 // computation serves four views.  Otherwise SYM = 1 and every view is a base view.
 //
-// Projector: one lane per base ray; a workgroup covers 256 consecutive bins of
-// one base view, so output writes are coalesced along the detector.  It reads
-// an "orbit" image O[j][i] = (X[rot^k (i, j)], k < SYM) -- the SYM rotated
-// copies interleaved per pixel -- or its transpose for x-stepped rays, so that
-// one load per tap serves all SYM views and neighbouring lanes read
-// neighbouring addresses.
+// Projector: one lane per base ray; a wave holds consecutive bins of one to four
+// neighbouring base views, so output writes are coalesced along the detector.  It
+// reads an "orbit" image O[j][i] = (X[rot^k (i, j)], k < SYM) -- the SYM rotated
+// copies interleaved per pixel -- or its transpose for x-stepped rays, so that one
+// record per tap serves all SYM views; a wave stages the part of each image line its
+// rays cross in LDS and its lanes read their taps from there.
 //
 // Transpose: one lane owns the rotation orbit of a pixel.  For every base view
 // and every orbit member it locates, from the central projection of the
 // two-pixel segment around the pixel, the bins whose samples can touch it, and
 // re-evaluates each candidate's interpolation weight from the same ray geometry;
-// each weight serves SYM (pixel, view) pairs.  The projector forms a0 + alpha (a1 -
-// a0) per sample and scales by the step length at the end, while the transpose
-// forms the weight step max(0, 1 - |d|) explicitly (on symmetric plans from the
-// signed-distance ray records), so the pair is a transpose up to rounding (FP64
-// adjointness to 1e-12), not bit for bit.  The views are split over the waves of a workgroup and
-// the wave sums are added in a fixed order through LDS.
+// each weight serves SYM (pixel, view) pairs.  The projector forms the two tap
+// weights of a sample as tents max(0, 1 - |phi - j|) and scales by the step length at
+// the end, while the transpose forms each weight step max(0, 1 - |d|) from the
+// signed distance d of its own ray records, so the pair is a transpose up to rounding
+// (FP64 adjointness to 1e-12), not bit for bit.  The views are split over the waves
+// of a workgroup and the wave sums are added in a fixed order through LDS.
 #include <mutex>
 
 #include "common.h"
@@ -34,12 +34,6 @@
 namespace dect {
 
 namespace {
-
-template <typename T, int N>
-__device__ inline void vzero(vec<T, N>& a) {
-#pragma unroll
-    for (int c = 0; c < N; ++c) a.v[c] = T(0);
-}
 
 // Pixel (i, j) turned by k quarter turns about the image centre (n x n image).
 __device__ inline void rot(int k, int n, int i, int j, int& io, int& jo) {
