@@ -225,8 +225,9 @@ def _oracle_admm_rate(O, pr, iters: int):
 
 def cpu_baseline(pr, iters: int):
     """The FP64 oracle on the host cores: `iters` ADMM iterations of the same 512x512
-    slice on all threads (the reported value) and one iteration on one thread, and the
-    tiny 64x64 parallel-beam problem in full (20 iterations) on both."""
+    slice on all threads (the reported value) and one iteration on one thread, the tiny
+    64x64 parallel-beam problem in full (20 iterations) on both, and 2 iterations of
+    each size class of the uneven mix on all threads."""
     import oracle as O
     from paper_1905_00934_amd import synth
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -234,6 +235,17 @@ def cpu_baseline(pr, iters: int):
     rate, dt = _oracle_admm_rate(O, pr, iters)
     tiny = synth.tiny_problem(0)
     tiny_all, tiny_all_s = _oracle_admm_rate(O, tiny, 20)
+    # The uneven batch's and the server's three size classes (slices 0, 1, 2 of the
+    # uneven mix): 2 iterations each on all threads, and the oracle's latency per request
+    # at the server's 100-iteration cap projected from that rate (stated as such).
+    per_size = {}
+    for idx in (0, 1, 2):
+        up = synth.uneven_problem(idx, with_image=False)
+        r, d = _oracle_admm_rate(O, up, 2)
+        g = up.geom
+        per_size[f"{g['nx']}x{g['ny']}/{g['n_views']}x{g['n_det']}"] = {
+            "iter_per_s": round(r, 3), "measured_s": round(d, 2), "iterations": 2,
+            "latency_s_at_100_iterations_projected": round(100.0 / r, 1)}
     O.set_threads(1)
     rate1, dt1 = _oracle_admm_rate(O, pr, 1)
     tiny_1, tiny_1_s = _oracle_admm_rate(O, tiny, 20)
@@ -249,7 +261,8 @@ def cpu_baseline(pr, iters: int):
                             "one_thread_iter_per_s": round(tiny_1, 3),
                             "one_thread_s": round(tiny_1_s, 2),
                             "workload": "64x64 parallel beam, 90 views x 95 bins, FP64, "
-                                        "20 ADMM iterations (the whole tiny configuration)"}}
+                                        "20 ADMM iterations (the whole tiny configuration)"},
+            "per_size_all_threads": per_size}
 
 
 def batch_workload(dect, torch, dev, items, params, steps, warmup):
