@@ -104,6 +104,7 @@ def algorithmic_bytes(N: int, M: int, cg_iters: int, elem: int = 4) -> dict:
         "backproject_dual": 2 * M + 14 * N,         # da; dy, dz; h in and out
         "project": 2 * N + 2 * M,                   # p; R p
         "orbit": 2 * N + 16 * N,                    # p; its orbit image and the transpose
+        "rhs_orbit": 24 * N + extra + 16 * N,       # the right-hand side and r0's orbit images
         # a-update: m, w, a, R x, R p, u^a, f cache in; a, u^a, R x, da, cache out; with
         # the TV/z/dual blocks: x, y, u^y, z, u^z in; y, u^y, dy, z, u^z, dz out
         "udm": 32 * M + 32 * N,

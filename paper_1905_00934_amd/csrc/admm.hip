@@ -383,7 +383,14 @@ hipError_t iteration_t(const SliceJob<T>& J, const JobArrays<T>* dev, int nsl,
     } while (0)
     const dim3 gN(nblk(J.N), 1, z), gM(nblk(J.M), 1, z);
     const VecArgs<T>* dvec = dev ? dev->vec : nullptr;
-    {
+    // CG (not PCG) starts from p0 = r0: on a quarter-turn symmetric slice the
+    // right-hand-side kernel also writes the orbit images of r0 the projector reads.
+    const bool fused = !J.precond && rhs_orbit_fits(J.sym, J.rhs.nx, J.rhs.ny);
+    if (fused) {
+        ProfScope ps("rhs_orbit", s);
+        DECT_TRY(launch_rhs_orbit<T>(dev ? dev->rhs : nullptr, J.rhs, dev ? dev->orb : nullptr,
+                                     J.orb, nsl, s));
+    } else {
         // R^T t of the right-hand side is tracked (h + u), so no transpose is needed.
         ProfScope ps("rhs", s);
         hipLaunchKernelGGL((k_rhs<T, BATCH>), gN, dim3(256), 0, s, dev ? dev->rhs : nullptr,
@@ -394,7 +401,7 @@ hipError_t iteration_t(const SliceJob<T>& J, const JobArrays<T>* dev, int nsl,
     for (int c = 0; c < n; ++c) {
         DECT_TRY(launch_project_pair<T>(J.sym, J.pj_waves, dev ? dev->orb : nullptr, J.orb,
                                         dev ? dev->prj : nullptr, J.prj, nsl, J.N, J.pj_gx,
-                                        J.pj_gy, s));
+                                        J.pj_gy, s, !(fused && c == 0)));
         DECT_TRY(launch_backproject_admm<T>(J.sym, J.bp_waves, EPI_Q, dev ? dev->q : nullptr, J.q,
                                             nsl, J.bp_gx, J.bp_gy, s));
         DECT_TRY(reduce(RED_ALPHA));

@@ -256,12 +256,23 @@ hipError_t launch_project(const dect_plan* p, const void* img, void* sino, int c
 // Two-channel projection of the ADMM direction into quad-interleaved records, for
 // one slice (dev == nullptr: `one`) or n slices (dev: device arrays); the grid is
 // (gx, gy) projector blocks of `waves` (2, 4 or 8) waves splitting the lines, and
-// `pixels` orbit-image threads per slice.
+// `pixels` orbit-image threads per slice.  orbit = false: the orbit images are
+// already in place (written by launch_rhs_orbit) and only the projector runs.
 template <typename T>
 hipError_t launch_project_pair(int sym, int waves, const OrbitArgs<T>* odev,
                                const OrbitArgs<T>& oone, const ProjArgs<T>* pdev,
                                const ProjArgs<T>& pone, int n, long pixels, int gx, int gy,
-                               hipStream_t s);
+                               hipStream_t s, bool orbit = true);
+// The CG right-hand side (as the right-hand-side kernel: r0 into rhs.out and rhs.out2,
+// partials of |r0|^2 per 256 pixels into rhs.part_img) and, in the same launch, the
+// orbit images of r0 into orb.O and orb.OT, for quarter-turn symmetric square slices
+// of side n with n % 16 == 0 (rhs_orbit_fits); one slice or nsl slices in dev arrays.
+__host__ __device__ inline bool rhs_orbit_fits(int sym, int nx, int ny) {
+    return sym == 4 && nx == ny && nx >= 16 && nx % 16 == 0;
+}
+template <typename T>
+hipError_t launch_rhs_orbit(const BpArgs<T>* dev, const BpArgs<T>& one, const OrbitArgs<T>* odev,
+                            const OrbitArgs<T>& oone, int nsl, hipStream_t s);
 // Plain R^T of a standard-order sinogram with ch channels (one slice).
 template <typename T>
 hipError_t launch_backproject(const dect_plan* p, int ch, const BpArgs<T>& a, hipStream_t s);

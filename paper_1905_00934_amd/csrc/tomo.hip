@@ -134,6 +134,78 @@ __global__ __launch_bounds__(256) void k_orbit_tiled(const OrbitArgs<T>* __restr
     }
 }
 
+// The CG right-hand side of Eq. (12) (what k_rhs computes) and the orbit images of
+// it (what k_orbit_tiled writes) in one launch, for a quarter-turn symmetric square
+// image with n % 16 == 0.  A workgroup owns an 8x8 tile of the first quadrant and its
+// three rotations: wave k computes r0 on rotation k of the tile in memory order, the
+// four tiles' values meet in LDS, and every record of the four tiles is written to O
+// along i and to OT along j.  Each partial of |r0|^2 covers the workgroup's 256
+// pixels.  The quadrant's tiles are dealt to the XCDs in bands of consecutive tiles,
+// so that most stencil neighbours of a tile are read through the same L2.
+template <typename T, bool BATCH>
+__global__ __launch_bounds__(256) void k_rhs_orbit(const BpArgs<T>* __restrict__ dev,
+                                                   BpArgs<T> one,
+                                                   const OrbitArgs<T>* __restrict__ odev,
+                                                   OrbitArgs<T> oone) {
+    using V2 = vec<T, 2>;
+    using R = vec<T, 8>;
+    constexpr int TS = 8;
+    __shared__ V2 xs[4][TS][TS + 1];  // xs[k][a][b] = r0 at rot^k(i0 + b, j0 + a)
+    const BpArgs<T> A = pick_args<BATCH>(dev, one);
+    const OrbitArgs<T> Ob = pick_args<BATCH>(odev, oone);
+    const int n = A.nx;
+    const unsigned h = (unsigned)n / (2 * TS), tiles = h * h, id = blockIdx.x;
+    if (id >= tiles) return;  // beyond this slice (whole block)
+    const unsigned tile =
+        tiles % kXcds == 0 ? (id % kXcds) * (tiles / kXcds) + id / kXcds : id;
+    const int i0 = (int)(tile % h) * TS, j0 = (int)(tile / h) * TS;
+    const int k = (int)(threadIdx.x >> 6), l = (int)(threadIdx.x & 63);
+    // Lower corner (ci, cj) of rotation k of the tile [i0, i0 + TS) x [j0, j0 + TS).
+    int ci, cj;
+    switch (k) {
+        case 0: ci = i0; cj = j0; break;
+        case 1: ci = n - TS - j0; cj = i0; break;
+        case 2: ci = n - TS - i0; cj = n - TS - j0; break;
+        default: ci = j0; cj = n - TS - i0; break;
+    }
+    const int back = (4 - k) & 3;  // rot^back undoes rot^k
+    {
+        const int pi = ci + (l & (TS - 1)), pj = cj + (l >> 3);
+        const size_t pix = (size_t)pj * n + pi;
+        T res[2] = {(T)(A.h[2 * pix] + A.u[2 * pix]), (T)(A.h[2 * pix + 1] + A.u[2 * pix + 1])};
+        double part[2] = {0.0, 0.0};
+        epilogue<T, EPI_RHS>(A, pi, pj, res, part);
+        int ib, jb;
+        rot(back, n, pi, pj, ib, jb);
+        V2& d = xs[k][jb - j0][ib - i0];
+        d.v[0] = res[0];
+        d.v[1] = res[1];
+        block_sum_store<2>(part, A.part_img + (size_t)tile * kPartialSlots);
+    }
+    __syncthreads();
+    // The record of pixel P = rot^k(B), B = (i0 + b, j0 + a): component kk of it is r0
+    // at rot^kk(P) = rot^(kk + k)(B).
+    auto rec = [&](int pi, int pj) {
+        int ib, jb;
+        rot(back, n, pi, pj, ib, jb);
+        const int a = jb - j0, b = ib - i0;
+        R o;
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) o.v[kk * 2 + c] = xs[(kk + k) & 3][a][b].v[c];
+        return o;
+    };
+    {
+        const int pi = ci + (l & (TS - 1)), pj = cj + (l >> 3);  // along i
+        reinterpret_cast<R*>(Ob.O)[(size_t)pj * n + pi] = rec(pi, pj);
+    }
+    {
+        const int pi = ci + (l >> 3), pj = cj + (l & (TS - 1));  // along j
+        reinterpret_cast<R*>(Ob.OT)[(size_t)pi * n + pj] = rec(pi, pj);
+    }
+}
+
 // The value of x in lane l (uniform).
 __device__ inline float lane_value(float x, int l) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
@@ -818,8 +890,9 @@ constexpr int kLineSplit = 8;
 
 template <typename T, int CH, int SYM, bool QUAD, bool BATCH, int KS>
 void project_launch(const OrbitArgs<T>* odev, const OrbitArgs<T>& oone, const ProjArgs<T>* pdev,
-                    const ProjArgs<T>& pone, int n, long pixels, int gx, int gy, hipStream_t s) {
-    {
+                    const ProjArgs<T>& pone, int n, long pixels, int gx, int gy, hipStream_t s,
+                    bool orbit) {
+    if (orbit) {
         ProfScope pt("orbit", s);
         if constexpr (SYM == 4) {
             constexpr int TS = 16;
@@ -839,11 +912,13 @@ void project_launch(const OrbitArgs<T>* odev, const OrbitArgs<T>& oone, const Pr
 template <typename T, int CH, int SYM, bool QUAD, int KS>
 hipError_t project_t(const OrbitArgs<T>* odev, const OrbitArgs<T>& oone,
                      const ProjArgs<T>* pdev, const ProjArgs<T>& pone, int n, long pixels, int gx,
-                     int gy, hipStream_t s) {
+                     int gy, hipStream_t s, bool orbit = true) {
     if (odev)
-        project_launch<T, CH, SYM, QUAD, true, KS>(odev, oone, pdev, pone, n, pixels, gx, gy, s);
+        project_launch<T, CH, SYM, QUAD, true, KS>(odev, oone, pdev, pone, n, pixels, gx, gy, s,
+                                                   orbit);
     else
-        project_launch<T, CH, SYM, QUAD, false, KS>(odev, oone, pdev, pone, n, pixels, gx, gy, s);
+        project_launch<T, CH, SYM, QUAD, false, KS>(odev, oone, pdev, pone, n, pixels, gx, gy, s,
+                                                    orbit);
     return hipGetLastError();
 }
 
@@ -940,11 +1015,11 @@ hipError_t bp_admm(int waves, int epi, const BpArgs<T>* dev, const BpArgs<T>& on
 template <typename T, int SYM>
 hipError_t project_pair_w(int waves, const OrbitArgs<T>* odev, const OrbitArgs<T>& oone,
                           const ProjArgs<T>* pdev, const ProjArgs<T>& pone, int n, long pixels,
-                          int gx, int gy, hipStream_t s) {
+                          int gx, int gy, hipStream_t s, bool orbit) {
     switch (waves) {
-        case 2: return project_t<T, 2, SYM, true, 2>(odev, oone, pdev, pone, n, pixels, gx, gy, s);
-        case 4: return project_t<T, 2, SYM, true, 4>(odev, oone, pdev, pone, n, pixels, gx, gy, s);
-        case 8: return project_t<T, 2, SYM, true, 8>(odev, oone, pdev, pone, n, pixels, gx, gy, s);
+        case 2: return project_t<T, 2, SYM, true, 2>(odev, oone, pdev, pone, n, pixels, gx, gy, s, orbit);
+        case 4: return project_t<T, 2, SYM, true, 4>(odev, oone, pdev, pone, n, pixels, gx, gy, s, orbit);
+        case 8: return project_t<T, 2, SYM, true, 8>(odev, oone, pdev, pone, n, pixels, gx, gy, s, orbit);
     }
     return hipErrorInvalidValue;
 }
@@ -1009,9 +1084,26 @@ template <typename T>
 hipError_t launch_project_pair(int sym, int waves, const OrbitArgs<T>* odev,
                                const OrbitArgs<T>& oone, const ProjArgs<T>* pdev,
                                const ProjArgs<T>& pone, int n, long pixels, int gx, int gy,
-                               hipStream_t s) {
-    return sym == 4 ? project_pair_w<T, 4>(waves, odev, oone, pdev, pone, n, pixels, gx, gy, s)
-                    : project_pair_w<T, 1>(waves, odev, oone, pdev, pone, n, pixels, gx, gy, s);
+                               hipStream_t s, bool orbit) {
+    return sym == 4
+               ? project_pair_w<T, 4>(waves, odev, oone, pdev, pone, n, pixels, gx, gy, s, orbit)
+               : project_pair_w<T, 1>(waves, odev, oone, pdev, pone, n, pixels, gx, gy, s, orbit);
+}
+
+template <typename T>
+hipError_t launch_rhs_orbit(const BpArgs<T>* dev, const BpArgs<T>& one, const OrbitArgs<T>* odev,
+                            const OrbitArgs<T>& oone, int nsl, hipStream_t s) {
+    if (!rhs_orbit_fits(4, one.nx, one.ny) || oone.nx != one.nx || oone.ny != one.ny ||
+        (dev == nullptr) != (odev == nullptr) || nsl < 1 || (dev == nullptr && nsl != 1))
+        return hipErrorInvalidValue;
+    const unsigned h = (unsigned)one.nx / 16;
+    const dim3 g(h * h, 1, (unsigned)nsl);
+    if (dev)
+        hipLaunchKernelGGL((k_rhs_orbit<T, true>), g, dim3(256), 0, s, dev, one, odev, oone);
+    else
+        hipLaunchKernelGGL((k_rhs_orbit<T, false>), g, dim3(256), 0, s, nullptr, one, nullptr,
+                           oone);
+    return hipGetLastError();
 }
 
 template <typename T>
@@ -1049,7 +1141,10 @@ hipError_t launch_backproject_admm(int sym, int waves, int epi, const BpArgs<T>*
     template hipError_t launch_project<T>(const dect_plan*, const void*, void*, int, hipStream_t); \
     template hipError_t launch_project_pair<T>(int, int, const OrbitArgs<T>*, const OrbitArgs<T>&, \
                                                const ProjArgs<T>*, const ProjArgs<T>&, int, long, \
-                                               int, int, hipStream_t);                            \
+                                               int, int, hipStream_t, bool);                      \
+    template hipError_t launch_rhs_orbit<T>(const BpArgs<T>*, const BpArgs<T>&,                  \
+                                            const OrbitArgs<T>*, const OrbitArgs<T>&, int,       \
+                                            hipStream_t);                                        \
     template hipError_t launch_backproject<T>(const dect_plan*, int, const BpArgs<T>&, hipStream_t); \
     template hipError_t launch_backproject_admm<T>(int, int, int, const BpArgs<T>*,              \
                                                    const BpArgs<T>&, int, int, int, hipStream_t);
