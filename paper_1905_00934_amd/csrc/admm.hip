@@ -10,9 +10,14 @@
 //   per-ray LM on Eq. (13) with R x += alpha R p and u^a (one lane per ray), and in
 //   the same launch y, z, u^y, u^z (Eq. (9)-(11)) with their partials (one lane per
 //   pixel), reading x through the pending last CG step
-//   R^T da + D^T dy + dz                             (dual residual; R^T da also goes to h)
+//   R^T da + D^T dy + dz                             (dual residual; R^T da also goes to h;
+//                                                    per pixel also the last CG step
+//                                                    x += alpha p, h -= alpha R^T R p,
+//                                                    and u += h)
 //   residuals, rho and the log                        (one workgroup)
-//   the last CG step and the dual rescale            (elementwise)
+// The dual rescale after a change of rho, kappa = rho_old / rho_new, is left pending:
+// the next iteration's readers of u, u^a, u^y, u^z scale them as they read them, and
+// the end of a call applies what is still pending (k_settle).
 #include <cmath>
 #include <cstring>
 
@@ -105,71 +110,49 @@ __global__ __launch_bounds__(256) void k_p_step(const VecArgs<T>* __restrict__ d
     reinterpret_cast<V2*>(A.p)[i] = a;
 }
 
-// Scaled duals follow rho: u *= rho_old / rho_new, and t = a + u^a - R x again.
+// The pending dual rescale kappa = rho_old / rho_new applied to the stored duals:
+// u (R^T u^a), u^a, u^y, u^z.  Every element is scaled as its reader in the next
+// iteration would scale it, so the iterations continue bitwise as without it.
 template <typename T, bool BATCH>
-__global__ __launch_bounds__(256) void k_rescale(const RescaleArgs<T>* __restrict__ dev,
-                                                 RescaleArgs<T> one) {
+__global__ __launch_bounds__(256) void k_settle(const RescaleArgs<T>* __restrict__ dev,
+                                                RescaleArgs<T> one) {
     using V2 = vec<T, 2>;
     using V4 = vec<T, 4>;
     const RescaleArgs<T> A = pick_args<BATCH>(dev, one);
     const long M = A.M, N = A.N;
-    const int sym = A.sym, Vb = A.Vb, D = A.D;
-    T* __restrict__ ua = A.ua;
-    T* __restrict__ t = A.t;
-    const T* __restrict__ a = A.a;
-    const T* __restrict__ Rx = A.Rx;
-    T* __restrict__ uy = A.uy;
-    T* __restrict__ uz = A.uz;
     if ((long)blockIdx.x * blockDim.x >= (M > N ? M : N)) return;
     const double k0 = A.scal[S_KAPPA], k1 = A.scal[S_KAPPA + 1];
-    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < N) {
-        double hv[2] = {A.h[2 * i], A.h[2 * i + 1]};
-        if (A.x) {
-            // The iteration's last CG step: x += alpha p, and R x having moved by alpha R p,
-            // the tracked R^T (a - R x) by -alpha R^T R p.
-            const double al[2] = {A.scal[S_ALPHA], A.scal[S_ALPHA + 1]};
-            V2 xv = reinterpret_cast<V2*>(A.x)[i];
-            const V2 pv = reinterpret_cast<const V2*>(A.p)[i];
-            const V2 rr = reinterpret_cast<const V2*>(A.rtrp)[i];
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                xv.v[c] = fma((T)al[c], pv.v[c], xv.v[c]);
-                hv[c] = fma(-al[c], (double)rr.v[c], hv[c]);
-                A.h[2 * i + c] = hv[c];
-            }
-            reinterpret_cast<V2*>(A.x)[i] = xv;
-        }
-        // u^a <- kappa (u^a + a - R x) gives R^T u^a <- kappa (R^T u^a + R^T (a - R x)).
-        A.u[2 * i] = k0 * (A.u[2 * i] + hv[0]);
-        A.u[2 * i + 1] = k1 * (A.u[2 * i + 1] + hv[1]);
-    }
     if (k0 == 1.0 && k1 == 1.0) return;
     const T kc[2] = {(T)k0, (T)k1};
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < M) {
-        const long si = std_ray(i, sym, Vb, D);
-        V2 u = reinterpret_cast<V2*>(ua)[si];
+        V2 u = reinterpret_cast<V2*>(A.ua)[i];
 #pragma unroll
-        for (int c = 0; c < 2; ++c) u.v[c] *= kc[c];
-        reinterpret_cast<V2*>(ua)[si] = u;
-        if (t) {  // the sinogram right-hand side, when it is kept
-            const V2 av = reinterpret_cast<const V2*>(a)[si];
-            const V2 rv = reinterpret_cast<const V2*>(Rx)[si];
-            V2 tv;
-#pragma unroll
-            for (int c = 0; c < 2; ++c) tv.v[c] = av.v[c] + u.v[c] - rv.v[c];
-            reinterpret_cast<V2*>(t)[i] = tv;
-        }
+        for (int c = 0; c < 2; ++c) u.v[c] = mul_rn(kc[c], u.v[c]);
+        reinterpret_cast<V2*>(A.ua)[i] = u;
     }
     if (i < N) {
-        V4 u4 = reinterpret_cast<V4*>(uy)[i];
+        A.u[2 * i] = mul_rn(k0, A.u[2 * i]);
+        A.u[2 * i + 1] = mul_rn(k1, A.u[2 * i + 1]);
+        V4 u4 = reinterpret_cast<V4*>(A.uy)[i];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) u4.v[k] *= kc[k & 1];
-        reinterpret_cast<V4*>(uy)[i] = u4;
-        V2 u2 = reinterpret_cast<V2*>(uz)[i];
-        u2.v[0] *= kc[0];
-        u2.v[1] *= kc[1];
-        reinterpret_cast<V2*>(uz)[i] = u2;
+        for (int k = 0; k < 4; ++k) u4.v[k] = mul_rn(kc[k & 1], u4.v[k]);
+        reinterpret_cast<V4*>(A.uy)[i] = u4;
+        V2 u2 = reinterpret_cast<V2*>(A.uz)[i];
+        u2.v[0] = mul_rn(kc[0], u2.v[0]);
+        u2.v[1] = mul_rn(kc[1], u2.v[1]);
+        reinterpret_cast<V2*>(A.uz)[i] = u2;
+    }
+}
+
+// kappa = 1 once k_settle has applied it (a launch of its own: every thread of
+// k_settle reads kappa).
+template <typename T, bool BATCH>
+__global__ void k_settle_done(const RescaleArgs<T>* __restrict__ dev, RescaleArgs<T> one) {
+    const RescaleArgs<T> A = pick_args<BATCH>(dev, one);
+    if (threadIdx.x == 0) {
+        A.scal[S_KAPPA] = 1.0;
+        A.scal[S_KAPPA + 1] = 1.0;
     }
 }
 
@@ -197,7 +180,8 @@ __global__ __launch_bounds__(256) void k_rhs(const BpArgs<T>* __restrict__ dev, 
     const long pix = (long)blockIdx.x * blockDim.x + threadIdx.x;
     double part[2] = {0.0, 0.0};
     if (pix < N) {
-        T res[2] = {(T)(a.h[2 * pix] + a.u[2 * pix]), (T)(a.h[2 * pix + 1] + a.u[2 * pix + 1])};
+        T res[2];
+        rhs_tracked(a, (size_t)pix, res);
         int pi, pj;
         pixel_ij(pix, a.nx, pi, pj);
         epilogue<T, EPI_RHS>(a, pi, pj, res, part);
@@ -304,10 +288,17 @@ SliceJob<T> make_job(const dect_plan* p, const void* mh, const void* ml, const v
     J.rhs.part_img = P.img;
     J.q.raw = rtrp;
     J.dual.h = hh;
+    J.rhs.scal = scal;
+    // The last CG step of the iteration (x += alpha p, h -= alpha R^T R p) is applied
+    // by the dual transpose's epilogue, and read through by the TV update before it;
+    // the same epilogue adds the new h to u.
+    J.dual.u = uu;
+    J.dual.scal = scal;
+    J.dual.step_x = x;
+    J.dual.step_p = pp;
+    J.dual.step_rtrp = rtrp;
     // The scalar steps (CG step sizes; residuals, rho and the log) run as one
-    // workgroup per slice.  The last CG step of the iteration (x += alpha p,
-    // h -= alpha R^T R p) is applied by the rescale kernel at the end, and read through
-    // by the TV update before it.
+    // workgroup per slice.
     J.red = RedArgs{P.tiles, p->nb_tiles, P.img, p->nb_img, P.sino, p->nb_sino, P.pre, p->nb_pre,
                     pre ? 1 : 0, scal,
                     at<double>(st, p->off_log), prm->rho_mode,
@@ -353,8 +344,7 @@ SliceJob<T> make_job(const dect_plan* p, const void* mh, const void* ml, const v
     u.udm_blocks = (int)nblk(p->M);
     u.tv = J.tv;
     // The iterations keep R^T t tracked in h + u, not t itself (t is set at the start).
-    J.resc = RescaleArgs<T>{p->M, p->N, p->sym, p->Vb, p->D, ua, nullptr, a, Rx, uy, uz, scal,
-                            hh, uu, x, pp, rtrp};
+    J.resc = RescaleArgs<T>{p->M, p->N, ua, uy, uz, uu, scal};
     return J;
 }
 
@@ -413,7 +403,7 @@ hipError_t iteration_t(const SliceJob<T>& J, const JobArrays<T>* dev, int nsl,
             DECT_TRY(reduce(RED_BETA));
             hipLaunchKernelGGL((k_p_step<T, BATCH>), gN, dim3(256), 0, s, dvec, J.vec);
         }
-        // The last step's x and h updates are applied by the rescale kernel.
+        // The last step's x and h updates are applied by the dual transpose.
         DECT_TRY(hipGetLastError());
     }
     // The a-update (Eq. (13)) and, in the same launch, the TV/z/dual update.
@@ -425,17 +415,27 @@ hipError_t iteration_t(const SliceJob<T>& J, const JobArrays<T>* dev, int nsl,
     DECT_TRY(launch_backproject_admm<T>(J.sym, J.bp_waves, EPI_DUAL, dev ? dev->dual : nullptr,
                                         J.dual, nsl, J.bp_gx, J.bp_gy, s));
     DECT_TRY(reduce(RED_FINAL));
-    {
-        ProfScope ps("rescale", s);
-        hipLaunchKernelGGL((k_rescale<T, BATCH>), dim3(nblk(J.M > J.N ? J.M : J.N), 1, z), dim3(256), 0,
-                           s, dev ? dev->resc : nullptr, J.resc);
-        DECT_TRY(hipGetLastError());
-    }
 #undef DECT_TRY
     return hipSuccess;
 }
 
+template <typename T, bool BATCH>
+hipError_t settle_t(const SliceJob<T>& J, const JobArrays<T>* dev, int nsl, hipStream_t s) {
+    ProfScope ps("settle", s);
+    const unsigned z = (unsigned)nsl;
+    hipLaunchKernelGGL((k_settle<T, BATCH>), dim3(nblk(J.M > J.N ? J.M : J.N), 1, z), dim3(256), 0,
+                       s, dev ? dev->resc : nullptr, J.resc);
+    hipLaunchKernelGGL((k_settle_done<T, BATCH>), dim3(1, 1, z), dim3(64), 0, s,
+                       dev ? dev->resc : nullptr, J.resc);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+template <typename T>
+hipError_t launch_settle(const SliceJob<T>& J, const JobArrays<T>* dev, int nsl, hipStream_t s) {
+    return dev ? settle_t<T, true>(J, dev, nsl, s) : settle_t<T, false>(J, nullptr, 1, s);
+}
 
 template <typename T>
 hipError_t launch_iteration(const SliceJob<T>& J, const JobArrays<T>* dev, int nsl,
@@ -463,6 +463,8 @@ hipError_t launch_track_init(const dect_plan* p, void* st, hipStream_t s) {
                                      const void*, void*, const dect_params*);                    \
     template hipError_t launch_iteration<T>(const SliceJob<T>&, const JobArrays<T>*, int,        \
                                             const dect_params*, long, hipStream_t);              \
+    template hipError_t launch_settle<T>(const SliceJob<T>&, const JobArrays<T>*, int,           \
+                                         hipStream_t);                                           \
     template hipError_t launch_track_init<T>(const dect_plan*, void*, hipStream_t);
 DECT_INST(float)
 DECT_INST(double)
@@ -490,6 +492,12 @@ dect_status iterate_T(const dect_plan* p, const void* mh, const void* ml, const 
     const SliceJob<T> J = make_job<T>(p, mh, ml, wh, wl, st, prm);
     for (int k = 0; k < n_iters; ++k) {
         const hipError_t e = launch_iteration<T>(J, nullptr, 1, prm, it0 + k, s);
+        if (e != hipSuccess)
+            return fail(DECT_E_DEVICE, "launch failed: %s", hipGetErrorString(e));
+    }
+    // The state's duals hold their scaled values between calls.
+    if (n_iters > 0) {
+        const hipError_t e = launch_settle<T>(J, nullptr, 1, s);
         if (e != hipSuccess)
             return fail(DECT_E_DEVICE, "launch failed: %s", hipGetErrorString(e));
     }

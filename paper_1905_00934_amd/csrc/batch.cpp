@@ -146,6 +146,15 @@ hipError_t Runner<T>::enqueue(hipStream_t s) const {
     return hipSuccess;
 }
 
+template <typename T>
+hipError_t Runner<T>::settle(hipStream_t s) const {
+    for (const Group& g : groups_) {
+        hipError_t e = launch_settle<T>(g.jobs[0], &g.dev, (int)g.jobs.size(), s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 template class Runner<float>;
 template class Runner<double>;
 
@@ -168,6 +177,9 @@ struct dect_batch {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         if (cap) (void)hipStreamDestroy(cap);
+    }
+    hipError_t settle(hipStream_t s) {
+        return dtype == DECT_F32 ? rf.settle(s) : rd.settle(s);
     }
     hipError_t enqueue(hipStream_t s) {
         return dtype == DECT_F32 ? rf.enqueue(s) : rd.enqueue(s);
@@ -257,12 +269,19 @@ dect_status dect_batch_iterate(dect_batch* b, int n_iters, void* stream) {
     if (n_iters < 0) return fail(DECT_E_ARG, "n_iters must be >= 0");
     hipStream_t s = static_cast<hipStream_t>(stream);
     // Direct launches when timing per kernel (the events bracket each launch).
+    // The states' duals hold their scaled values between calls.
+    auto settle = [&]() -> dect_status {
+        if (n_iters == 0) return DECT_OK;
+        const hipError_t e = b->settle(s);
+        return e == hipSuccess ? DECT_OK
+                               : fail(DECT_E_DEVICE, "launch failed: %s", hipGetErrorString(e));
+    };
     if (!b->use_graph || prof_enabled()) {
         for (int k = 0; k < n_iters; ++k) {
             hipError_t e = b->enqueue(s);
             if (e != hipSuccess) return fail(DECT_E_DEVICE, "launch failed: %s", hipGetErrorString(e));
         }
-        return DECT_OK;
+        return settle();
     }
     if (!b->exec) {
         // Capture one outer iteration of every group on a private stream (a capture
@@ -281,7 +300,7 @@ dect_status dect_batch_iterate(dect_batch* b, int n_iters, void* stream) {
         DECT_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
     }
     for (int k = 0; k < n_iters; ++k) DECT_HIP(hipGraphLaunch(b->exec, s));
-    return DECT_OK;
+    return settle();
 }
 
 int dect_batch_groups(const dect_batch* b) {

@@ -7,6 +7,21 @@
 
 namespace dect {
 
+// The tracked R^T t = h + u of the right-hand side at pixel pix: u is read scaled by
+// the pending kappa (scal == nullptr: 1) and stored back scaled.
+template <typename T>
+__device__ inline void rhs_tracked(const BpArgs<T>& a, size_t pix, T (&res)[2]) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        double u = a.u[2 * pix + c];
+        if (a.scal) {
+            u = mul_rn(a.scal[S_KAPPA + c], u);
+            a.u[2 * pix + c] = u;
+        }
+        res[c] = (T)(a.h[2 * pix + c] + u);
+    }
+}
+
 // Image-side terms added to R^T at pixel (i, j) for the ADMM epilogues (CH = 2).
 // Adds the per-channel partial sums of the finished values to part.
 template <typename T, int EPI>
@@ -17,13 +32,26 @@ __device__ inline void epilogue(const BpArgs<T>& a, int i, int j, T (&res)[2], d
     const size_t pix = (size_t)j * nx + i;
     const V2* x2 = reinterpret_cast<const V2*>(a.x);
     if constexpr (EPI == EPI_RHS) {
-        // r0 = R^T t + D^T (y + u^y - D x) + (z + u^z - x), Eq. (12).
+        // r0 = R^T t + D^T (y + u^y - D x) + (z + u^z - x), Eq. (12), with u^y and u^z
+        // scaled by the pending kappa as they are read (their stored values are
+        // scaled by the TV update that follows).
+        const T k0 = a.scal ? (T)a.scal[S_KAPPA] : T(1), k1 = a.scal ? (T)a.scal[S_KAPPA + 1] : T(1);
         const V4* y4 = reinterpret_cast<const V4*>(a.y);
-        const V4* u4 = reinterpret_cast<const V4*>(a.uy);
+        const V4* uy4 = reinterpret_cast<const V4*>(a.uy);
+        auto u4 = [&](size_t q) {
+            V4 v = uy4[q];
+            v.v[0] = mul_rn(k0, v.v[0]);
+            v.v[1] = mul_rn(k1, v.v[1]);
+            v.v[2] = mul_rn(k0, v.v[2]);
+            v.v[3] = mul_rn(k1, v.v[3]);
+            return v;
+        };
         const V2 xc = x2[pix];
         const V2 z = reinterpret_cast<const V2*>(a.z)[pix];
-        const V2 uz = reinterpret_cast<const V2*>(a.uz)[pix];
-        const V4 yc = y4[pix], uc = u4[pix];
+        V2 uz = reinterpret_cast<const V2*>(a.uz)[pix];
+        uz.v[0] = mul_rn(k0, uz.v[0]);
+        uz.v[1] = mul_rn(k1, uz.v[1]);
+        const V4 yc = y4[pix], uc = u4(pix);
 #pragma unroll
         for (int c = 0; c < 2; ++c) res[c] += z.v[c] + uz.v[c] - xc.v[c];
         if (i < nx - 1) {
@@ -33,7 +61,7 @@ __device__ inline void epilogue(const BpArgs<T>& a, int i, int j, T (&res)[2], d
         }
         if (i > 0) {
             const V2 xl = x2[pix - 1];
-            const V4 yl = y4[pix - 1], ul = u4[pix - 1];
+            const V4 yl = y4[pix - 1], ul = u4(pix - 1);
 #pragma unroll
             for (int c = 0; c < 2; ++c) res[c] += yl.v[c] + ul.v[c] - (xc.v[c] - xl.v[c]);
         }
@@ -44,7 +72,7 @@ __device__ inline void epilogue(const BpArgs<T>& a, int i, int j, T (&res)[2], d
         }
         if (j > 0) {
             const V2 xu = x2[pix - nx];
-            const V4 yu = y4[pix - nx], uu = u4[pix - nx];
+            const V4 yu = y4[pix - nx], uu = u4(pix - nx);
 #pragma unroll
             for (int c = 0; c < 2; ++c) res[c] += yu.v[2 + c] + uu.v[2 + c] - (xc.v[c] - xu.v[c]);
         }
@@ -80,8 +108,27 @@ __device__ inline void epilogue(const BpArgs<T>& a, int i, int j, T (&res)[2], d
         part[1] += (double)pc.v[1] * (double)res[1];
     } else {  // EPI_DUAL: s = R^T da + D^T dy + dz; h += R^T da
         if (a.h) {
-            a.h[2 * pix] += (double)res[0];
-            a.h[2 * pix + 1] += (double)res[1];
+            double hv[2] = {a.h[2 * pix] + (double)res[0], a.h[2 * pix + 1] + (double)res[1]};
+            if (a.step_x) {
+                // The iteration's last CG step: x += alpha p, and R x having moved by
+                // alpha R p, the tracked R^T (a - R x) by -alpha R^T R p.  Then the
+                // a-block dual update u^a += a - R x in R^T form, u += h; its rescale by
+                // kappa (not known before this launch's partials are summed) is left to
+                // the readers of u.
+                const double al[2] = {a.scal[S_ALPHA], a.scal[S_ALPHA + 1]};
+                V2 xv = reinterpret_cast<V2*>(a.step_x)[pix];
+                const V2 pv = reinterpret_cast<const V2*>(a.step_p)[pix];
+                const V2 rr = reinterpret_cast<const V2*>(a.step_rtrp)[pix];
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    xv.v[c] = fma((T)al[c], pv.v[c], xv.v[c]);
+                    hv[c] = fma(-al[c], (double)rr.v[c], hv[c]);
+                    a.u[2 * pix + c] = a.u[2 * pix + c] + hv[c];
+                }
+                reinterpret_cast<V2*>(a.step_x)[pix] = xv;
+            }
+            a.h[2 * pix] = hv[0];
+            a.h[2 * pix + 1] = hv[1];
         }
         const V4* d4 = reinterpret_cast<const V4*>(a.y);
         const V4 dc = d4[pix];

@@ -11,11 +11,15 @@ enum Epilogue : int { EPI_NONE = 0, EPI_RHS = 1, EPI_Q = 2, EPI_DUAL = 3 };
 // Arguments of the transposed projector and its image-side epilogues.
 //  EPI_NONE: out = R^T sino (ch channels)
 //  EPI_RHS : out (and out2 if set) = R^T t + D^T (y + uy - D x) + (z + uz - x);
-//            partials = per-channel |out|^2.  Only the right-hand-side kernel uses it,
-//            with the tracked R^T t = h + u in place of a transpose.
+//            partials = per-channel |out|^2.  Only the right-hand-side kernels use it,
+//            with the tracked R^T t = h + u in place of a transpose; the duals u, uy, uz
+//            are read scaled by the pending kappa = scal[S_KAPPA] (scal == nullptr: 1)
 //  EPI_Q   : out (if set) = R^T sino + D^T D x + x, with x = p; partials = p . out;
 //            raw (if set) = R^T sino
-//  EPI_DUAL: y = dy, z = dz; partials = |R^T sino + D^T dy + dz|^2; h (if set) += R^T sino
+//  EPI_DUAL: y = dy, z = dz; partials = |R^T sino + D^T dy + dz|^2; h (if set) += R^T sino;
+//            with step_x set also the iteration's last CG step, x += alpha step_p and
+//            h -= alpha step_rtrp (alpha = scal[S_ALPHA]), and u += h (the dual update
+//            of u^a in R^T form, its rescale by kappa left to the next right-hand side)
 // Every kernel takes its per-slice arguments either by value (BATCH = false: one
 // slice) or as a device array indexed by blockIdx.z (BATCH = true: several
 // slices of one shape in one launch).  The array is read word by word through
@@ -123,7 +127,25 @@ struct BpArgs {
     double* u;
     T* raw;
     double* part_img;
+    // The ADMM's device scalars (kappa for EPI_RHS; alpha for EPI_DUAL's CG step) and
+    // the last CG step EPI_DUAL applies: x, the direction p and R^T R p (x == nullptr:
+    // no step).
+    const double* scal;
+    T* step_x;
+    const T* step_p;
+    const T* step_rtrp;
 };
+
+// a * b rounded by itself: never contracted with a neighbouring add into one fma, so
+// that a value scaled on the fly rounds exactly as the same value scaled and stored.
+__device__ inline float mul_rn(float a, float b) {
+#pragma clang fp contract(off)
+    return a * b;
+}
+__device__ inline double mul_rn(double a, double b) {
+#pragma clang fp contract(off)
+    return a * b;
+}
 
 // Deterministic sum of K doubles over a 256-thread block (fixed shuffle and LDS
 // order); thread 0 stores the K sums at out.  Every thread of the block must call it.
@@ -393,28 +415,19 @@ struct VecArgs {
 
 // Shrinkage, nonnegativity and the y, z duals (Eq. (9)-(11)).
 
-// Dual rescale after a change of rho.
+// The dual rescale after a change of rho, kappa = rho_old / rho_new, which the
+// iterations leave pending (every reader of u, u^a, u^y, u^z scales by it on the fly
+// and the next right-hand side, a-update and TV update store the scaled values):
+// applied to all four at the end of a call, then kappa = 1.
 template <typename T>
 struct RescaleArgs {
     long M, N;
-    int sym, Vb, D;
     T* ua;
-    T* t;
-    const T* a;
-    const T* Rx;
     T* uy;
     T* uz;
-    const double* scal;
-    double* h;  // R^T (a - R x) of the new iterate
-    double* u;  // R^T u^a: u <- kappa (u + h)
-    // The iteration's last CG step, applied here: x += alpha p and h -= alpha R^T R p,
-    // alpha = scal[S_ALPHA] (the TV update read x through it before).  x == nullptr:
-    // none.
-    T* x;
-    const T* p;
-    const T* rtrp;
+    double* u;  // R^T u^a
+    double* scal;
 };
-
 
 // Every argument block of one slice's outer iteration, and its launch extents.
 template <typename T>
@@ -462,6 +475,10 @@ SliceJob<T> make_job(const dect_plan* p, const void* mh, const void* ml, const v
 template <typename T>
 hipError_t launch_iteration(const SliceJob<T>& one, const JobArrays<T>* dev, int n,
                             const dect_params* prm, long it, hipStream_t s);
+// The pending dual rescale of `one` or of n slices in dev applied to the state's
+// arrays (RescaleArgs), so that they hold the scaled duals between calls.
+template <typename T>
+hipError_t launch_settle(const SliceJob<T>& one, const JobArrays<T>* dev, int n, hipStream_t s);
 
 // f and its gradient of both spectra at (R x_c, R x_p) for the LM x CG scheme, with
 // `at` the basis' projection and `ao` the other one's; cache [6][M]; partials: data

@@ -23,6 +23,9 @@ public:
     hipError_t set(const std::vector<SliceJob<T>>& jobs);
     // One outer iteration of every slice, enqueued on s.
     hipError_t enqueue(hipStream_t s) const;
+    // The dual rescale the iterations leave pending, applied to every slice's state
+    // (launch_settle), enqueued on s.
+    hipError_t settle(hipStream_t s) const;
     int groups() const { return (int)groups_.size(); }
     int slices() const { return n_; }
 

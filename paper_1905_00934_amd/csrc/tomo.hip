@@ -172,7 +172,8 @@ __global__ __launch_bounds__(256) void k_rhs_orbit(const BpArgs<T>* __restrict__
     {
         const int pi = ci + (l & (TS - 1)), pj = cj + (l >> 3);
         const size_t pix = (size_t)pj * n + pi;
-        T res[2] = {(T)(A.h[2 * pix] + A.u[2 * pix]), (T)(A.h[2 * pix + 1] + A.u[2 * pix + 1])};
+        T res[2];
+        rhs_tracked(A, pix, res);
         double part[2] = {0.0, 0.0};
         epilogue<T, EPI_RHS>(A, pi, pj, res, part);
         int ib, jb;

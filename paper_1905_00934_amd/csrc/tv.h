@@ -66,7 +66,11 @@ __device__ inline void tv_dual_block(const TvArgs<T>& A, long blk) {
             Dx.v[2] = Dx.v[3] = T(0);
         }
         const T th[2] = {(T)(scal[S_LAM] / scal[S_RHO]), (T)(scal[S_LAM + 1] / scal[S_RHO + 1])};
+        // u^y and u^z as rescaled by the pending kappa (stored below with their update).
+        const T kc[2] = {(T)scal[S_KAPPA], (T)scal[S_KAPPA + 1]};
         V4 u = reinterpret_cast<V4*>(uy)[pix];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) u.v[k] = mul_rn(kc[k & 1], u.v[k]);
         const V4 yo = reinterpret_cast<V4*>(y)[pix];
         V4 yn, d;
 #pragma unroll
@@ -82,6 +86,8 @@ __device__ inline void tv_dual_block(const TvArgs<T>& A, long blk) {
         reinterpret_cast<V4*>(uy)[pix] = u;
         reinterpret_cast<V4*>(dy)[pix] = d;
         V2 w = reinterpret_cast<V2*>(uz)[pix];
+        w.v[0] = mul_rn(kc[0], w.v[0]);
+        w.v[1] = mul_rn(kc[1], w.v[1]);
         const V2 zo = reinterpret_cast<V2*>(z)[pix];
         V2 zn, dzv;
 #pragma unroll

@@ -232,7 +232,10 @@ __global__ __launch_bounds__(256) void k_udm(const UdmArgs<T>* __restrict__ dev,
             // R x after the last CG step (tracked: R x += alpha R p), v = R x - u^a.
             const V2 rx0 = reinterpret_cast<const V2*>(A.Rx)[i];
             const V2 rp2 = reinterpret_cast<const V2*>(A.Rp)[l];
+            // u^a as rescaled by the pending kappa (stored below with its update).
             ua = reinterpret_cast<const V2*>(A.ua)[i];
+            ua.v[0] = mul_rn((T)A.scal[S_KAPPA], ua.v[0]);
+            ua.v[1] = mul_rn((T)A.scal[S_KAPPA + 1], ua.v[1]);
             rx.v[0] = rx0.v[0] + (T)A.scal[S_ALPHA] * rp2.v[0];
             rx.v[1] = rx0.v[1] + (T)A.scal[S_ALPHA + 1] * rp2.v[1];
             vc = rx.v[0] - ua.v[0];

@@ -153,6 +153,27 @@ def test_batch_full_size_graph_equals_alone(dect):
     b.close()
 
 
+def test_pending_dual_rescale_settles_at_call_ends(dect):
+    """The iterations leave the dual rescale after a change of rho pending for the readers
+    of the duals and each call applies what is still pending: 20 calls of one iteration
+    must give the state of one call of 20, bit for bit, with rho changing on the way."""
+    params = dect.AdmmParams()
+    pr = S.uneven_problem(0, with_image=False)
+    plan = dect.Plan(pr.geom, pr.spec, F32)
+    meas = _meas(pr, F32)
+    one, many = plan.new_state(), plan.new_state()
+    plan.admm_init(meas, one, params)
+    plan.admm_init(meas, many, params)
+    log = plan.admm_iterate(meas, one, params, 20, log=True)
+    for _ in range(20):
+        plan.admm_iterate(meas, many, params, 1)
+    torch.cuda.synchronize()
+    rhos = [e["rho"] for e in log]
+    assert any(r != rhos[0] for r in rhos), "rho never changed: the test would be vacuous"
+    assert torch.equal(one.buf, many.buf)
+    assert one.scalars[2].item() == 1.0 and one.scalars[3].item() == 1.0  # nothing pending
+
+
 def test_batch_argument_errors(dect):
     params = dect.AdmmParams()
     sl = _setup(dect, F32, params, MIX[:2])
