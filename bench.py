@@ -99,16 +99,17 @@ def algorithmic_bytes(N: int, M: int, cg_iters: int, elem: int = 4) -> dict:
     of their values counts as two FP32 words."""
     extra = 2 * N if cg_iters > 1 else 0
     return {k: v * elem for k, v in {
-        "rhs": 24 * N + extra,                      # h, u; x, y, u^y, z, u^z; p (and r)
+        "rhs": 28 * N + extra,                      # h, u in, u out; x, y, u^y, z, u^z; p (and r)
         "backproject_q": 2 * M + 4 * N + extra,     # R p; p; R^T R p (and q)
-        "backproject_dual": 2 * M + 14 * N,         # da; dy, dz; h in and out
+        # da; dy, dz; h in and out; the last CG step: x in and out, p, R^T R p; u in and out
+        "backproject_dual": 2 * M + 30 * N,
         "project": 2 * N + 2 * M,                   # p; R p
         "orbit": 2 * N + 16 * N,                    # p; its orbit image and the transpose
-        "rhs_orbit": 24 * N + extra + 16 * N,       # the right-hand side and r0's orbit images
+        "rhs_orbit": 28 * N + extra + 16 * N,       # the right-hand side and r0's orbit images
         # a-update: m, w, a, R x, R p, u^a, f cache in; a, u^a, R x, da, cache out; with
         # the TV/z/dual blocks: x, y, u^y, z, u^z in; y, u^y, dy, z, u^z, dz out
         "udm": 32 * M + 32 * N,
-        "rescale": 4 * M + 24 * N,                  # u, h in, u out; when rho changes u^a, u^y, u^z in and out
+        "settle": 4 * M + 20 * N,                   # once per call, after a change of rho: u^a, u, u^y, u^z in and out
         "cg_vector": 16 * N,                        # x in and out, p, R^T R p, h in and out
     }.items()}
 
