@@ -250,6 +250,28 @@ def test_admm_fp64_symmetric_fan_matches_oracle(dect):
     _check_objective_log(log, ost.log)
 
 
+@pytest.mark.parametrize("n, views, bins", [(48, 88, 80), (40, 72, 66)])
+def test_admm_fp64_symmetric_fan_sizes_match_oracle(dect, n, views, bins):
+    """CG(1) on quarter-turn symmetric fans whose right-hand side takes the other
+    paths: n = 48 writes the orbit images with the right-hand side in plain tile order
+    (9 quadrant tiles, not a multiple of the 8 XCDs), n = 40 (n % 16 != 0) runs the
+    right-hand side and the orbit images as two kernels."""
+    g = S.fan_geometry_fov(n, views, bins, fov_cm=0.4 * n, src_iso_cm=40.0, src_det_cm=70.0)
+    k = g["nx"] * g["pixel_cm"] / 32.0
+    ph = S.tiny_phantom(7)
+    ph = S.Phantom([S.Shape(sh.kind, k * sh.cx, k * sh.cy, k * sh.ax, k * sh.ay, sh.rot,
+                            sh.xc, sh.xp) for sh in ph.shapes])
+    pr = S.make_problem(f"sym_fan{n}", g, ph, 1e5, 7, with_image=False)
+    prm = O.Params()
+    ost = _admm_oracle(pr, prm, 8)
+    _, st, log = _admm_gpu(dect, pr, F64, dect.AdmmParams(), 8)
+    x = host(st.x)
+    for b in range(2):
+        assert rel(x[..., b], ost.x[b]) <= 1e-8
+    assert [e["rho"] for e in log] == [tuple(e["rho"]) for e in ost.log]
+    _check_objective_log(log, ost.log)
+
+
 # Problems of the FP32 parity runs: the uneven mix's 256^2 / 360 x 512 and
 # 384^2 / 540 x 768 classes, and the single 512^2 / 720 x 1024 luggage slice.
 FP32_CASES = {
