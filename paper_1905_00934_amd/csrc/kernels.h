@@ -47,21 +47,24 @@ __device__ inline A pick_args(const A* __restrict__ dev, const A& one) {
     return pick_args<BATCH>(dev, one, blockIdx.z);
 }
 
-// Workgroups of a batched launch of n slices of T workgroups each, placed so that all
-// workgroups of a slice run on one XCD: the dispatcher deals consecutive workgroup ids
-// to the kXcds XCDs in turn, so id = XCD + kXcds k, and XCD x takes slices x, x + kXcds,
-// ... one after the other (k = T j + tile).  A slice's data then passes through one
-// XCD's L2 instead of being fetched by all of them.  Returns false for the padding
-// workgroups of XCDs with fewer slices.
+// Workgroups of a batched launch of n slices of T workgroups each, dealt so that every
+// XCD takes an equal, contiguous share of the slice-major sequence of the n T
+// workgroups: the dispatcher deals consecutive workgroup ids to the kXcds XCDs in
+// turn, so id = XCD + kXcds k, and XCD x takes sequence positions x P + k, with
+// P = ceil(n T / kXcds).  A slice's workgroups then run on as few XCDs as that balance
+// allows (on one when n is a multiple of kXcds, on about kXcds / n when n < kXcds), so
+// its data passes through few L2s and no XCD idles.  Returns false for the padding
+// workgroups past the n T of the sequence.
 __device__ inline bool xcd_slice_tile(unsigned id, unsigned T, unsigned n, unsigned& slice,
                                       unsigned& tile) {
-    const unsigned x = id % kXcds, k = id / kXcds;
-    slice = x + kXcds * (k / T);
-    tile = k % T;
-    return slice < n;
+    const unsigned P = (n * T + kXcds - 1) / kXcds;
+    const unsigned g = (id % kXcds) * P + id / kXcds;
+    slice = g / T;
+    tile = g % T;
+    return g < n * T;
 }
 __host__ __device__ inline unsigned xcd_slice_blocks(unsigned T, unsigned n) {
-    return kXcds * ((n + kXcds - 1) / kXcds) * T;
+    return kXcds * ((n * T + kXcds - 1) / kXcds);
 }
 
 template <typename T>

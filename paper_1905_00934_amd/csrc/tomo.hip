@@ -759,8 +759,9 @@ __global__ __launch_bounds__(64 * VS) void k_backproject(const BpArgs<T>* __rest
         else return red_own[w];
     };
     // The orbit block (bx, by) of this workgroup: its 2-D grid position for one slice;
-    // in a batch, a 1-D grid with every slice's blocks on one XCD (one.gx, one.gy: the
-    // group's block grid, the same for all its slices).
+    // in a batch, a 1-D grid that gives each XCD an equal contiguous share of the
+    // slices' blocks (one.gx, one.gy: the group's block grid, the same for all its
+    // slices).
     int bx, by;
     unsigned slice = 0;
     if constexpr (BATCH) {
@@ -974,8 +975,9 @@ hipError_t bp_plain(const BpArgs<T>& one, hipStream_t s) {
 template <typename T, int SYM, bool BATCH, int VS>
 hipError_t bp_admm_t(int epi, const BpArgs<T>* dev, const BpArgs<T>& one, int n, int gx, int gy,
                      hipStream_t s) {
-    // One slice: a (gx, gy) grid.  A batch: every slice's blocks on one XCD; the kernel
-    // takes the block grid from `one`, the same for every slice of the group.
+    // One slice: a (gx, gy) grid.  A batch: each XCD an equal contiguous share of the
+    // slices' blocks; the kernel takes the block grid from `one`, the same for every
+    // slice of the group.
     if (gx != one.gx || gy != one.gy) return hipErrorInvalidValue;
     const dim3 g = BATCH ? dim3(xcd_slice_blocks((unsigned)(gx * gy), (unsigned)n)) : dim3(gx, gy);
     const dim3 blk(64 * VS);
