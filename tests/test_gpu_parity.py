@@ -399,13 +399,13 @@ def test_admm_pcg_fp64_256_matches_oracle_after_50_iterations(dect):
 def test_admm_pcg_fp32_matches_oracle_after_20_iterations(dect, case):
     """UDM1-PCG1 in single precision against the FP64 oracle in lockstep (as above),
     after 20 iterations: x_c within 1e-3 and x_p within 5e-3.  The preconditioned
-    direction is ramp filtered, so its line integrals nearly cancel: the single-
-    precision sums of R p and R^T R p lose about two more digits than with plain CG,
-    and the iterates drift from the oracle by about 3e-5 per iteration in x_c (1.4e-3
-    after 50 iterations at 256^2, where the double-precision library stays within
-    1e-11), against 2e-6 with plain CG.  The near-tie check of the LM decisions is not
-    applied: once the states differ by more than rounding, so do the inputs of a
-    decision."""
+    direction is ramp filtered, so the terms of R^T over its projection nearly cancel,
+    and the single-precision sums of R^T lose enough digits that the iterates drift
+    from the oracle by about 3e-5 per iteration in x_c (1.4e-3 after 50 iterations at
+    256^2, where the double-precision library stays within 1e-11; 3.4e-4 with R^T
+    summing in double), against 2e-6 with plain CG.  The near-tie check of the LM
+    decisions is not applied: once the states differ by more than rounding, so do the
+    inputs of a decision."""
     pr = FP32_CASES[case]()
     print(f"\n[pcg fp32] {case} 20 iterations in lockstep", flush=True)
     ost, st, log, tie = _fp32_lockstep(dect, pr, 20, pcg=True)
