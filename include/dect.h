@@ -172,7 +172,18 @@ typedef struct {
     const double* rho_schedule;/* host, 2*rho_schedule_len doubles, for DECT_RHO_SCHEDULE */
     int rho_schedule_len;
     int precond;               /* dect_precond: CG (0) or CG preconditioned by the ramp filter */
+    int rt_sums;               /* dect_rt_sums: precision of the ADMM transposes' sums */
 } dect_params;
+
+/* Sums of the ADMM's transposes (R^T of the CG direction's projection and of the
+ * change of a) on an FP32 plan.  PLAN: single precision.  F64: the products (exact
+ * in double) summed in double precision and each result rounded once, at about 40 %
+ * more transpose time.  The terms of R^T over the projection of a ramp-filtered
+ * direction nearly cancel: with DECT_PRECOND_RAMP on an FP32 plan, F64 sums keep the
+ * iterates near those of double-precision arithmetic for longer (x_c within ~3e-4
+ * after 50 iterations on a 256^2 slice, against ~1.4e-3 with PLAN).  FP64 plans sum
+ * in double either way.  Slices of a batch share launches only if this agrees. */
+typedef enum { DECT_RT_SUMS_PLAN = 0, DECT_RT_SUMS_F64 = 1 } dect_rt_sums;
 
 /* Preconditioner of the x-update (Sec. 3.3: the system of Eq. (12) is shift-invariant,
  * so CG is preconditioned by a high-pass filter applied by FFT).  RAMP: the image is

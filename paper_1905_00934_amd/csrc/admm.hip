@@ -243,6 +243,7 @@ SliceJob<T> make_job(const dect_plan* p, const void* mh, const void* ml, const v
     J.cg_iters = prm->cg_iters;
     J.rho_mode = prm->rho_mode;
     J.precond = pre ? 1 : 0;
+    J.rt_sums64 = prm->rt_sums == DECT_RT_SUMS_F64 ? 1 : 0;
     J.N = p->N;
     J.M = p->M;
     J.sym = p->sym;
@@ -393,7 +394,7 @@ hipError_t iteration_t(const SliceJob<T>& J, const JobArrays<T>* dev, int nsl,
                                         dev ? dev->prj : nullptr, J.prj, nsl, J.N, J.pj_gx,
                                         J.pj_gy, s, !(fused && c == 0)));
         DECT_TRY(launch_backproject_admm<T>(J.sym, J.bp_waves, EPI_Q, dev ? dev->q : nullptr, J.q,
-                                            nsl, J.bp_gx, J.bp_gy, s));
+                                            nsl, J.bp_gx, J.bp_gy, s, J.rt_sums64 != 0));
         DECT_TRY(reduce(RED_ALPHA));
         if (c < n - 1) {
             ProfScope ps("cg_vector", s);
@@ -413,7 +414,7 @@ hipError_t iteration_t(const SliceJob<T>& J, const JobArrays<T>* dev, int nsl,
         DECT_TRY(launch_udm<T>(nullptr, 2, J.udm, s));
     // R^T da: the dual residual (adaptive rho) and the tracked h in every mode.
     DECT_TRY(launch_backproject_admm<T>(J.sym, J.bp_waves, EPI_DUAL, dev ? dev->dual : nullptr,
-                                        J.dual, nsl, J.bp_gx, J.bp_gy, s));
+                                        J.dual, nsl, J.bp_gx, J.bp_gy, s, J.rt_sums64 != 0));
     DECT_TRY(reduce(RED_FINAL));
 #undef DECT_TRY
     return hipSuccess;
@@ -445,7 +446,7 @@ hipError_t launch_iteration(const SliceJob<T>& J, const JobArrays<T>* dev, int n
 }
 
 template <typename T>
-hipError_t launch_track_init(const dect_plan* p, void* st, hipStream_t s) {
+hipError_t launch_track_init(const dect_plan* p, void* st, hipStream_t s, bool sums64) {
     double* hh = at<double>(st, p->off_h);
     hipLaunchKernelGGL(k_zero_f64, dim3(nblk(2 * p->N)), dim3(256), 0, s, hh, 2 * p->N);
     BpArgs<T> b{};
@@ -455,7 +456,8 @@ hipError_t launch_track_init(const dect_plan* p, void* st, hipStream_t s) {
     b.z = at<T>(st, p->off_dz);  // zero at the start
     b.h = hh;
     b.partials = at<double>(st, p->off_partials) + (size_t)(p->nb_sino + p->nb_img) * kPartialSlots;
-    return launch_backproject_admm<T>(p->sym, p->bp_waves, EPI_DUAL, nullptr, b, 1, b.gx, b.gy, s);
+    return launch_backproject_admm<T>(p->sym, p->bp_waves, EPI_DUAL, nullptr, b, 1, b.gx, b.gy, s,
+                                      sums64);
 }
 
 #define DECT_INST(T)                                                                            \
@@ -465,7 +467,7 @@ hipError_t launch_track_init(const dect_plan* p, void* st, hipStream_t s) {
                                             const dect_params*, long, hipStream_t);              \
     template hipError_t launch_settle<T>(const SliceJob<T>&, const JobArrays<T>*, int,           \
                                          hipStream_t);                                           \
-    template hipError_t launch_track_init<T>(const dect_plan*, void*, hipStream_t);
+    template hipError_t launch_track_init<T>(const dect_plan*, void*, hipStream_t, bool);
 DECT_INST(float)
 DECT_INST(double)
 #undef DECT_INST
@@ -558,7 +560,7 @@ dect_status init_T(const dect_plan* p, const void* mh, const void* ml, const voi
     u.lin[2] = -lc / det;
     u.lin[3] = hc / det;
     hipError_t e = launch_udm<T>(p, 1, u, s);
-    if (e == hipSuccess) e = launch_track_init<T>(p, st, s);
+    if (e == hipSuccess) e = launch_track_init<T>(p, st, s, prm->rt_sums == DECT_RT_SUMS_F64);
     if (e != hipSuccess) return fail(DECT_E_DEVICE, "launch failed: %s", hipGetErrorString(e));
     return DECT_OK;
 }
@@ -576,6 +578,8 @@ dect_status check_params(const dect_params* prm) {
     if (!(prm->lm_mu0 > 0)) return fail(DECT_E_ARG, "lm_mu0 must be > 0");
     if (prm->precond != DECT_PRECOND_NONE && prm->precond != DECT_PRECOND_RAMP)
         return fail(DECT_E_ARG, "bad precond %d", prm->precond);
+    if (prm->rt_sums != DECT_RT_SUMS_PLAN && prm->rt_sums != DECT_RT_SUMS_F64)
+        return fail(DECT_E_ARG, "bad rt_sums %d", prm->rt_sums);
     return DECT_OK;
 }
 
@@ -702,8 +706,9 @@ dect_status dect_admm_init_image(const dect_plan* p, const void* m_h, const void
     dect_status st = dect_admm_init(p, m_h, m_l, w_h, w_l, state, prm, stream);
     if (st) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const hipError_t e = p->dtype == DECT_F32 ? launch_init_image<float>(p, x0, state, s)
-                                              : launch_init_image<double>(p, x0, state, s);
+    const bool sums64 = prm->rt_sums == DECT_RT_SUMS_F64;
+    const hipError_t e = p->dtype == DECT_F32 ? launch_init_image<float>(p, x0, state, s, sums64)
+                                              : launch_init_image<double>(p, x0, state, s, sums64);
     if (e != hipSuccess) return fail(DECT_E_DEVICE, "launch failed: %s", hipGetErrorString(e));
     return DECT_OK;
 }

@@ -24,7 +24,7 @@ bool same_shape(const SliceJob<T>& a, const SliceJob<T>& b) {
            a.prj.nx == b.prj.nx && a.prj.ny == b.prj.ny && a.cg_iters == b.cg_iters &&
            a.rho_mode == b.rho_mode && a.bp_waves == b.bp_waves && a.pj_waves == b.pj_waves &&
            a.pj_views == b.pj_views && a.pj_chunk == b.pj_chunk &&
-           a.precond == b.precond;
+           a.precond == b.precond && a.rt_sums64 == b.rt_sums64;
 }
 
 // Byte offsets of the ten argument arrays of a group of n slices.
@@ -140,6 +140,7 @@ hipError_t Runner<T>::enqueue(hipStream_t s) const {
         prm.cg_iters = g.jobs[0].cg_iters;
         prm.rho_mode = g.jobs[0].rho_mode;
         prm.precond = g.jobs[0].precond;
+        prm.rt_sums = g.jobs[0].rt_sums64 ? DECT_RT_SUMS_F64 : DECT_RT_SUMS_PLAN;
         hipError_t e = launch_iteration<T>(g.jobs[0], &g.dev, (int)g.jobs.size(), &prm, 0, s);
         if (e != hipSuccess) return e;
     }
@@ -219,6 +220,8 @@ dect_status check_batch_params(const dect_params* prm) {
         return fail(DECT_E_ARG, "rho must be > 0 and lambda >= 0");
     if (prm->precond != DECT_PRECOND_NONE && prm->precond != DECT_PRECOND_RAMP)
         return fail(DECT_E_ARG, "bad precond %d", prm->precond);
+    if (prm->rt_sums != DECT_RT_SUMS_PLAN && prm->rt_sums != DECT_RT_SUMS_F64)
+        return fail(DECT_E_ARG, "bad rt_sums %d", prm->rt_sums);
     return DECT_OK;
 }
 

@@ -235,7 +235,8 @@ hipError_t start_t(const dect_plan* p, const void* a, void* fbp, void* x0, hipSt
 }  // namespace
 
 template <typename T>
-hipError_t launch_init_image(const dect_plan* p, const void* x0, void* state, hipStream_t s) {
+hipError_t launch_init_image(const dect_plan* p, const void* x0, void* state, hipStream_t s,
+                             bool sums64) {
     const dect_layout& L = p->layout;
     char* st = static_cast<char*>(state);
     T* Rx = reinterpret_cast<T*>(st + L.Rx);
@@ -252,11 +253,13 @@ hipError_t launch_init_image(const dect_plan* p, const void* x0, void* state, hi
                        reinterpret_cast<T*>(st + p->off_t));
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_track_init<T>(p, state, s);
+    return launch_track_init<T>(p, state, s, sums64);
 }
 
-template hipError_t launch_init_image<float>(const dect_plan*, const void*, void*, hipStream_t);
-template hipError_t launch_init_image<double>(const dect_plan*, const void*, void*, hipStream_t);
+template hipError_t launch_init_image<float>(const dect_plan*, const void*, void*, hipStream_t,
+                                             bool);
+template hipError_t launch_init_image<double>(const dect_plan*, const void*, void*, hipStream_t,
+                                              bool);
 
 }  // namespace dect
 

@@ -302,10 +302,12 @@ hipError_t launch_rhs_orbit(const BpArgs<T>* dev, const BpArgs<T>& one, const Or
 template <typename T>
 hipError_t launch_backproject(const dect_plan* p, int ch, const BpArgs<T>& a, hipStream_t s);
 // ADMM epilogue variants of R^T on quad records, one or n slices; `waves` (2, 4
-// or 8) split the views of a workgroup.
+// or 8) split the views of a workgroup.  sums64: keep the sums in double precision
+// (the products of an FP32 plan are exact in double; the result is rounded once).
 template <typename T>
 hipError_t launch_backproject_admm(int sym, int waves, int epi, const BpArgs<T>* dev,
-                                   const BpArgs<T>& one, int n, int gx, int gy, hipStream_t s);
+                                   const BpArgs<T>& one, int n, int gx, int gy, hipStream_t s,
+                                   bool sums64 = false);
 // Fill the plan-dependent fields of BpArgs.
 template <typename T>
 void fill_bp_plan(const dect_plan* p, BpArgs<T>& a);
@@ -450,6 +452,7 @@ struct SliceJob {
     int bp_waves, pj_waves;  // workgroup shapes of the plan
     int pj_views, pj_chunk;  // projector lane layout and workgroup order of the plan
     int cg_iters, rho_mode;  // launch structure: slices share launches only if these agree
+    int rt_sums64;           // the ADMM transposes sum in double (dect_rt_sums)
 };
 
 // Device copies of the argument blocks of n slices of one shape, in slice order.
@@ -492,14 +495,16 @@ hipError_t launch_lm_eval(const dect_plan* p, int basis, const T* at, const T* a
                           hipStream_t s);
 
 // The tracked right-hand side of a state whose t (= a + u^a - R x, internal ray order)
-// and zero u^a, dy, dz were just set: h = R^T t, by one transpose.
+// and zero u^a, dy, dz were just set: h = R^T t, by one transpose (sums64: summed in
+// double precision, as the iterations' transposes with dect_rt_sums F64).
 template <typename T>
-hipError_t launch_track_init(const dect_plan* p, void* state, hipStream_t s);
+hipError_t launch_track_init(const dect_plan* p, void* state, hipStream_t s, bool sums64);
 
 // Start of the iterations from an image pair x0: x = z = x0, y = D x0, R x = R x0,
 // t = a - R x0 and h = R^T t (the state already initialised with x = 0).
 template <typename T>
-hipError_t launch_init_image(const dect_plan* p, const void* x0, void* state, hipStream_t s);
+hipError_t launch_init_image(const dect_plan* p, const void* x0, void* state, hipStream_t s,
+                             bool sums64);
 
 template <typename T>
 hipError_t launch_ingest(const dect_plan* p, const void* ch, const void* cl, double i0h,

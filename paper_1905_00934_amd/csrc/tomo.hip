@@ -415,9 +415,9 @@ __device__ inline float fast_rcp<float>(float x) { return __builtin_amdgcn_rcpf(
 // max(0, step (1 - |phi - p|)) is the projector's linear-interpolation weight of
 // the pixel at minor coordinate p for the sample at phi, phi computed with the
 // same fma on the same table entries as the projector's sample position.
-template <typename T, int CH, int SYM, int VS>
+template <typename T, typename A, int CH, int SYM, int VS>
 __device__ inline void gather_orbit(const BpArgs<T>& a, int wave, int i, int j,
-                                    T (&acc)[SYM][CH]) {
+                                    A (&acc)[SYM][CH]) {
     const T m = (T)a.margin;
     const int D = a.D, Vb = a.Vb, n = a.nx;
     const T cx = T(0.5) * (T)(a.nx - 1), cy = T(0.5) * (T)(a.ny - 1);
@@ -450,7 +450,8 @@ __device__ inline void gather_orbit(const BpArgs<T>& a, int wave, int i, int j,
                 for (int kp = 0; kp < SYM; ++kp) {
                     const vec<T, CH> t = sv[(size_t)(v + kp * Vb) * D + b];
 #pragma unroll
-                    for (int c = 0; c < CH; ++c) acc[(mm + kp) % SYM][c] += wt * t.v[c];
+                    for (int c = 0; c < CH; ++c)
+                        acc[(mm + kp) % SYM][c] = fma((A)wt, (A)t.v[c], acc[(mm + kp) % SYM][c]);
                 }
             }
         }
@@ -477,9 +478,9 @@ __device__ inline void rotf(int k, int n, T i, T j, T& io, T& jo) {
 // each lane loading them again.  The loads for the wave's next view are issued
 // before the current view is accumulated, so their latency is hidden.  A candidate
 // outside the window (a steep footprint near the source) is loaded directly.
-template <typename T, int CH, int SYM, int VS>
+template <typename T, typename A, int CH, int SYM, int VS>
 __device__ inline void gather_orbit_staged(const BpArgs<T>& a, int wave, int lane, int i, int j,
-                                           int bx, int by, bool inside, T (&acc)[SYM][CH]) {
+                                           int bx, int by, bool inside, A (&acc)[SYM][CH]) {
     constexpr int WIN = 16;
     using Q = vec<T, SYM * CH>;
     __shared__ RayParam<T> s_ray[VS][WIN * SYM];
@@ -562,7 +563,8 @@ __device__ inline void gather_orbit_staged(const BpArgs<T>& a, int wave, int lan
                     for (int kp = 0; kp < SYM; ++kp)
 #pragma unroll
                         for (int c = 0; c < CH; ++c)
-                            acc[(mm + kp) % SYM][c] += wt * s.v[kp * CH + c];
+                            acc[(mm + kp) % SYM][c] =
+                                fma((A)wt, (A)s.v[kp * CH + c], acc[(mm + kp) % SYM][c]);
                 }
             }
         }
@@ -598,9 +600,9 @@ constexpr int kWideStride = kWideWin + kBpFixed;
 
 // Each lane stages WIN * SYM / 64 records.  s_win: the workgroup's staging windows,
 // [VS][SYM members][kWideStride]; each wave uses only its own row.
-template <typename T, int CH, int SYM, int VS>
+template <typename T, typename A, int CH, int SYM, int VS>
 __device__ inline void gather_orbit_staged_wide(const BpArgs<T>& a, int wave, int lane, int i, int j,
-                                                int bx, int by, bool inside, T (&acc)[SYM][CH],
+                                                int bx, int by, bool inside, A (&acc)[SYM][CH],
                                                 Staged<T, CH, SYM> (*s_win)[kWideStride * SYM]) {
     constexpr int WIN = kWideWin;
     constexpr int REC = WIN * SYM;
@@ -707,7 +709,8 @@ __device__ inline void gather_orbit_staged_wide(const BpArgs<T>& a, int wave, in
                     for (int kp = 0; kp < SYM; ++kp)
 #pragma unroll
                         for (int c = 0; c < CH; ++c)
-                            acc[(mm + kp) % SYM][c] += wt * s[kp * CH + c];
+                            acc[(mm + kp) % SYM][c] =
+                                fma((A)wt, (A)s[kp * CH + c], acc[(mm + kp) % SYM][c]);
                 };
                 // Candidates in the window come from LDS, in window coordinates (bins
                 // of the window past the detector's ends hold zero records and add
@@ -738,8 +741,11 @@ __device__ inline void gather_orbit_staged_wide(const BpArgs<T>& a, int wave, in
 
 // R^T (+ epilogue).  A workgroup owns an 8x8 block of pixel orbits (the block
 // lies in the first quadrant when SYM = 4) and has VS waves, each summing a
-// disjoint subset of the base views; wave 0 adds the others' sums in order.
-template <typename T, int CH, int SYM, bool QUAD, int EPI, int VS, bool BATCH>
+// disjoint subset of the base views; wave 0 adds the others' sums in order.  A: the
+// type the sums are kept in (T, or double for an FP32 plan's sums in double precision:
+// each product of two FP32 values is exact in double, so only the sums round); the
+// finished values are rounded to T once.
+template <typename T, int CH, int SYM, bool QUAD, int EPI, int VS, bool BATCH, typename A = T>
 __global__ __launch_bounds__(64 * VS) void k_backproject(const BpArgs<T>* __restrict__ dev,
                                                          BpArgs<T> one, unsigned nslices) {
     // The ADMM epilogues (q, dual) run one orbit member per wave; the plain transpose
@@ -751,11 +757,11 @@ __global__ __launch_bounds__(64 * VS) void k_backproject(const BpArgs<T>* __rest
     using St = Staged<T, CH, SYM>;
     __shared__ St s_win[kWide ? VS : 1][kWide ? kWideStride * SYM : 1];
     constexpr int kRed = kFinish ? (kWide ? 1 : VS) : (VS > 1 ? VS - 1 : 1);
-    __shared__ T red_own[kRed][64][SYM * CH];
-    static_assert(!kWide || sizeof(T) * 64 * SYM * CH <= sizeof(St) * kWideStride * SYM,
+    __shared__ A red_own[kRed][64][SYM * CH];
+    static_assert(!kWide || sizeof(A) * 64 * SYM * CH <= sizeof(St) * kWideStride * SYM,
                   "a wave's view sums fit in its staging row");
-    auto red = [&](int w) -> T(*)[SYM * CH] {
-        if constexpr (kFinish && kWide) return reinterpret_cast<T(*)[SYM * CH]>(&s_win[w][0]);
+    auto red = [&](int w) -> A(*)[SYM * CH] {
+        if constexpr (kFinish && kWide) return reinterpret_cast<A(*)[SYM * CH]>(&s_win[w][0]);
         else return red_own[w];
     };
     // The orbit block (bx, by) of this workgroup: its 2-D grid position for one slice;
@@ -782,17 +788,17 @@ __global__ __launch_bounds__(64 * VS) void k_backproject(const BpArgs<T>* __rest
     const int j = by * 8 + (lane >> 3);
     const int dom_x = SYM == 4 ? a.nx / 2 : a.nx, dom_y = SYM == 4 ? a.ny / 2 : a.ny;
     const bool inside = i < dom_x && j < dom_y;
-    T acc[SYM][CH];
+    A acc[SYM][CH];
 #pragma unroll
     for (int k = 0; k < SYM; ++k)
 #pragma unroll
-        for (int c = 0; c < CH; ++c) acc[k][c] = T(0);
+        for (int c = 0; c < CH; ++c) acc[k][c] = A(0);
     if constexpr (kWide)
-        gather_orbit_staged_wide<T, CH, SYM, VS>(a, wave, lane, i, j, bx, by, inside, acc, s_win);
+        gather_orbit_staged_wide<T, A, CH, SYM, VS>(a, wave, lane, i, j, bx, by, inside, acc, s_win);
     else if constexpr (QUAD)
-        gather_orbit_staged<T, CH, SYM, VS>(a, wave, lane, i, j, bx, by, inside, acc);
+        gather_orbit_staged<T, A, CH, SYM, VS>(a, wave, lane, i, j, bx, by, inside, acc);
     else if (inside)
-        gather_orbit<T, CH, SYM, VS>(a, wave, i, j, acc);
+        gather_orbit<T, A, CH, SYM, VS>(a, wave, i, j, acc);
     if constexpr (kFinish) {
         // Every wave's view sums go to LDS; wave w then finishes orbit members w, w + VS,
         // ...: it adds the waves' sums in wave order, runs the epilogue of its member
@@ -800,7 +806,7 @@ __global__ __launch_bounds__(64 * VS) void k_backproject(const BpArgs<T>* __rest
         // in member order.
         __shared__ double wpart[SYM][2];
         {
-            T(*mine)[SYM * CH] = red(wave);
+            A(*mine)[SYM * CH] = red(wave);
 #pragma unroll
             for (int k = 0; k < SYM; ++k)
 #pragma unroll
@@ -808,10 +814,11 @@ __global__ __launch_bounds__(64 * VS) void k_backproject(const BpArgs<T>* __rest
         }
         __syncthreads();
         for (int k = wave; k < SYM; k += VS) {
-            T res[2] = {T(0), T(0)};
+            A sum[2] = {A(0), A(0)};
             for (int w = 0; w < VS; ++w)
 #pragma unroll
-                for (int c = 0; c < 2; ++c) res[c] += red(w)[lane][k * CH + (CH > 1 ? c : 0)];
+                for (int c = 0; c < 2; ++c) sum[c] += red(w)[lane][k * CH + (CH > 1 ? c : 0)];
+            T res[2] = {(T)sum[0], (T)sum[1]};
             double part[2] = {0.0, 0.0};
             if (inside) {
                 int io, jo;
@@ -863,10 +870,10 @@ __global__ __launch_bounds__(64 * VS) void k_backproject(const BpArgs<T>* __rest
                 if constexpr (EPI == EPI_NONE) {
                     vec<T, CH> o;
 #pragma unroll
-                    for (int c = 0; c < CH; ++c) o.v[c] = acc[k][c];
+                    for (int c = 0; c < CH; ++c) o.v[c] = (T)acc[k][c];
                     reinterpret_cast<vec<T, CH>*>(a.out)[(size_t)jo * a.nx + io] = o;
                 } else {
-                    T res[2] = {acc[k][0], acc[k][CH > 1 ? 1 : 0]};
+                    T res[2] = {(T)acc[k][0], (T)acc[k][CH > 1 ? 1 : 0]};
                     epilogue<T, EPI>(a, io, jo, res, part);
                 }
             }
@@ -972,7 +979,7 @@ hipError_t bp_plain(const BpArgs<T>& one, hipStream_t s) {
 }
 
 // The ADMM's own sinograms are two-channel quad records.
-template <typename T, int SYM, bool BATCH, int VS>
+template <typename T, int SYM, bool BATCH, int VS, typename A>
 hipError_t bp_admm_t(int epi, const BpArgs<T>* dev, const BpArgs<T>& one, int n, int gx, int gy,
                      hipStream_t s) {
     // One slice: a (gx, gy) grid.  A batch: each XCD an equal contiguous share of the
@@ -984,12 +991,12 @@ hipError_t bp_admm_t(int epi, const BpArgs<T>* dev, const BpArgs<T>& one, int n,
     const unsigned nsl = (unsigned)n;
     switch (epi) {
         case EPI_Q:
-            hipLaunchKernelGGL((k_backproject<T, 2, SYM, true, EPI_Q, VS, BATCH>), g, blk, 0, s, dev,
-                               one, nsl);
+            hipLaunchKernelGGL((k_backproject<T, 2, SYM, true, EPI_Q, VS, BATCH, A>), g, blk, 0, s,
+                               dev, one, nsl);
             break;
         case EPI_DUAL:
-            hipLaunchKernelGGL((k_backproject<T, 2, SYM, true, EPI_DUAL, VS, BATCH>), g, blk, 0, s,
-                               dev, one, nsl);
+            hipLaunchKernelGGL((k_backproject<T, 2, SYM, true, EPI_DUAL, VS, BATCH, A>), g, blk, 0,
+                               s, dev, one, nsl);
             break;
         default:
             return hipErrorInvalidValue;
@@ -997,22 +1004,22 @@ hipError_t bp_admm_t(int epi, const BpArgs<T>* dev, const BpArgs<T>& one, int n,
     return hipGetLastError();
 }
 
-template <typename T, int SYM, bool BATCH>
+template <typename T, int SYM, bool BATCH, typename A>
 hipError_t bp_admm_w(int waves, int epi, const BpArgs<T>* dev, const BpArgs<T>& one, int n, int gx,
                      int gy, hipStream_t s) {
     switch (waves) {
-        case 2: return bp_admm_t<T, SYM, BATCH, 2>(epi, dev, one, n, gx, gy, s);
-        case 4: return bp_admm_t<T, SYM, BATCH, 4>(epi, dev, one, n, gx, gy, s);
-        case 8: return bp_admm_t<T, SYM, BATCH, 8>(epi, dev, one, n, gx, gy, s);
+        case 2: return bp_admm_t<T, SYM, BATCH, 2, A>(epi, dev, one, n, gx, gy, s);
+        case 4: return bp_admm_t<T, SYM, BATCH, 4, A>(epi, dev, one, n, gx, gy, s);
+        case 8: return bp_admm_t<T, SYM, BATCH, 8, A>(epi, dev, one, n, gx, gy, s);
     }
     return hipErrorInvalidValue;
 }
 
-template <typename T, int SYM>
+template <typename T, int SYM, typename A>
 hipError_t bp_admm(int waves, int epi, const BpArgs<T>* dev, const BpArgs<T>& one, int n, int gx,
                    int gy, hipStream_t s) {
-    return dev ? bp_admm_w<T, SYM, true>(waves, epi, dev, one, n, gx, gy, s)
-               : bp_admm_w<T, SYM, false>(waves, epi, dev, one, n, gx, gy, s);
+    return dev ? bp_admm_w<T, SYM, true, A>(waves, epi, dev, one, n, gx, gy, s)
+               : bp_admm_w<T, SYM, false, A>(waves, epi, dev, one, n, gx, gy, s);
 }
 
 template <typename T, int SYM>
@@ -1133,10 +1140,14 @@ hipError_t launch_backproject(const dect_plan* p, int ch, const BpArgs<T>& a0, h
 
 template <typename T>
 hipError_t launch_backproject_admm(int sym, int waves, int epi, const BpArgs<T>* dev,
-                                   const BpArgs<T>& one, int n, int gx, int gy, hipStream_t s) {
+                                   const BpArgs<T>& one, int n, int gx, int gy, hipStream_t s,
+                                   bool sums64) {
     ProfScope ps(bp_name(epi), s);
-    return sym == 4 ? bp_admm<T, 4>(waves, epi, dev, one, n, gx, gy, s)
-                    : bp_admm<T, 1>(waves, epi, dev, one, n, gx, gy, s);
+    if (sums64)  // an FP64 plan sums in double anyway
+        return sym == 4 ? bp_admm<T, 4, double>(waves, epi, dev, one, n, gx, gy, s)
+                        : bp_admm<T, 1, double>(waves, epi, dev, one, n, gx, gy, s);
+    return sym == 4 ? bp_admm<T, 4, T>(waves, epi, dev, one, n, gx, gy, s)
+                    : bp_admm<T, 1, T>(waves, epi, dev, one, n, gx, gy, s);
 }
 
 #define DECT_INST(T)                                                                          \
@@ -1150,7 +1161,8 @@ hipError_t launch_backproject_admm(int sym, int waves, int epi, const BpArgs<T>*
                                             hipStream_t);                                        \
     template hipError_t launch_backproject<T>(const dect_plan*, int, const BpArgs<T>&, hipStream_t); \
     template hipError_t launch_backproject_admm<T>(int, int, int, const BpArgs<T>*,              \
-                                                   const BpArgs<T>&, int, int, int, hipStream_t);
+                                                   const BpArgs<T>&, int, int, int, hipStream_t, \
+                                                   bool);
 DECT_INST(float)
 DECT_INST(double)
 #undef DECT_INST

@@ -20,6 +20,7 @@ STATUS = {-1: "DECT_E_ARG", -2: "DECT_E_SHAPE", -3: "DECT_E_NOMEM", -4: "DECT_E_
 F32, F64 = 0, 1
 RHO_FIXED, RHO_ADAPTIVE, RHO_SCHEDULE = 0, 1, 2
 PRECOND_NONE, PRECOND_RAMP = 0, 1
+RT_SUMS_PLAN, RT_SUMS_F64 = 0, 1
 
 
 class DectError(RuntimeError):
@@ -50,7 +51,8 @@ class Params(ctypes.Structure):
                 ("rho_mode", ctypes.c_int), ("bal_mu", ctypes.c_double),
                 ("bal_tau", ctypes.c_double), ("lm_mu0", ctypes.c_double),
                 ("rho_schedule", ctypes.POINTER(ctypes.c_double)),
-                ("rho_schedule_len", ctypes.c_int), ("precond", ctypes.c_int)]
+                ("rho_schedule_len", ctypes.c_int), ("precond", ctypes.c_int),
+                ("rt_sums", ctypes.c_int)]
 
 
 class IterLog(ctypes.Structure):
@@ -248,6 +250,7 @@ class AdmmParams:
     lm_mu0: float = 1e-3
     rho_schedule: object = None   # sequence of (rho_c, rho_p) per iteration
     precond: int = PRECOND_NONE    # PRECOND_RAMP: CG preconditioned by the ramp filter
+    rt_sums: int = RT_SUMS_PLAN    # RT_SUMS_F64: an FP32 plan's ADMM transposes sum in double
 
     def c_struct(self):
         P = Params()
@@ -256,6 +259,7 @@ class AdmmParams:
         P.lm_iters, P.cg_iters, P.rho_mode = self.lm_iters, self.cg_iters, self.rho_mode
         P.bal_mu, P.bal_tau, P.lm_mu0 = self.bal_mu, self.bal_tau, self.lm_mu0
         P.precond = int(self.precond)
+        P.rt_sums = int(self.rt_sums)
         keep = None
         if self.rho_schedule is not None:
             flat = [float(v) for pair in self.rho_schedule for v in pair]

@@ -82,9 +82,10 @@ SMALL["sym_fan64_v128"] = S.fan_geometry_fov(64, 128, 93, fov_cm=25.6, src_iso_c
                                              src_det_cm=70.0)
 
 
-@pytest.mark.parametrize("dtype", [F32, F64])
-def test_batch_group_of_different_view_and_bin_counts(dect, dtype):
-    params = dect.AdmmParams(cg_iters=2)
+@pytest.mark.parametrize("dtype,rt_sums", [(F32, 0), (F64, 0), (F32, 1)])
+def test_batch_group_of_different_view_and_bin_counts(dect, dtype, rt_sums):
+    """(rt_sums 1: the FP32 transposes summing in double.)"""
+    params = dect.AdmmParams(cg_iters=2, rt_sums=rt_sums)
     mix = [("sym_fan64_v124", 5), ("sym_fan64_v128", 6), ("sym_fan64_v124", 7)]
     sl = _setup(dect, dtype, params, mix)
     b = dect.Batch([(p, m, bs) for p, m, _, bs in sl], params, graph=True)

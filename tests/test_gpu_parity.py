@@ -297,7 +297,7 @@ SAME_A = 1e-4
 SPLIT_MAX = 1e-3
 
 
-def _fp32_lockstep(dect, pr, n_iters, pcg=False):
+def _fp32_lockstep(dect, pr, n_iters, pcg=False, rt_sums=0):
     """n_iters ADMM iterations of the FP32 library, one call each with its own adaptive rho,
     and of the oracle on the same single-precision inputs replaying, iteration by
     iteration, the library's LM accept decisions and rho choices (pcg: both with the ramp
@@ -311,7 +311,8 @@ def _fp32_lockstep(dect, pr, n_iters, pcg=False):
     ost = orc.admm_init(*meas64, prm)
     plan = dect.Plan(pr.geom, pr.spec, F32)
     meas = [dev(m, F32) for m in meas64]
-    params = dect.AdmmParams(precond=dect.PRECOND_RAMP) if pcg else dect.AdmmParams()
+    params = dect.AdmmParams(precond=dect.PRECOND_RAMP if pcg else dect.PRECOND_NONE,
+                             rt_sums=rt_sums)
     st = plan.new_state()
     plan.admm_init(meas, st, params)
     log, tie = [], 0.0
@@ -420,6 +421,42 @@ def test_admm_pcg_fp32_matches_oracle_after_20_iterations(dect, case):
     # The logged objective follows the oracle's, and the rho sequences are the same.
     _check_objective_log(log, ost.log, rtol_data=1e-3, rtol_tv=1e-3)
     assert [tuple(e["rho"]) for e in log] == [tuple(e["rho"]) for e in ost.log]
+
+
+def test_admm_pcg_fp32_double_sums_match_oracle_after_50_iterations(dect):
+    """UDM1-PCG1 on the FP32 plan with the transposes summing in double precision
+    (dect_rt_sums F64) against the FP64 oracle in lockstep after 50 iterations at 256^2:
+    x_c within 1e-3 and x_p within 5e-3, where single-precision sums drift past 1e-3."""
+    pr = FP32_CASES["fan256"]()
+    print("\n[pcg fp32, double sums] fan256 50 iterations in lockstep", flush=True)
+    ost, st, log, tie = _fp32_lockstep(dect, pr, 50, pcg=True, rt_sums=dect.RT_SUMS_F64)
+    x = host(st.x)
+    ec, ep = rel(x[..., 0], ost.x[0]), rel(x[..., 1], ost.x[1])
+    rtie = max(e.get("rho_tie", 0.0) for e in ost.log)
+    print(f"[pcg fp32, double sums]: x_c {ec:.3e} x_p {ep:.3e}; rho tie {rtie:.3g}", flush=True)
+    assert ec <= 1e-3
+    assert ep <= 5e-3
+    assert rtie <= RHO_TIE_MAX
+    _check_objective_log(log, ost.log, rtol_data=1e-3, rtol_tv=1e-3)
+    assert [tuple(e["rho"]) for e in log] == [tuple(e["rho"]) for e in ost.log]
+
+
+def test_double_sums_leave_fp64_plans_unchanged(dect):
+    """An FP64 plan sums in double either way: the option changes no bit of its state."""
+    pr = S.tiny_problem(0)
+    plan = dect.Plan(pr.geom, pr.spec, F64)
+    meas = [dev(m, F64) for m in _meas(pr)]
+    states = []
+    for sums in (dect.RT_SUMS_PLAN, dect.RT_SUMS_F64):
+        prm = dect.AdmmParams(rt_sums=sums)
+        st = plan.new_state()
+        plan.admm_init(meas, st, prm)
+        plan.admm_iterate(meas, st, prm, 5)
+        states.append(st)
+    torch.cuda.synchronize()
+    assert torch.equal(states[0].buf, states[1].buf)
+    with pytest.raises(dect.DectError):
+        plan.admm_iterate(meas, states[0], dect.AdmmParams(rt_sums=2), 1)
 
 
 def test_checkpoint_resume_and_determinism(dect):
