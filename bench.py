@@ -82,10 +82,13 @@ def binding_unit(kernel: str) -> dict | None:
             rows[parts[0]] = {"valu_busy": float(parts[4]), "ta_busy": float(parts[6])}
     if meta.get("source_hash") != kernel_source_hash():
         return None
-    name = {"project": "k_project", "backproject_q": "k_backproject", "backproject_dual":
-            "k_backproject"}.get(kernel)
+    # The FP32 ADMM instantiations (two channels, quarter-turn symmetry, quad records;
+    # the transposes' q and dual epilogues with single-precision sums).
+    pick = {"project": ("k_project<float,2,4,true,", ">"),
+            "backproject_q": ("k_backproject<float,2,4,true,2,", ",float>"),
+            "backproject_dual": ("k_backproject<float,2,4,true,3,", ",float>")}.get(kernel)
     for k, v in rows.items():
-        if name and k.startswith(name + "<"):
+        if pick and k.startswith(pick[0]) and k.endswith(pick[1]):
             unit = "texture addresser (vector-memory path)" if v["ta_busy"] >= v["valu_busy"] \
                 else "VALU issue"
             return {**v, "busiest": unit, "source": os.path.relpath(COUNTERS_FILE, ROOT)}
