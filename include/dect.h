@@ -293,7 +293,10 @@ dect_status dect_admm_init(const dect_plan* plan, const void* m_h, const void* m
  * records or NULL; with a log the call synchronises the stream and returns
  * DECT_E_NONFINITE if any record has the non-finite flag.  Without a log the
  * call is async.  A DECT_RHO_SCHEDULE run must cover every iteration index it
- * reaches (DECT_E_ARG otherwise). */
+ * reaches (DECT_E_ARG otherwise).  Within a call the rescale of the scaled duals
+ * after a change of rho is applied by their next readers; the call ends by applying
+ * what is still pending, so between calls the state's u^a, u^y, u^z hold the scaled
+ * duals of Eq. (11). */
 dect_status dect_admm_iterate(const dect_plan* plan, const void* m_h, const void* m_l,
                               const void* w_h, const void* w_l, void* state,
                               const dect_params* params, int n_iters, dect_iter_log* log,
@@ -409,7 +412,8 @@ dect_status dect_batch_create(int n, const dect_plan* const* plans, const void* 
                               const dect_params* params, int use_graph, dect_batch** out);
 /* n_iters outer iterations of every slice, enqueued on stream.  async.  While
  * per-kernel timing is on (dect_profile_start) the kernels are launched
- * directly instead of through the graph. */
+ * directly instead of through the graph.  As dect_admm_iterate, the call ends with
+ * every slice's duals rescaled for the last change of rho. */
 dect_status dect_batch_iterate(dect_batch* batch, int n_iters, void* stream);
 /* Number of shape groups (launches per kernel per iteration). */
 int dect_batch_groups(const dect_batch* batch);
