@@ -326,8 +326,8 @@ struct TvArgs {
     T* dz;
     const double* scal;
     double* partials;
-    // The pending last CG step (x + alpha p, alpha = scal[S_ALPHA]), which the rescale
-    // kernel stores at the end of the iteration: the TV update reads x through it.
+    // The pending last CG step (x + alpha p, alpha = scal[S_ALPHA]), which the dual
+    // transpose's epilogue stores after this launch: the TV update reads x through it.
     // step_p == nullptr: none (x is current).
     const T* step_p;
 };

@@ -38,7 +38,7 @@ __device__ inline void tv_dual_block(const TvArgs<T>& A, long blk) {
         const V2* x2 = reinterpret_cast<const V2*>(x);
         const V2* p2 = reinterpret_cast<const V2*>(A.step_p);
         // x after the iteration's last CG step, x + alpha p, when that step is still
-        // pending (the rescale kernel stores it with the same fma).
+        // pending (the dual transpose's epilogue stores it with the same fma).
         const T al[2] = {(T)scal[S_ALPHA], (T)scal[S_ALPHA + 1]};
         auto xat = [&](long q) {
             V2 v = x2[q];
