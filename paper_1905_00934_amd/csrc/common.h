@@ -107,6 +107,18 @@ struct dect_plan {
     void* bp_rays = nullptr;  // BpRay<T>[Vb * D]: the transpose's form of the rays
     void* spec = nullptr;   // T[6 * Kmax]: lw_h, kc_h, kp_h, lw_l, kc_l, kp_l
     int kh = 0, kl = 0, kmax = 0;
+    // Both spectra on one energy grid, for evaluating them with one exponential per
+    // energy: T[nj][8] = kc, kp, w_h, w_h kc, w_h kp, w_l, w_l kc, w_l kp (w: normalised
+    // weight, linear; kc, kp: f_KN, f_p times log2(e)) over the bins where both spectra
+    // are nonzero (jb of them), then where only the high one is (jh), then only the low
+    // one (jl).  joint_lim: the largest log2 distance from the shift to a spectrum's
+    // log-sum-exp for which no A_k overflows, 124 + log2 of the smallest weight (0: the
+    // joint evaluation is not used).  joint_kc, joint_kp: smallest and largest f_KN, f_p
+    // times log2(e) over the bins (they bound how far a step moves any exponent).
+    void* joint = nullptr;
+    int jb = 0, jh = 0, jl = 0;
+    double joint_lim = 0.0;
+    double joint_kc[2] = {0.0, 0.0}, joint_kp[2] = {0.0, 0.0};
     double kc_max = 0.0, kp_max = 0.0;  // largest f_KN, f_p times log2(e) over used bins
     double mean_f[2][2];    // spectrum-mean (f_KN, f_p) per spectrum (h, l)
     // plan-owned scratch: orbit images of the image being projected (up to 4 channels)

@@ -337,6 +337,10 @@ struct UdmArgs {
     const T* spec;     // spectral tables (plan)
     int kmax, kh, kl;
     float kc_max, kp_max;
+    const T* joint;    // both spectra on one energy grid (plan; see dect_plan::joint)
+    int jb, jh, jl;
+    float joint_lim;
+    float jkc[2], jkp[2];  // smallest and largest kc, kp of the joint table
     long M;
     int sym, Vb, D;  // internal (quad) ray order of t, da, Rp; sym = 1: standard order
     const T* mh;

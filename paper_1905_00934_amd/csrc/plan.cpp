@@ -143,6 +143,56 @@ dect_status build_tables(dect_plan* p, const dect_spectra* spec) {
                 packed[(size_t)(3 * h + q) * p->kmax + k] = tab[h][q][k];
     st = upload<T>(packed.data(), packed.size() * sizeof(T), &p->spec);
     if (st) return st;
+    {
+        // The joint table: bins where both spectra are nonzero, then high only, then low
+        // only, each in energy order.
+        double tot[2] = {0.0, 0.0};
+        for (int h = 0; h < 2; ++h)
+            for (int k = 0; k < spec->n_bins; ++k) tot[h] += S[h][k];
+        std::vector<int> order[3];
+        for (int k = 0; k < spec->n_bins; ++k) {
+            const bool on_h = S[0][k] > 0.0, on_l = S[1][k] > 0.0;
+            if (on_h && on_l) order[0].push_back(k);
+            else if (on_h) order[1].push_back(k);
+            else if (on_l) order[2].push_back(k);
+        }
+        p->jb = (int)order[0].size();
+        p->jh = (int)order[1].size();
+        p->jl = (int)order[2].size();
+        const int nj = p->jb + p->jh + p->jl;
+        std::vector<T> joint((size_t)8 * (nj > 0 ? nj : 1), (T)0);
+        double wmin = 1.0;
+        int j = 0;
+        for (int r = 0; r < 3; ++r)
+            for (int k : order[r]) {
+                const double kc = spec->f_kn[k] * log2e, kp = spec->f_p[k] * log2e;
+                const double wh = S[0][k] / tot[0], wl = S[1][k] / tot[1];
+                if (S[0][k] > 0.0) wmin = std::fmin(wmin, wh);
+                if (S[1][k] > 0.0) wmin = std::fmin(wmin, wl);
+                const double v[8] = {kc, kp, wh, wh * kc, wh * kp, wl, wl * kc, wl * kp};
+                for (int q = 0; q < 8; ++q) joint[(size_t)j * 8 + q] = (T)v[q];
+                ++j;
+            }
+        // Every A_k is at most 2^(L - s) / w_k, L the log-sum-exp of a spectrum the bin
+        // belongs to: L - s <= 124 + log2 wmin keeps it below 2^124.  The joint evaluation
+        // is used when that leaves at least 100 (every weight at least 2^-24).
+        const double lim = 124.0 + std::log2(wmin);
+        p->joint_lim = nj > 0 && lim >= 100.0 ? lim : 0.0;
+        double kcr[2] = {INFINITY, -INFINITY}, kpr[2] = {INFINITY, -INFINITY};
+        for (int q = 0; q < nj; ++q) {
+            kcr[0] = std::fmin(kcr[0], (double)joint[(size_t)q * 8]);
+            kcr[1] = std::fmax(kcr[1], (double)joint[(size_t)q * 8]);
+            kpr[0] = std::fmin(kpr[0], (double)joint[(size_t)q * 8 + 1]);
+            kpr[1] = std::fmax(kpr[1], (double)joint[(size_t)q * 8 + 1]);
+        }
+        if (nj > 0)
+            for (int e = 0; e < 2; ++e) {
+                p->joint_kc[e] = kcr[e];
+                p->joint_kp[e] = kpr[e];
+            }
+        st = upload<T>(joint.data(), joint.size() * sizeof(T), &p->joint);
+        if (st) return st;
+    }
     DECT_HIP(hipMalloc(&p->scratch_O, (size_t)p->N * 4 * p->sym * sizeof(T)));
     DECT_HIP(hipMalloc(&p->scratch_OT, (size_t)p->N * 4 * p->sym * sizeof(T)));
     if (p->sym == 4) DECT_HIP(hipMalloc(&p->scratch_sq, (size_t)p->M * 2 * sizeof(T)));
@@ -426,6 +476,7 @@ void dect_plan_destroy(dect_plan* p) {
     (void)hipFree(p->views);
     (void)hipFree(p->bp_rays);
     (void)hipFree(p->spec);
+    (void)hipFree(p->joint);
     (void)hipFree(p->scratch_O);
     (void)hipFree(p->scratch_OT);
     (void)hipFree(p->scratch_sq);

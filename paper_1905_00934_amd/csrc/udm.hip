@@ -14,6 +14,11 @@
 #include "profile.h"
 #include "tv.h"
 
+// No contraction into fused multiply-adds beyond the fma() calls written out: the
+// compiler could fuse a sum of products differently in different instantiations of a
+// kernel, and the batched and single-slice a-updates must agree bit for bit.
+#pragma clang fp contract(off)
+
 namespace dect {
 
 namespace {
@@ -52,15 +57,15 @@ __device__ inline void spectrum_eval(const T* __restrict__ lw_, const T* __restr
     if (exact) {
         m = -INFINITY;
 #pragma unroll 8
-        for (int k = 0; k < n; ++k) m = fmax(m, lw[k] - kc[k] * ac - kp[k] * ap);
+        for (int k = 0; k < n; ++k) m = fmax(m, fma(-kp[k], ap, fma(-kc[k], ac, lw[k])));
     }
     T z = T(0), sc = T(0), sp = T(0);
 #pragma unroll 8
     for (int k = 0; k < n; ++k) {
-        const T q = Cst<T>::exp2((lw[k] - m) - kc[k] * ac - kp[k] * ap);
+        const T q = Cst<T>::exp2(fma(-kp[k], ap, fma(-kc[k], ac, lw[k] - m)));
         z += q;
-        sc += q * kc[k];
-        sp += q * kp[k];
+        sc = fma(q, kc[k], sc);
+        sp = fma(q, kp[k], sp);
     }
     f = -(m + Cst<T>::log2(z)) * ln2;
     // sum_k q_k f_KN[k] / z = ln2 * sum_k q_k kc[k] / z, since kc = f_KN / ln2.
@@ -73,6 +78,86 @@ template <typename T>
 struct Point {
     T ac, ap, fh, fl, ghc, ghp, glc, glp, phi;
 };
+
+// Both spectra on one energy grid (the plan's joint table, [jb + jh + jl][8]).
+template <typename T>
+struct JointTab {
+    const T* tab;
+    int jb, jh, jl;
+    float lim;       // largest log2 distance from the shift to a log-sum-exp (0: never)
+    float kc0, kc1;  // smallest and largest kc of the table
+    float kp0, kp1;  // smallest and largest kp
+};
+
+// f and gradient of both spectra at (ac, ap) with one exponential per energy bin:
+// A_k = 2^(-kc_k ac - kp_k ap - s) is shared by the spectra, which differ only in their
+// weights, so f_s = -ln2 (s + log2 sum_k w_sk A_k) and grad f_s = ln2 sum_k w_sk A_k
+// (kc_k, kp_k) / sum_k w_sk A_k, with the products w_sk kc_k, w_sk kp_k from the table
+// (one record of 8 values per bin, read with one scalar load).  Returns whether the shift
+// s kept the evaluation in range: every sum finite (no A_k overflowed) and both
+// normalising sums at least 2^-90, so that terms lost below 2^-126 are below 2^-36 of
+// their sum.
+template <typename T, int U = 4>
+__device__ inline bool spectra_eval_joint(const JointTab<T>& J, T ac, T ap, T s, T& fh, T& ghc,
+                                          T& ghp, T& fl, T& glc, T& glp) {
+    using CT = const __attribute__((address_space(4))) T;
+    CT* rec = (CT*)J.tab;
+    const int nj = J.jb + J.jh + J.jl;
+    constexpr T ln2 = T(0.6931471805599453);
+    const T ns = -s;
+    T zh = T(0), ah = T(0), bh = T(0), zl = T(0), al = T(0), bl = T(0);
+    int k = 0;
+#pragma unroll U
+    for (; k < J.jb; ++k) {
+        CT* r = rec + 8 * k;
+        const T A = Cst<T>::exp2(fma(-r[1], ap, fma(-r[0], ac, ns)));
+        zh = fma(r[2], A, zh);
+        ah = fma(r[3], A, ah);
+        bh = fma(r[4], A, bh);
+        zl = fma(r[5], A, zl);
+        al = fma(r[6], A, al);
+        bl = fma(r[7], A, bl);
+    }
+#pragma unroll 2
+    for (; k < J.jb + J.jh; ++k) {
+        CT* r = rec + 8 * k;
+        const T A = Cst<T>::exp2(fma(-r[1], ap, fma(-r[0], ac, ns)));
+        zh = fma(r[2], A, zh);
+        ah = fma(r[3], A, ah);
+        bh = fma(r[4], A, bh);
+    }
+#pragma unroll 2
+    for (; k < nj; ++k) {
+        CT* r = rec + 8 * k;
+        const T A = Cst<T>::exp2(fma(-r[1], ap, fma(-r[0], ac, ns)));
+        zl = fma(r[5], A, zl);
+        al = fma(r[6], A, al);
+        bl = fma(r[7], A, bl);
+    }
+    fh = -(s + Cst<T>::log2(zh)) * ln2;
+    fl = -(s + Cst<T>::log2(zl)) * ln2;
+    const T ih = ln2 / zh, il = ln2 / zl;
+    ghc = ah * ih;
+    ghp = bh * ih;
+    glc = al * il;
+    glp = bl * il;
+    constexpr T tiny = T(8.077935669463161e-28);  // 2^-90
+    return zh >= tiny && zl >= tiny && isfinite(((zh + zl) + (ah + bh)) + (al + bl));
+}
+
+// The largest exponent log2 w_k - kc_k ac - kp_k ap of one spectrum.
+template <typename T>
+__device__ inline T spectrum_max(const T* __restrict__ lw_, const T* __restrict__ kc_,
+                                 const T* __restrict__ kp_, int n, T ac, T ap) {
+    using CT = const __attribute__((address_space(4))) T;
+    CT* lw = (CT*)lw_;
+    CT* kc = (CT*)kc_;
+    CT* kp = (CT*)kp_;
+    T m = -INFINITY;
+#pragma unroll 4
+    for (int k = 0; k < n; ++k) m = fmax(m, fma(-kp[k], ap, fma(-kc[k], ac, lw[k])));
+    return m;
+}
 
 // Largest |kc| and |kp| over both spectra (bounds the exponent change of a step).
 struct StepBound {
@@ -106,15 +191,24 @@ __device__ inline T det2(T a, T d, T b, T c) {
 // B = kcmax |d_c| + kpmax |d_p|, so for B <= 96 nothing overflows and the largest
 // term stays above 2^-(96 + log2 K).  Larger steps take the two-pass form.
 //
+// JT (the plan has a joint table): every trial point is evaluated with the joint table
+// (spectra_eval_joint), first for both spectra with one shift placed between bounds of
+// their log-sum-exps at the trial point.  A ray for which that shift left the range (a
+// step across which the bounds are too far apart, a non-finite current point) evaluates
+// each spectrum again with its own shift, its largest exponent at the trial point, which
+// bounds every A_k by 2^8 over the smallest weight.  Without a joint table (a weight
+// below 2^-24 of its spectrum) the spectra are evaluated apart.
+//
 // CONSTR (the constrained decomposition, a >= 0): a coordinate at zero whose
 // gradient is positive is held at zero and the damped step is taken in the other
 // coordinate alone; trial points are projected onto a >= 0.
 //
 // accepted: bit k set when LM iteration k (k < 32) accepted its trial point.
-template <typename T, bool CONSTR = false>
-__device__ inline void lm_solve(const T* __restrict__ spec, int kmax, int kh, int kl, T mh, T ml,
-                                T wh, T wl, T vc, T vp, T rc, T rp, int iters, T mu,
-                                StepBound sb, Point<T>& P, unsigned& accepted) {
+template <typename T, bool CONSTR, bool JT>
+__device__ inline void lm_solve(const T* __restrict__ spec, int kmax, int kh, int kl,
+                                const JointTab<T>& jt, T mh, T ml, T wh, T wl, T vc, T vp,
+                                T rc, T rp, int iters, T mu, StepBound sb, Point<T>& P,
+                                unsigned& accepted) {
     constexpr T log2e = T(1.4426950408889634);
     accepted = 0u;
     for (int it = 0; it < iters; ++it) {
@@ -166,9 +260,36 @@ __device__ inline void lm_solve(const T* __restrict__ spec, int kmax, int kh, in
         }
         const T bound = (T)sb.kcmax * fabs(dc) + (T)sb.kpmax * fabs(dp);
         // A non-finite current value gives no usable shift either.
-        const bool exact = !(bound <= T(96)) || !isfinite(P.fh) || !isfinite(P.fl);
-        evaluate<T>(spec, kmax, kh, kl, mh, ml, wh, wl, vc, vp, rc, rp, -P.fh * log2e,
-                    -P.fl * log2e, exact, Q);
+        const bool finite = isfinite(P.fh) && isfinite(P.fl);
+        const T sh = -P.fh * log2e, sl = -P.fl * log2e;
+        if constexpr (JT) {
+            // Each spectrum's log-sum-exp at Q lies between its first-order prediction
+            // from P (the log-sum-exp is convex in a) and its value at P plus the largest
+            // change of any exponent.  The shift, halfway between the predictions, is
+            // moved so that the highest bound is at most lim above it and the lowest at
+            // most 90 below it; both hold when the bounds are within lim + 90.
+            const T up = (dc >= T(0) ? -(T)jt.kc0 * dc : -(T)jt.kc1 * dc) +
+                         (dp >= T(0) ? -(T)jt.kp0 * dp : -(T)jt.kp1 * dp);
+            const T lh = -(P.fh + P.ghc * dc + P.ghp * dp) * log2e;
+            const T ll = -(P.fl + P.glc * dc + P.glp * dp) * log2e;
+            const T s = fmin(fmax(T(0.5) * (lh + ll), fmax(sh, sl) + up - (T)jt.lim),
+                             fmin(lh, ll) + T(90));
+            const bool ok =
+                spectra_eval_joint<T>(jt, Q.ac, Q.ap, s, Q.fh, Q.ghc, Q.ghp, Q.fl, Q.glc, Q.glp);
+            if (!ok) {
+                const T s_h = spectrum_max<T>(spec, spec + kmax, spec + 2 * kmax, kh, Q.ac, Q.ap);
+                const T s_l = spectrum_max<T>(spec + 3 * kmax, spec + 4 * kmax, spec + 5 * kmax,
+                                              kl, Q.ac, Q.ap);
+                T u0, u1, u2;  // the other spectrum's values at each shift are not used
+                (void)spectra_eval_joint<T>(jt, Q.ac, Q.ap, s_h, Q.fh, Q.ghc, Q.ghp, u0, u1, u2);
+                (void)spectra_eval_joint<T>(jt, Q.ac, Q.ap, s_l, u0, u1, u2, Q.fl, Q.glc, Q.glp);
+            }
+            const T rh = Q.fh - mh, rl = Q.fl - ml, ec = Q.ac - vc, ep = Q.ap - vp;
+            Q.phi = T(0.5) * (wh * rh * rh + wl * rl * rl) + T(0.5) * (rc * ec * ec + rp * ep * ep);
+        } else {
+            const bool exact = !(bound <= T(96)) || !finite;
+            evaluate<T>(spec, kmax, kh, kl, mh, ml, wh, wl, vc, vp, rc, rp, sh, sl, exact, Q);
+        }
         if (Q.phi < P.phi) {
             P = Q;
             mu *= T(0.1);
@@ -179,7 +300,8 @@ __device__ inline void lm_solve(const T* __restrict__ spec, int kmax, int kh, in
     }
 }
 
-template <typename T, int MODE, bool BATCH>
+// JT: the plan has a joint table (joint_lim > 0); see lm_solve.
+template <typename T, int MODE, bool BATCH, bool JT>
 __global__ __launch_bounds__(256) void k_udm(const UdmArgs<T>* __restrict__ dev, UdmArgs<T> one) {
     using V2 = vec<T, 2>;
     using V4 = vec<T, 4>;
@@ -260,7 +382,9 @@ __global__ __launch_bounds__(256) void k_udm(const UdmArgs<T>* __restrict__ dev,
             evaluate<T>(spec, kmax, kh, kl, mh, ml, wh, wl, vc, vp, rc, rp, T(0), T(0), true, P);
         }
         unsigned accepted;
-        lm_solve<T, MODE == 3>(spec, kmax, kh, kl, mh, ml, wh, wl, vc, vp, rc, rp, A.iters,
+        const JointTab<T> jt{A.joint,  A.jb,      A.jh,      A.jl,     A.joint_lim,
+                             A.jkc[0], A.jkc[1], A.jkp[0], A.jkp[1]};
+        lm_solve<T, MODE == 3, JT>(spec, kmax, kh, kl, jt, mh, ml, wh, wl, vc, vp, rc, rp, A.iters,
                                (T)A.mu0, sb, P, accepted);
         if constexpr (MODE == 2) {
             if (A.lmbits) A.lmbits[i] = (uint8_t)(accepted & 0xffu);
@@ -362,6 +486,15 @@ void fill_udm_tables(const dect_plan* p, UdmArgs<T>& a) {
     a.kl = p->kl;
     a.kc_max = (float)p->kc_max;
     a.kp_max = (float)p->kp_max;
+    a.joint = static_cast<const T*>(p->joint);
+    a.jb = p->jb;
+    a.jh = p->jh;
+    a.jl = p->jl;
+    a.joint_lim = (float)p->joint_lim;
+    for (int e = 0; e < 2; ++e) {
+        a.jkc[e] = (float)p->joint_kc[e];
+        a.jkp[e] = (float)p->joint_kp[e];
+    }
 }
 
 template <typename T>
@@ -372,21 +505,31 @@ hipError_t launch_udm(const dect_plan* p, int mode, const UdmArgs<T>& a0, hipStr
     const long tvb = mode == 2 && a.tv.x ? ((long)a.tv.nx * a.tv.ny + 255) / 256 : 0;
     dim3 g((unsigned)(a.udm_blocks + tvb));
     ProfScope ps(mode == 1 ? "udm_init" : (mode == 3 ? "cdm" : "udm"), s);
-    if (mode == 0)
-        hipLaunchKernelGGL((k_udm<T, 0, false>), g, dim3(256), 0, s, nullptr, a);
+    // The ADMM a-update (mode 2) evaluates the spectra apart: its rays that leave the
+    // joint evaluation's range are few but spread over enough waves to hold up the launch.
+    const bool jt = a.joint_lim > 0.0f;
+    if (mode == 0 && jt)
+        hipLaunchKernelGGL((k_udm<T, 0, false, true>), g, dim3(256), 0, s, nullptr, a);
+    else if (mode == 0)
+        hipLaunchKernelGGL((k_udm<T, 0, false, false>), g, dim3(256), 0, s, nullptr, a);
+    else if (mode == 3 && jt)
+        hipLaunchKernelGGL((k_udm<T, 3, false, true>), g, dim3(256), 0, s, nullptr, a);
     else if (mode == 3)
-        hipLaunchKernelGGL((k_udm<T, 3, false>), g, dim3(256), 0, s, nullptr, a);
+        hipLaunchKernelGGL((k_udm<T, 3, false, false>), g, dim3(256), 0, s, nullptr, a);
+    else if (mode == 1 && jt)
+        hipLaunchKernelGGL((k_udm<T, 1, false, true>), g, dim3(256), 0, s, nullptr, a);
     else if (mode == 1)
-        hipLaunchKernelGGL((k_udm<T, 1, false>), g, dim3(256), 0, s, nullptr, a);
+        hipLaunchKernelGGL((k_udm<T, 1, false, false>), g, dim3(256), 0, s, nullptr, a);
     else
-        hipLaunchKernelGGL((k_udm<T, 2, false>), g, dim3(256), 0, s, nullptr, a);
+        hipLaunchKernelGGL((k_udm<T, 2, false, false>), g, dim3(256), 0, s, nullptr, a);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_udm_batch(const UdmArgs<T>* args, int n, int blocks, hipStream_t s) {
     ProfScope ps("udm", s);
-    hipLaunchKernelGGL((k_udm<T, 2, true>), dim3(blocks, 1, n), dim3(256), 0, s, args, UdmArgs<T>{});
+    hipLaunchKernelGGL((k_udm<T, 2, true, false>), dim3(blocks, 1, n), dim3(256), 0, s, args,
+                       UdmArgs<T>{});
     return hipGetLastError();
 }
 

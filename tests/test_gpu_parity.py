@@ -146,6 +146,74 @@ def test_decompose_fp64_matches_oracle(dect, iters):
     assert rel(got[..., 1], wp) <= 1e-10
 
 
+def _wide_rays(orc, spec, n_views, n_det, seed):
+    """Rays from air to metal: view row r holds line integrals up to (1000, 300) r / V,
+    so whole 64-ray waves lie on either side of the distance in log-sum-exp at which the
+    two spectra stop sharing one shift; noisy measurements, unit weights."""
+    rng = np.random.default_rng(seed)
+    t = (np.arange(n_views)[:, None] + rng.uniform(0, 1, (n_views, n_det))) / n_views
+    ac = 1000.0 * t
+    ap = 300.0 * t * rng.uniform(0.2, 1.0, t.shape)
+    fh, fl, _, _ = orc.forward(ac, ap)
+    mh = fh + rng.normal(0, 0.05, t.shape)
+    ml = fl + rng.normal(0, 0.05, t.shape)
+    return ac, ap, mh, ml
+
+
+def _has_joint_table(spec):
+    """Whether the plan evaluates the spectra together: every normalised weight is at least
+    2^-24, so that with the shift at a spectrum's largest exponent no A_k overflows."""
+    w = [s / s.sum() for s in (spec.s_high, spec.s_low)]
+    return min(v[v > 0].min() for v in w) >= 2.0 ** -24
+
+
+def _decompose_case(dect, spec, seed):
+    g = S.geometry("parallel", 4, 4, 1.0, 16, 64, 1.0)
+    orc = O.Oracle(g, spec)
+    ac, ap, mh, ml = _wide_rays(orc, spec, 16, 64, seed)
+    wh = np.ones_like(mh)
+    wl = np.ones_like(ml)
+    rng = np.random.default_rng(seed + 1)
+    vc = ac + rng.normal(0, 0.5, ac.shape)
+    vp = ap + rng.normal(0, 0.5, ap.shape)
+    ac0, ap0 = orc.linearised(mh, ml)
+    rho = (1e-3, 3e-3)
+    want = orc.udm(mh, ml, wh, wl, vc, vp, rho[0], rho[1], 3, ac0, ap0)
+    plan = dect.Plan(g, spec, F64)
+    a = dev(np.stack([ac0, ap0], -1), F64)
+    plan.decompose_rays(*(dev(m, F64) for m in (mh, ml, wh, wl)), a,
+                        dev(np.stack([vc, vp], -1), F64), rho, 3)
+    got = host(a)
+    assert np.isfinite(got).all()
+    assert rel(got[..., 0], want[0]) <= 1e-10
+    assert rel(got[..., 1], want[1]) <= 1e-10
+    return orc, want
+
+
+def test_decompose_fp64_air_to_metal(dect):
+    """Rays from air to metal: the two spectra's log-sum-exps lie up to ~175 (base 2)
+    apart, and the first LM steps from the linearised start are long.  The shared shift
+    of the joint evaluation and its per-spectrum fallback give the oracle's results."""
+    spec = S.default_spectra()
+    assert _has_joint_table(spec)
+    orc, want = _decompose_case(dect, spec, 11)
+    fh, fl, _, _ = orc.forward(want[0], want[1])
+    assert (np.abs(fh - fl) / np.log(2)).max() > 100
+
+
+def test_decompose_fp64_without_joint_table(dect):
+    """A spectrum with a bin weighted below 2^-24 of its total leaves the plan without
+    the joint evaluation (its inverse weight would take A_k out of range); the spectra
+    are then evaluated apart, with the same results as the oracle."""
+    base = S.default_spectra()
+    s_high = base.s_high.copy()
+    k = int(np.flatnonzero(s_high > 0)[-1])
+    s_high[k] = 1e-40 * s_high.sum()
+    spec = S.Spectra(base.energy_kev, s_high, base.s_low, base.f_kn, base.f_p)
+    assert not _has_joint_table(spec)
+    _decompose_case(dect, spec, 12)
+
+
 def test_decompose_fp32_full_size(dect, slice512):
     pr = slice512
     orc = O.Oracle(pr.geom, pr.spec)
