@@ -409,7 +409,8 @@ hipError_t iteration_t(const SliceJob<T>& J, const JobArrays<T>* dev, int nsl,
     }
     // The a-update (Eq. (13)) and, in the same launch, the TV/z/dual update.
     if (dev)
-        DECT_TRY(launch_udm_batch<T>(dev->udm, nsl, (int)(nblk(J.M) + nblk(J.N)), s));
+        DECT_TRY(launch_udm_batch<T>(dev->udm, nsl, (int)(nblk(J.M) + nblk(J.N)),
+                                      J.udm.joint_lim > 0.0f, s));
     else
         DECT_TRY(launch_udm<T>(nullptr, 2, J.udm, s));
     // R^T da: the dual residual (adaptive rho) and the tracked h in every mode.

@@ -24,7 +24,8 @@ bool same_shape(const SliceJob<T>& a, const SliceJob<T>& b) {
            a.prj.nx == b.prj.nx && a.prj.ny == b.prj.ny && a.cg_iters == b.cg_iters &&
            a.rho_mode == b.rho_mode && a.bp_waves == b.bp_waves && a.pj_waves == b.pj_waves &&
            a.pj_views == b.pj_views && a.pj_chunk == b.pj_chunk &&
-           a.precond == b.precond && a.rt_sums64 == b.rt_sums64;
+           a.precond == b.precond && a.rt_sums64 == b.rt_sums64 &&
+           (a.udm.joint_lim > 0.0f) == (b.udm.joint_lim > 0.0f);
 }
 
 // Byte offsets of the ten argument arrays of a group of n slices.

@@ -375,9 +375,10 @@ void fill_udm_tables(const dect_plan* p, UdmArgs<T>& a);
 // p: plan whose spectral tables are filled into a (nullptr: a carries them).
 template <typename T>
 hipError_t launch_udm(const dect_plan* p, int mode, const UdmArgs<T>& a, hipStream_t s);
-// Batched a-step over n slices (args: device array), grid of `blocks` x n.
+// Batched a-step over n slices (args: device array), grid of `blocks` x n; joint: every
+// slice's plan has a joint spectral table (joint_lim > 0).
 template <typename T>
-hipError_t launch_udm_batch(const UdmArgs<T>* args, int n, int blocks, hipStream_t s);
+hipError_t launch_udm_batch(const UdmArgs<T>* args, int n, int blocks, bool joint, hipStream_t s);
 // Preconditioner z = M r of the x-update (ramp filter by 2-D FFT, both bases as one
 // complex image); partials: r . z per basis, one block per image row.
 template <typename T>

@@ -145,18 +145,52 @@ __device__ inline bool spectra_eval_joint(const JointTab<T>& J, T ac, T ap, T s,
     return zh >= tiny && zl >= tiny && isfinite(((zh + zl) + (ah + bh)) + (al + bl));
 }
 
-// The largest exponent log2 w_k - kc_k ac - kp_k ap of one spectrum.
+// Sum and maximum over the 64 lanes of a wave, in a fixed butterfly order that gives every
+// lane the same bits; every lane of the wave must be active.
 template <typename T>
-__device__ inline T spectrum_max(const T* __restrict__ lw_, const T* __restrict__ kc_,
-                                 const T* __restrict__ kp_, int n, T ac, T ap) {
-    using CT = const __attribute__((address_space(4))) T;
-    CT* lw = (CT*)lw_;
-    CT* kc = (CT*)kc_;
-    CT* kp = (CT*)kp_;
+__device__ inline T wave_sum(T v) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+template <typename T>
+__device__ inline T wave_max(T v) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// f and gradient of one spectrum at the wave-uniform point (ac, ap), its bins spread over
+// the lanes of the wave (lane t takes bins t, t + 64, ...), with the largest exponent as
+// the shift: the exact form of spectrum_eval for one ray, at a wave's cost of a few bins.
+// Every lane of the wave must be active; every lane returns the same values.
+template <typename T>
+__device__ inline void wave_spectrum_eval(const T* __restrict__ lw, const T* __restrict__ kc,
+                                          const T* __restrict__ kp, int n, T ac, T ap, T& f,
+                                          T& gc, T& gp) {
+    constexpr T ln2 = T(0.6931471805599453);
+    const int t = (int)(threadIdx.x & 63u);
+    __builtin_amdgcn_sched_barrier(0);
     T m = -INFINITY;
-#pragma unroll 4
-    for (int k = 0; k < n; ++k) m = fmax(m, fma(-kp[k], ap, fma(-kc[k], ac, lw[k])));
-    return m;
+#pragma unroll 1
+    for (int k = t; k < n; k += 64) m = fmax(m, fma(-kp[k], ap, fma(-kc[k], ac, lw[k])));
+    m = wave_max<T>(m);
+    T z = T(0), sc = T(0), sp = T(0);
+#pragma unroll 1
+    for (int k = t; k < n; k += 64) {
+        const T q = Cst<T>::exp2(fma(-kp[k], ap, fma(-kc[k], ac, lw[k] - m)));
+        z += q;
+        sc = fma(q, kc[k], sc);
+        sp = fma(q, kp[k], sp);
+    }
+    z = wave_sum<T>(z);
+    sc = wave_sum<T>(sc);
+    sp = wave_sum<T>(sp);
+    f = -(m + Cst<T>::log2(z)) * ln2;
+    const T iz = ln2 / z;
+    gc = sc * iz;
+    gp = sp * iz;
+    __builtin_amdgcn_sched_barrier(0);
 }
 
 // Largest |kc| and |kp| over both spectra (bounds the exponent change of a step).
@@ -192,12 +226,12 @@ __device__ inline T det2(T a, T d, T b, T c) {
 // term stays above 2^-(96 + log2 K).  Larger steps take the two-pass form.
 //
 // JT (the plan has a joint table): every trial point is evaluated with the joint table
-// (spectra_eval_joint), first for both spectra with one shift placed between bounds of
-// their log-sum-exps at the trial point.  A ray for which that shift left the range (a
-// step across which the bounds are too far apart, a non-finite current point) evaluates
-// each spectrum again with its own shift, its largest exponent at the trial point, which
-// bounds every A_k by 2^8 over the smallest weight.  Without a joint table (a weight
-// below 2^-24 of its spectrum) the spectra are evaluated apart.
+// (spectra_eval_joint) for both spectra with one shift placed between bounds of their
+// log-sum-exps at the trial point.  A ray for which that shift left the range (a step
+// across which the bounds are too far apart, a non-finite current point) is evaluated
+// again exactly, by the whole wave (wave_spectrum_eval); every lane of the wave must call
+// lm_solve together.  Without a joint table (a weight below 2^-24 of its spectrum) the
+// spectra are evaluated apart.
 //
 // CONSTR (the constrained decomposition, a >= 0): a coordinate at zero whose
 // gradient is positive is held at zero and the damped step is taken in the other
@@ -211,6 +245,9 @@ __device__ inline void lm_solve(const T* __restrict__ spec, int kmax, int kh, in
                                 unsigned& accepted) {
     constexpr T log2e = T(1.4426950408889634);
     accepted = 0u;
+    // The iterations are predicated rather than left early, so that all lanes of a wave
+    // reach the spectra evaluation together (the joint path's fallback is wave-wide).
+    bool stop = false;  // CONSTR: stationary at the corner
     for (int it = 0; it < iters; ++it) {
         const T rh = P.fh - mh, rl = P.fl - ml;
         const T Gc = wh * rh * P.ghc + wl * rl * P.glc + rc * (P.ac - vc);
@@ -224,31 +261,32 @@ __device__ inline void lm_solve(const T* __restrict__ spec, int kmax, int kh, in
         if constexpr (CONSTR) {
             fix_c = P.ac == T(0) && Gc > T(0);
             fix_p = P.ap == T(0) && Gp > T(0);
-            if (fix_c && fix_p) break;  // stationary at the corner
+            stop = stop || (fix_c && fix_p);
         }
-        T dc, dp;
+        T dc = T(0), dp = T(0);
+        bool bad;  // singular or non-finite damped system: no step, mu grows
         if (fix_c || fix_p) {
             const T d1 = fix_c ? Dpp : Dcc;
-            if (!(d1 > T(0)) || !(d1 < INFINITY)) {
-                mu *= T(10);
-                continue;
+            bad = !(d1 > T(0)) || !(d1 < INFINITY);
+            if (!bad) {
+                dc = fix_c ? T(0) : -Gc / d1;
+                dp = fix_p ? T(0) : -Gp / d1;
             }
-            dc = fix_c ? T(0) : -Gc / d1;
-            dp = fix_p ? T(0) : -Gp / d1;
         } else {
             // det(H + mu diag H) as a sum of nonnegative terms (no cancellation):
             // w_h w_l (g_h x g_l)^2 + rc App + rp Acc + rc rp + mu (2 + mu) Hcc Hpp.
             const T cr = det2<T>(P.ghc, P.glp, P.ghp, P.glc);
             const T det = wh * wl * cr * cr + rc * App + rp * Acc + rc * rp +
                           mu * (T(2) + mu) * Hcc * Hpp;
-            if (!(det > T(0)) || !(det < INFINITY)) {
-                mu *= T(10);
-                continue;
+            bad = !(det > T(0)) || !(det < INFINITY);
+            if (!bad) {
+                const T id = T(1) / det;
+                dc = -(Dpp * Gc - Hcp * Gp) * id;
+                dp = -(Dcc * Gp - Hcp * Gc) * id;
             }
-            const T id = T(1) / det;
-            dc = -(Dpp * Gc - Hcp * Gp) * id;
-            dp = -(Dcc * Gp - Hcp * Gc) * id;
         }
+        const bool skip = stop || bad;  // no trial point in this iteration
+        if (!stop && bad) mu *= T(10);
         Point<T> Q;
         Q.ac = P.ac + dc;
         Q.ap = P.ap + dp;
@@ -258,9 +296,6 @@ __device__ inline void lm_solve(const T* __restrict__ spec, int kmax, int kh, in
             dc = Q.ac - P.ac;
             dp = Q.ap - P.ap;
         }
-        const T bound = (T)sb.kcmax * fabs(dc) + (T)sb.kpmax * fabs(dp);
-        // A non-finite current value gives no usable shift either.
-        const bool finite = isfinite(P.fh) && isfinite(P.fl);
         const T sh = -P.fh * log2e, sl = -P.fl * log2e;
         if constexpr (JT) {
             // Each spectrum's log-sum-exp at Q lies between its first-order prediction
@@ -276,26 +311,46 @@ __device__ inline void lm_solve(const T* __restrict__ spec, int kmax, int kh, in
                              fmin(lh, ll) + T(90));
             const bool ok =
                 spectra_eval_joint<T>(jt, Q.ac, Q.ap, s, Q.fh, Q.ghc, Q.ghp, Q.fl, Q.glc, Q.glp);
-            if (!ok) {
-                const T s_h = spectrum_max<T>(spec, spec + kmax, spec + 2 * kmax, kh, Q.ac, Q.ap);
-                const T s_l = spectrum_max<T>(spec + 3 * kmax, spec + 4 * kmax, spec + 5 * kmax,
-                                              kl, Q.ac, Q.ap);
-                T u0, u1, u2;  // the other spectrum's values at each shift are not used
-                (void)spectra_eval_joint<T>(jt, Q.ac, Q.ap, s_h, Q.fh, Q.ghc, Q.ghp, u0, u1, u2);
-                (void)spectra_eval_joint<T>(jt, Q.ac, Q.ap, s_l, u0, u1, u2, Q.fl, Q.glc, Q.glp);
+            // A ray whose sums left the range is evaluated again by the whole wave, its
+            // bins spread over the lanes, so that a few such rays do not hold up the wave.
+            unsigned long long need = __ballot(!ok && !skip);
+            const int t = (int)(threadIdx.x & 63u);
+            while (need) {
+                const int j = __ffsll((long long)need) - 1;
+                need &= need - 1;
+                const T ac = __shfl(Q.ac, j, 64), ap = __shfl(Q.ap, j, 64);
+                T f0, g0, g1;
+                wave_spectrum_eval<T>(spec, spec + kmax, spec + 2 * kmax, kh, ac, ap, f0, g0,
+                                      g1);
+                if (t == j) {
+                    Q.fh = f0;
+                    Q.ghc = g0;
+                    Q.ghp = g1;
+                }
+                wave_spectrum_eval<T>(spec + 3 * kmax, spec + 4 * kmax, spec + 5 * kmax, kl, ac,
+                                      ap, f0, g0, g1);
+                if (t == j) {
+                    Q.fl = f0;
+                    Q.glc = g0;
+                    Q.glp = g1;
+                }
             }
             const T rh = Q.fh - mh, rl = Q.fl - ml, ec = Q.ac - vc, ep = Q.ap - vp;
             Q.phi = T(0.5) * (wh * rh * rh + wl * rl * rl) + T(0.5) * (rc * ec * ec + rp * ep * ep);
-        } else {
-            const bool exact = !(bound <= T(96)) || !finite;
+        } else if (!skip) {
+            const T bound = (T)sb.kcmax * fabs(dc) + (T)sb.kpmax * fabs(dp);
+            // A non-finite current value gives no usable shift either.
+            const bool exact = !(bound <= T(96)) || !(isfinite(P.fh) && isfinite(P.fl));
             evaluate<T>(spec, kmax, kh, kl, mh, ml, wh, wl, vc, vp, rc, rp, sh, sl, exact, Q);
         }
-        if (Q.phi < P.phi) {
-            P = Q;
-            mu *= T(0.1);
-            if (it < 32) accepted |= 1u << it;
-        } else {
-            mu *= T(10);
+        if (!skip) {
+            if (Q.phi < P.phi) {
+                P = Q;
+                mu *= T(0.1);
+                if (it < 32) accepted |= 1u << it;
+            } else {
+                mu *= T(10);
+            }
         }
     }
 }
@@ -319,10 +374,14 @@ __global__ __launch_bounds__(256) void k_udm(const UdmArgs<T>* __restrict__ dev,
     if ((long)blockIdx.x * blockDim.x >= A.M) return;  // beyond this slice (whole block)
     // l: internal ray index (t, da, R p, f cache); i: standard [V][D] index (m, w, a,
     // u^a, R x).
-    const long l = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long i = l < A.M ? std_ray(l, A.sym, A.Vb, A.D) : 0;
+    // With JT every lane of a wave takes part in the LM iterations (their fallback is
+    // wave-wide): lanes past the last ray repeat it and store nothing.
+    const long l0 = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = l0 < A.M;
+    const long l = live ? l0 : A.M - 1;
+    const long i = live || JT ? std_ray(l, A.sym, A.Vb, A.D) : 0;
     double part[4] = {0.0, 0.0, 0.0, 0.0};
-    if (l < A.M) {
+    if (live || JT) {
         const T mh = A.mh[i], ml = A.ml[i], wh = A.wh[i], wl = A.wl[i];
         V2* a2 = reinterpret_cast<V2*>(A.a);
         Point<T> P;
@@ -386,46 +445,48 @@ __global__ __launch_bounds__(256) void k_udm(const UdmArgs<T>* __restrict__ dev,
                              A.jkc[0], A.jkc[1], A.jkp[0], A.jkp[1]};
         lm_solve<T, MODE == 3, JT>(spec, kmax, kh, kl, jt, mh, ml, wh, wl, vc, vp, rc, rp, A.iters,
                                (T)A.mu0, sb, P, accepted);
-        if constexpr (MODE == 2) {
-            if (A.lmbits) A.lmbits[i] = (uint8_t)(accepted & 0xffu);
-        }
-        V2 an;
-        an.v[0] = P.ac;
-        an.v[1] = P.ap;
-        a2[i] = an;
-        if constexpr (MODE == 1 || MODE == 2) {
-            V4 c0;
-            V2 c1;
-            c0.v[0] = P.fh;
-            c0.v[1] = P.fl;
-            c0.v[2] = P.ghc;
-            c0.v[3] = P.ghp;
-            c1.v[0] = P.glc;
-            c1.v[1] = P.glp;
-            reinterpret_cast<V4*>(A.fg)[2 * l] = c0;
-            reinterpret_cast<V2*>(A.fg)[4 * l + 2] = c1;
-        }
-        if constexpr (MODE == 0 || MODE == 3) {
-            if (A.cost) A.cost[i] = P.phi;
-        } else if constexpr (MODE == 1) {
-            reinterpret_cast<V2*>(A.t)[l] = an;  // u^a = R x = 0
-        } else {
-            V2 un, tn, dn;
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                un.v[c] = ua.v[c] + an.v[c] - rx.v[c];        // Eq. (11), a-block
-                tn.v[c] = an.v[c] + un.v[c] - rx.v[c];        // next R^T right-hand side
-                dn.v[c] = an.v[c] - a_prev.v[c];
-                part[c] = (double)(an.v[c] - rx.v[c]) * (double)(an.v[c] - rx.v[c]);
+        if (live) {
+            if constexpr (MODE == 2) {
+                if (A.lmbits) A.lmbits[i] = (uint8_t)(accepted & 0xffu);
             }
-            reinterpret_cast<V2*>(A.ua)[i] = un;
-            reinterpret_cast<V2*>(A.Rx)[i] = rx;
-            if (A.t) reinterpret_cast<V2*>(A.t)[l] = tn;
-            reinterpret_cast<V2*>(A.da)[l] = dn;
-            const T rh = P.fh - mh, rl = P.fl - ml;
-            part[2] = 0.5 * ((double)wh * (double)rh * (double)rh + (double)wl * (double)rl * (double)rl);
-            const bool finite = isfinite(P.ac) && isfinite(P.ap) && isfinite(part[2]);
-            part[3] = finite ? 0.0 : 1.0;
+            V2 an;
+            an.v[0] = P.ac;
+            an.v[1] = P.ap;
+            a2[i] = an;
+            if constexpr (MODE == 1 || MODE == 2) {
+                V4 c0;
+                V2 c1;
+                c0.v[0] = P.fh;
+                c0.v[1] = P.fl;
+                c0.v[2] = P.ghc;
+                c0.v[3] = P.ghp;
+                c1.v[0] = P.glc;
+                c1.v[1] = P.glp;
+                reinterpret_cast<V4*>(A.fg)[2 * l] = c0;
+                reinterpret_cast<V2*>(A.fg)[4 * l + 2] = c1;
+            }
+            if constexpr (MODE == 0 || MODE == 3) {
+                if (A.cost) A.cost[i] = P.phi;
+            } else if constexpr (MODE == 1) {
+                reinterpret_cast<V2*>(A.t)[l] = an;  // u^a = R x = 0
+            } else {
+                V2 un, tn, dn;
+    #pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    un.v[c] = ua.v[c] + an.v[c] - rx.v[c];        // Eq. (11), a-block
+                    tn.v[c] = an.v[c] + un.v[c] - rx.v[c];        // next R^T right-hand side
+                    dn.v[c] = an.v[c] - a_prev.v[c];
+                    part[c] = (double)(an.v[c] - rx.v[c]) * (double)(an.v[c] - rx.v[c]);
+                }
+                reinterpret_cast<V2*>(A.ua)[i] = un;
+                reinterpret_cast<V2*>(A.Rx)[i] = rx;
+                if (A.t) reinterpret_cast<V2*>(A.t)[l] = tn;
+                reinterpret_cast<V2*>(A.da)[l] = dn;
+                const T rh = P.fh - mh, rl = P.fl - ml;
+                part[2] = 0.5 * ((double)wh * (double)rh * (double)rh + (double)wl * (double)rl * (double)rl);
+                const bool finite = isfinite(P.ac) && isfinite(P.ap) && isfinite(part[2]);
+                part[3] = finite ? 0.0 : 1.0;
+            }
         }
     }
     if constexpr (MODE == 2) block_sum_store<4>(part, A.partials + (size_t)blockIdx.x * kPartialSlots);
@@ -505,8 +566,6 @@ hipError_t launch_udm(const dect_plan* p, int mode, const UdmArgs<T>& a0, hipStr
     const long tvb = mode == 2 && a.tv.x ? ((long)a.tv.nx * a.tv.ny + 255) / 256 : 0;
     dim3 g((unsigned)(a.udm_blocks + tvb));
     ProfScope ps(mode == 1 ? "udm_init" : (mode == 3 ? "cdm" : "udm"), s);
-    // The ADMM a-update (mode 2) evaluates the spectra apart: its rays that leave the
-    // joint evaluation's range are few but spread over enough waves to hold up the launch.
     const bool jt = a.joint_lim > 0.0f;
     if (mode == 0 && jt)
         hipLaunchKernelGGL((k_udm<T, 0, false, true>), g, dim3(256), 0, s, nullptr, a);
@@ -520,16 +579,23 @@ hipError_t launch_udm(const dect_plan* p, int mode, const UdmArgs<T>& a0, hipStr
         hipLaunchKernelGGL((k_udm<T, 1, false, true>), g, dim3(256), 0, s, nullptr, a);
     else if (mode == 1)
         hipLaunchKernelGGL((k_udm<T, 1, false, false>), g, dim3(256), 0, s, nullptr, a);
+    else if (jt)
+        hipLaunchKernelGGL((k_udm<T, 2, false, true>), g, dim3(256), 0, s, nullptr, a);
     else
         hipLaunchKernelGGL((k_udm<T, 2, false, false>), g, dim3(256), 0, s, nullptr, a);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_udm_batch(const UdmArgs<T>* args, int n, int blocks, hipStream_t s) {
+hipError_t launch_udm_batch(const UdmArgs<T>* args, int n, int blocks, bool joint,
+                            hipStream_t s) {
     ProfScope ps("udm", s);
-    hipLaunchKernelGGL((k_udm<T, 2, true, false>), dim3(blocks, 1, n), dim3(256), 0, s, args,
-                       UdmArgs<T>{});
+    if (joint)
+        hipLaunchKernelGGL((k_udm<T, 2, true, true>), dim3(blocks, 1, n), dim3(256), 0, s, args,
+                           UdmArgs<T>{});
+    else
+        hipLaunchKernelGGL((k_udm<T, 2, true, false>), dim3(blocks, 1, n), dim3(256), 0, s, args,
+                           UdmArgs<T>{});
     return hipGetLastError();
 }
 
@@ -564,8 +630,8 @@ template hipError_t launch_lm_eval<float>(const dect_plan*, int, const float*, c
 template hipError_t launch_lm_eval<double>(const dect_plan*, int, const double*, const double*,
                                            const double*, const double*, const double*,
                                            const double*, double*, double*, hipStream_t);
-template hipError_t launch_udm_batch<float>(const UdmArgs<float>*, int, int, hipStream_t);
-template hipError_t launch_udm_batch<double>(const UdmArgs<double>*, int, int, hipStream_t);
+template hipError_t launch_udm_batch<float>(const UdmArgs<float>*, int, int, bool, hipStream_t);
+template hipError_t launch_udm_batch<double>(const UdmArgs<double>*, int, int, bool, hipStream_t);
 template hipError_t launch_ingest<float>(const dect_plan*, const void*, const void*, double, double,
                                          void*, void*, void*, void*, hipStream_t);
 template hipError_t launch_ingest<double>(const dect_plan*, const void*, const void*, double,
