@@ -288,6 +288,27 @@ def test_admm_fp64_tiny_matches_oracle(dect):
     _check_objective_log(log, ost.log)
 
 
+def test_admm_fp64_without_joint_table_matches_oracle(dect):
+    """The ADMM on a plan whose spectra are evaluated apart (a bin weighted below 2^-24 of
+    its spectrum), as every decomposition kernel has both forms."""
+    import types
+    pr = S.tiny_problem(0)
+    s_high = pr.spec.s_high.copy()
+    s_high[int(np.flatnonzero(s_high > 0)[-1])] = 1e-40 * s_high.sum()
+    spec = S.Spectra(pr.spec.energy_kev, s_high, pr.spec.s_low, pr.spec.f_kn, pr.spec.f_p)
+    assert not _has_joint_table(spec)
+    pr2 = types.SimpleNamespace(geom=pr.geom, spec=spec, counts_high=pr.counts_high,
+                                counts_low=pr.counts_low, i0=pr.i0)
+    prm = O.Params(cg_iters=2, lm_iters=2)
+    ost = _admm_oracle(pr2, prm, 8)
+    _, st, log = _admm_gpu(dect, pr2, F64, dect.AdmmParams(cg_iters=2, lm_iters=2), 8)
+    x = host(st.x)
+    for b in range(2):
+        assert rel(x[..., b], ost.x[b]) <= 1e-8
+    assert [e["rho"] for e in log] == [tuple(e["rho"]) for e in ost.log]
+    _check_objective_log(log, ost.log)
+
+
 def _check_objective_log(log, olog, rtol_data=1e-9, rtol_tv=1e-8):
     """The logged split objective (the serving stop criterion) against the oracle's:
     the data fit 1/2 sum w (f(a) - m)^2 at the new a and lambda |y|_1 at the new y,
