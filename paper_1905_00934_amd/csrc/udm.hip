@@ -5,8 +5,10 @@
 // so they come from scalar loads and every lane runs the same bin loop; the
 // only divergence is the per-ray accept/reject of the LM step.  The polychromatic
 // transform f_s(a) = -ln sum_k omega_k exp(-f_KN[k] a_c - f_p[k] a_p) (Eq. (3))
-// is a log-sum-exp evaluated in base 2 with the largest exponent factored out,
-// which keeps metal rays (exponents below -700) finite in single precision.
+// is a log-sum-exp evaluated in base 2 with a shift factored out, which keeps metal
+// rays (exponents below -700) finite in single precision.  Where the plan has a
+// joint table both spectra come from one exponential per bin; a ray whose shift
+// left the range is evaluated again exactly by its whole wave.
 #include <cmath>
 
 #include "common.h"
